@@ -1,0 +1,223 @@
+/*
+ * pss.h - C ABI of the MI355X (gfx950) parallel square-root iterated smoother.
+ *
+ * Method: Yaghoobi, Corenflos, Hassan, Sarkka, "Parallel square-root
+ * statistical linear regression for inference in nonlinear state space
+ * models".  The library computes, on one GPU and for a batch of independent
+ * sequences,
+ *   - the cubature statistical linear regression of the model around a
+ *     nominal trajectory (Section 4.3),
+ *   - the square-root parallel Kalman filter elements (Lemma 1, Tables 1-2)
+ *     and their associative scan (Lemma 2, Table 3, Algorithm 1),
+ *   - the square-root parallel RTS smoother (Lemmas 3-4, Tables 4-5,
+ *     Algorithm 2, a reverse associative scan),
+ *   - the iterated posterior linearisation loop (Algorithm 3),
+ *   - the pseudo-log-likelihood (Section 5.1, eq. log-likelihood) and its
+ *     gradient with respect to the model parameters at a frozen nominal
+ *     trajectory (Section 5.2, eq. gradient).
+ *
+ * Conventions shared by every entry point
+ *   - Every buffer pointer is a DEVICE pointer unless its name ends in
+ *     "_host".  The caller allocates and owns every buffer; the library never
+ *     allocates device memory and keeps no device state between calls.
+ *   - Every call is asynchronous on the caller's HIP stream `stream` and
+ *     returns PSS_OK or a negative status.  Arguments are validated on the
+ *     host before anything is enqueued; a failed validation enqueues nothing.
+ *     Numerical breakdown (a NaN) is not a status: it propagates into the
+ *     outputs.
+ *   - Floating-point buffers hold `dtype` elements (float or double).
+ *   - A batch holds B sequences.  Sequence b has n_b = y_off[b+1]-y_off[b] >= 1
+ *     measurements y_1..y_n and n_b + 1 states x_0..x_n.  Measurements and
+ *     step quantities are indexed by the global STEP SLOT y_off[b] + (k-1)
+ *     for step k = 1..n_b (T_y = y_off[B] slots).  State quantities are indexed
+ *     by the global STATE SLOT y_off[b] + b + k, k = 0..n_b (T_x = T_y + B).
+ *   - Every array is structure-of-arrays, component-major: component c of
+ *     slot t is at [c * count + t] where count is T_y or T_x.  Square matrices
+ *     are row-major (component i*n + j); lower-triangular factors are packed
+ *     row-major (component i*(i+1)/2 + j, j <= i).
+ *   - Step slot j of a linearisation holds the transition x_{k-1} -> x_k
+ *     (F_{k-1}, c_{k-1}, S_Lambda_{k-1}) together with the measurement model of
+ *     y_k (H_k, d_k, S_Omega_k), for the step k it feeds (eq. linear-params).
+ *   - Covariances are carried only as lower Cholesky factors with a
+ *     non-negative diagonal (the Tria operator of Section 2.2).
+ */
+#ifndef PSS_H
+#define PSS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define PSS_OK 0
+#define PSS_EINVAL (-1)       /* null pointer, bad size, bad offsets, ... */
+#define PSS_EUNSUPPORTED (-2) /* dtype / model / dimension not built       */
+#define PSS_EWORKSPACE (-3)   /* workspace smaller than pss_workspace_size */
+#define PSS_EHIP (-4)         /* HIP launch or runtime error               */
+
+/* ---- enums -------------------------------------------------------------- */
+typedef enum { PSS_F32 = 0, PSS_F64 = 1 } pss_dtype;
+
+typedef enum {
+    /* affine Gaussian model of eq. linear-model; the caller supplies its
+       square-root parameters as a pss_gamma (possibly shared by all steps) */
+    PSS_MODEL_LINEAR = 0,
+    /* coordinated-turn target with two bearings-only sensors (Section 6.2):
+       x = (px, py, vx, vy, w), nx = 5, ny = 2, additive noise with
+       Q(theta) = q1 Qv + q2 Qw (integrated white-noise acceleration) and
+       R(theta) = sigma^2 I, theta = (log q1, log q2, log sigma). */
+    PSS_MODEL_CT_BEARINGS = 1
+} pss_model_kind;
+
+/* operations for pss_workspace_size */
+typedef enum {
+    PSS_OP_SLR = 0,
+    PSS_OP_FILTER_ELEMENTS = 1,
+    PSS_OP_FILTER_SCAN = 2,
+    PSS_OP_SMOOTHER_SCAN = 3,
+    PSS_OP_IPLS = 4,
+    PSS_OP_LOGLIK = 5,
+    PSS_OP_LOGLIK_GRAD = 6,
+    PSS_OP_SEQUENTIAL = 7
+} pss_op;
+
+/* ---- problem description (host struct, read during the call only) ----- */
+typedef struct pss_problem {
+    int32_t model;              /* pss_model_kind                              */
+    int32_t dtype;              /* pss_dtype                                   */
+    int32_t nx, ny;             /* state / measurement dimension               */
+    int32_t B;                  /* number of sequences, >= 1                   */
+    const int64_t *y_off;       /* device [B+1], y_off[0] = 0, strictly rising */
+    const int64_t *y_off_host;  /* host copy of y_off (launch planning)        */
+    const void *m0;             /* device [nx] prior mean, shared by sequences */
+    const void *N0;             /* device [nx(nx+1)/2] packed prior factor     */
+    /* coordinated-turn constants (ignored by PSS_MODEL_LINEAR) */
+    double dt;
+    double theta[3];            /* log q1, log q2, log sigma                   */
+    double sensors[4];          /* s1x, s1y, s2x, s2y                          */
+    /* launch shape overrides (0 = library default / autotuned):
+       block threads per scan tile (64, 128 or 256) and elements folded
+       sequentially per thread (>= 1) at the finest scan level */
+    int32_t scan_threads;
+    int32_t scan_elems;
+} pss_problem;
+
+/* Square-root linearisation parameters Gamma^sqrt (eq. Gamma-s), SoA over
+   step slots.  stride = 1: one set per step slot (arrays of T_y slots);
+   stride = 0: a single set shared by every step (arrays of 1 slot).
+     F  [nx*nx]  c [nx]  SL [nx(nx+1)/2]   transition, row-major / packed
+     H  [ny*nx]  d [ny]  SO [ny(ny+1)/2]   measurement                    */
+typedef struct pss_gamma {
+    void *F, *c, *SL, *H, *d, *SO;
+    int64_t stride;
+} pss_gamma;
+
+/* Square-root filter elements Pi^f_k = {A, b, U, eta, Z} (eq. pi-f), SoA over
+   step slots: A [nx*nx], b [nx], U [nx(nx+1)/2], eta [nx], Z [nx(nx+1)/2].
+   Z is stored as the packed lower factor Tria(Z_k) (same J_k = Z Z^T; this is
+   the squaring rule stated in the proof of Lemma 1). */
+typedef struct pss_felem {
+    void *A, *b, *U, *eta, *Z;
+} pss_felem;
+
+/* ---- entry points --------------------------------------------------------- */
+
+/* Bytes of workspace `op` needs for this problem (0 if none). Returns 0 and
+   sets the last error for an invalid problem. */
+size_t pss_workspace_size(const pss_problem *p, int32_t op);
+
+/* Cubature statistical linear regression (Sections 4.1 and 4.3) of the
+   model around the nominal marginals (m_nom [nx][T_x], N_nom packed [T_x]):
+   third-degree spherical-radial rule with 2 nx points m +/- sqrt(nx) N e_i.
+   Transition parameters of slot (b, k) come from the marginal at state k-1,
+   measurement parameters from the marginal at state k.  Bearings are taken
+   on the branch nearest to the measurement y (y [ny][T_y]).  Writes `out`
+   (stride must be 1).  PSS_MODEL_CT_BEARINGS only. */
+int pss_slr_linearize(const pss_problem *p, const void *m_nom, const void *N_nom,
+                      const void *y, const pss_gamma *out, hipStream_t stream);
+
+/* Square-root filter elements of Lemma 1 (Table 1 for k = 1, Table 2 for
+   k > 1) for every step of every sequence, from the linearisation `g`
+   (stride 0 or 1) and the measurements y [ny][T_y].  Writes `out`. */
+int pss_sqrt_filter_elements(const pss_problem *p, const pss_gamma *g, const void *y,
+                             const pss_felem *out, hipStream_t stream);
+
+/* Algorithm 1: inclusive associative scan of the filter elements with the
+   square-root operator of Lemma 2 (Table 3), per sequence.  Writes the
+   filtering marginals m_f [nx][T_x] and packed N_f [T_x] (state 0 receives
+   the prior).  `el` is read only.  ws: pss_workspace_size(PSS_OP_FILTER_SCAN). */
+int pss_sqrt_filter_scan(const pss_problem *p, const pss_felem *el, void *m_f, void *N_f,
+                         void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Algorithm 2: smoother elements of Lemma 3 (Table 4; the last state of each
+   sequence takes E = 0, g = m^f_n, D = N^f_n) built from the transition part
+   of `g` and the filtering marginals, then the reverse associative scan with
+   the operator of Lemma 4 (Table 5).  Writes m_s [nx][T_x], packed N_s.
+   ws: pss_workspace_size(PSS_OP_SMOOTHER_SCAN). */
+int pss_sqrt_smoother_scan(const pss_problem *p, const pss_gamma *g, const void *m_f,
+                           const void *N_f, void *m_s, void *N_s, void *ws, size_t ws_bytes,
+                           hipStream_t stream);
+
+/* Algorithm 3: n_iter passes of (SLR at the nominal, filter elements,
+   filter scan, smoother scan).  m_nom / N_nom hold the initial nominal on
+   entry and the final smoothing marginals on exit.  m_f / N_f (nullable)
+   receive the last pass's filtering marginals.  For PSS_MODEL_LINEAR the
+   linearisation `g` is used as is on every pass (the SLR of an affine model
+   is the model itself); for PSS_MODEL_CT_BEARINGS `g` must be NULL.
+   ws: pss_workspace_size(PSS_OP_IPLS). */
+int pss_ipls_iterate(const pss_problem *p, const pss_gamma *g, const void *y, int32_t n_iter,
+                     void *m_nom, void *N_nom, void *m_f, void *N_f, void *ws, size_t ws_bytes,
+                     hipStream_t stream);
+
+/* Pseudo-log-likelihood of Section 5.1: the model is linearised at the
+   nominal (CT; for LINEAR `g` is used), filtered with Algorithm 1, and
+   ll[b] = sum_k log N(y_k; H_k m^-_k + d_k, Y_k Y_k^T) with the predicted
+   factor Y_k = Tria([H_k Tria([F_{k-1} N^f_{k-1}, S_Lambda]), S_Omega]).
+   ll: device double [B] (FP64 accumulation for both dtypes).
+   ws: pss_workspace_size(PSS_OP_LOGLIK). */
+int pss_loglik(const pss_problem *p, const pss_gamma *g, const void *m_nom, const void *N_nom,
+               const void *y, double *ll, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Gradient of the pseudo-log-likelihood with respect to theta = (log q1,
+   log q2, log sigma) at a FROZEN nominal (the partial derivative term of
+   eq. gradient; PSS_MODEL_CT_BEARINGS only).  With the nominal fixed, theta
+   enters only through S_Lambda and S_Omega.  The sensitivities dl/dLambda_k
+   and dl/dOmega_k are the posterior expectations of the complete-data score
+   (Fisher's identity), computed from the parallel square-root smoother of
+   the linearised model; they are contracted with dQ/dtheta and dR/dtheta.
+   Outputs (device double): ll [B]; grad [3][B] per sequence, component-major
+   (nullable); theta_bar [3] = sum_b ll_bar[b] grad[.][b] (nullable; ll_bar
+   nullable means all ones).  ws: pss_workspace_size(PSS_OP_LOGLIK_GRAD). */
+int pss_loglik_grad(const pss_problem *p, const void *m_nom, const void *N_nom, const void *y,
+                    const double *ll_bar, double *ll, double *grad, double *theta_bar, void *ws,
+                    size_t ws_bytes, hipStream_t stream);
+
+/* Sequential square-root comparator: the same n_iter passes as
+   pss_ipls_iterate, but the filter and smoother run as the sequential
+   recursions (one thread per sequence walks k = 1..n then n-1..0); only the
+   SLR is parallel.  Same arguments and outputs as pss_ipls_iterate.
+   ws: pss_workspace_size(PSS_OP_SEQUENTIAL). */
+int pss_sequential_smoother(const pss_problem *p, const pss_gamma *g, const void *y,
+                            int32_t n_iter, void *m_nom, void *N_nom, void *m_f, void *N_f,
+                            void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Validation only: returns the status the entry points would return for
+   this problem before enqueuing work (no HIP call is made). */
+int pss_validate(const pss_problem *p);
+
+/* Message of the last error raised on the calling thread ("" if none). */
+const char *pss_last_error(void);
+
+/* Library version string. */
+const char *pss_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSS_H */

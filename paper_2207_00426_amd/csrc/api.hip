@@ -1,0 +1,539 @@
+// C ABI of the parallel square-root smoother: validation, dispatch on
+// (dtype, nx, ny), scan planning and the few non-template kernels.
+#include <math.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace pss {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+int hip_check(hipError_t e, const char *what)
+{
+    if (e == hipSuccess)
+        return PSS_OK;
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return PSS_EHIP;
+}
+
+// ---------------------------------------------------------------------------
+// scan planning (host side mirrors k_plan exactly)
+// ---------------------------------------------------------------------------
+ScanShape plan_scan(const Ctx &c, int extra, int T0, int E0, int Tup, int Eup)
+{
+    ScanShape sh;
+    std::vector<int64_t> cnt(c.B);
+    int64_t total = 0;
+    for (int b = 0; b < c.B; ++b) {
+        cnt[b] = c.p->y_off_host[b + 1] - c.p->y_off_host[b] + extra;
+        total += cnt[b];
+    }
+    sh.nelem[0] = total;
+    for (int l = 0; l < kMaxLevels; ++l) {
+        sh.T[l] = l == 0 ? T0 : Tup;
+        sh.E[l] = l == 0 ? E0 : Eup;
+        const int64_t TS = (int64_t)sh.T[l] * sh.E[l];
+        int64_t nt = 0, mx = 0;
+        for (int b = 0; b < c.B; ++b) {
+            mx = std::max(mx, cnt[b]);
+            cnt[b] = (cnt[b] + TS - 1) / TS;
+            nt += cnt[b];
+        }
+        sh.ntiles[l] = nt;
+        if (mx <= TS) {
+            sh.L = l + 1;
+            break;
+        }
+        if (l + 1 < kMaxLevels)
+            sh.nelem[l + 1] = nt;
+    }
+    return sh;
+}
+
+__global__ __launch_bounds__(1024) void k_plan(PlanArgs a)
+{
+    __shared__ int64_t sh[1024];
+    __shared__ int64_t carry;
+    for (int l = 0; l < a.L; ++l) {
+        if (threadIdx.x == 0) {
+            carry = 0;
+            a.tile_off[l][0] = 0;
+        }
+        for (int base = 0; base < a.B; base += 1024) {
+            const int b = base + threadIdx.x;
+            int64_t t = 0;
+            if (b < a.B) {
+                int64_t cn = a.y_off[b + 1] - a.y_off[b] + a.extra;
+                for (int q = 0; q <= l; ++q)
+                    cn = (cn + a.TS[q] - 1) / a.TS[q];
+                t = cn;
+            }
+            __syncthreads();
+            sh[threadIdx.x] = t;
+            for (int d = 1; d < 1024; d <<= 1) {
+                __syncthreads();
+                const int64_t v = (int)threadIdx.x >= d ? sh[threadIdx.x - d] : 0;
+                __syncthreads();
+                sh[threadIdx.x] += v;
+            }
+            __syncthreads();
+            if (b < a.B)
+                a.tile_off[l][b + 1] = carry + sh[threadIdx.x];
+            __syncthreads();
+            if (threadIdx.x == 0)
+                carry += sh[1023];
+            __syncthreads();
+        }
+    }
+}
+
+int launch_plan(const Ctx &c, const ScanShape &sh, int extra, int64_t *const *tile_off)
+{
+    PlanArgs a;
+    a.y_off = c.p->y_off;
+    a.B = c.B;
+    a.extra = extra;
+    a.L = sh.L;
+    for (int l = 0; l < kMaxLevels; ++l) {
+        a.TS[l] = l < sh.L ? (int64_t)sh.T[l] * sh.E[l] : 1;
+        a.tile_off[l] = l < sh.L ? tile_off[l] : nullptr;
+    }
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, c.s, a);
+    return hip_check(hipGetLastError(), "plan launch");
+}
+
+int launch_seq_sum(const Ctx &c, int nc, const double *terms, int64_t ld, double *out)
+{
+    if (nc == 1)
+        hipLaunchKernelGGL(k_seq_sum<1>, dim3(c.B), dim3(256), 0, c.s, c.p->y_off, terms, ld, out);
+    else
+        hipLaunchKernelGGL(k_seq_sum<3>, dim3(c.B), dim3(256), 0, c.s, c.p->y_off, terms, ld, out);
+    return hip_check(hipGetLastError(), "sequence sum launch");
+}
+
+__global__ __launch_bounds__(256) void k_weighted_grad(const double *grad, const double *w, int B,
+                                                       double *theta_bar)
+{
+    if (threadIdx.x < 3) {
+        double s = 0.0;
+        for (int b = 0; b < B; ++b)
+            s += (w ? w[b] : 1.0) * grad[(int64_t)threadIdx.x * B + b];
+        theta_bar[threadIdx.x] = s;
+    }
+}
+
+int launch_weighted_grad(const Ctx &c, const double *grad, const double *w, double *theta_bar)
+{
+    hipLaunchKernelGGL(k_weighted_grad, dim3(1), dim3(64), 0, c.s, grad, w, c.B, theta_bar);
+    return hip_check(hipGetLastError(), "weighted gradient launch");
+}
+
+// ---------------------------------------------------------------------------
+// coordinated-turn constants: Q(theta) = q1 Qv + q2 Qw (integrated white-noise
+// acceleration on each axis, random-walk turn rate); its lower factor splits
+// into the q1 part L1 (per axis [[a, 0], [b, c]] on (p, v)) and the q2 part L2.
+// ---------------------------------------------------------------------------
+CTHost ct_host(const pss_problem *p)
+{
+    CTHost h{};
+    h.dt = p->dt;
+    h.q1 = exp(p->theta[0]);
+    h.q2 = exp(p->theta[1]);
+    h.sigma = exp(p->theta[2]);
+    h.s1x = p->sensors[0];
+    h.s1y = p->sensors[1];
+    h.s2x = p->sensors[2];
+    h.s2y = p->sensors[3];
+    const double dt = h.dt;
+    const double a = sqrt(h.q1 * dt * dt * dt / 3.0);
+    const double b = (h.q1 * dt * dt / 2.0) / a;
+    const double cc = 0.5 * sqrt(h.q1 * dt);
+    for (int i = 0; i < 5; ++i)
+        for (int j = 0; j < 5; ++j)
+            h.L1[i][j] = h.L2[i][j] = 0.0;
+    h.L1[0][0] = h.L1[1][1] = a;
+    h.L1[2][0] = h.L1[3][1] = b;
+    h.L1[2][2] = h.L1[3][3] = cc;
+    h.L2[4][4] = sqrt(h.q2 * dt);
+    for (int i = 0; i < 5; ++i)
+        for (int j = 0; j < 5; ++j)
+            h.LQ[i][j] = h.L1[i][j] + h.L2[i][j];
+    return h;
+}
+
+// ---------------------------------------------------------------------------
+// dispatch
+// ---------------------------------------------------------------------------
+template <typename T, int NX, int NY>
+struct Tag {
+    using I = Impl<T, NX, NY>;
+};
+
+template <typename T, class Fn>
+static int dispatch_dims(const pss_problem *p, Fn &&fn)
+{
+#define PSS_CASE(a, b)                                                                           \
+    if (p->nx == a && p->ny == b)                                                                \
+        return fn(Tag<T, a, b>{});
+    PSS_DIMS(PSS_CASE)
+#undef PSS_CASE
+    set_error("dimension pair (nx, ny) not built");
+    return PSS_EUNSUPPORTED;
+}
+
+template <class Fn>
+static int dispatch(const pss_problem *p, Fn &&fn)
+{
+    if (p->dtype == PSS_F64)
+        return dispatch_dims<double>(p, fn);
+    return dispatch_dims<float>(p, fn);
+}
+
+static bool dims_built(int nx, int ny)
+{
+#define PSS_CHK(a, b)                                                                            \
+    if (nx == a && ny == b)                                                                      \
+        return true;
+    PSS_DIMS(PSS_CHK)
+#undef PSS_CHK
+    return false;
+}
+
+static int validate(const pss_problem *p)
+{
+    if (!p) {
+        set_error("null problem");
+        return PSS_EINVAL;
+    }
+    if (p->model != PSS_MODEL_LINEAR && p->model != PSS_MODEL_CT_BEARINGS) {
+        set_error("unknown model");
+        return PSS_EINVAL;
+    }
+    if (p->dtype != PSS_F32 && p->dtype != PSS_F64) {
+        set_error("unknown dtype");
+        return PSS_EINVAL;
+    }
+    if (p->nx < 1 || p->ny < 1 || p->nx > 8 || p->ny > 8) {
+        set_error("nx and ny must be in 1..8");
+        return PSS_EINVAL;
+    }
+    if (p->model == PSS_MODEL_CT_BEARINGS && (p->nx != 5 || p->ny != 2)) {
+        set_error("the coordinated-turn model has nx = 5, ny = 2");
+        return PSS_EINVAL;
+    }
+    if (!dims_built(p->nx, p->ny)) {
+        set_error("dimension pair (nx, ny) not built");
+        return PSS_EUNSUPPORTED;
+    }
+    if (p->B < 1) {
+        set_error("B must be >= 1");
+        return PSS_EINVAL;
+    }
+    if (!p->y_off || !p->y_off_host || !p->m0 || !p->N0) {
+        set_error("null y_off, y_off_host, m0 or N0");
+        return PSS_EINVAL;
+    }
+    if (p->y_off_host[0] != 0) {
+        set_error("y_off[0] must be 0");
+        return PSS_EINVAL;
+    }
+    for (int b = 0; b < p->B; ++b)
+        if (p->y_off_host[b + 1] <= p->y_off_host[b]) {
+            set_error("every sequence needs at least one measurement (y_off strictly rising)");
+            return PSS_EINVAL;
+        }
+    if (p->scan_threads != 0 && p->scan_threads != 64 && p->scan_threads != 128 &&
+        p->scan_threads != 256) {
+        set_error("scan_threads must be 0, 64, 128 or 256");
+        return PSS_EINVAL;
+    }
+    if (p->scan_elems < 0 || p->scan_elems > 256) {
+        set_error("scan_elems must be in 0..256");
+        return PSS_EINVAL;
+    }
+    if (p->model == PSS_MODEL_CT_BEARINGS) {
+        if (!(p->dt > 0.0) || !isfinite(p->theta[0]) || !isfinite(p->theta[1]) ||
+            !isfinite(p->theta[2])) {
+            set_error("coordinated-turn model needs dt > 0 and a finite theta");
+            return PSS_EINVAL;
+        }
+    }
+    return PSS_OK;
+}
+
+static Ctx make_ctx(const pss_problem *p, hipStream_t s)
+{
+    Ctx c;
+    c.p = p;
+    c.B = p->B;
+    c.T_y = p->y_off_host[p->B];
+    c.T_x = c.T_y + p->B;
+    c.s = s;
+    return c;
+}
+
+static bool gamma_ok(const pss_gamma *g)
+{
+    return g && g->F && g->c && g->SL && g->H && g->d && g->SO &&
+           (g->stride == 0 || g->stride == 1);
+}
+
+static int check_ws(const Ctx &c, int op, const void *ws, size_t ws_bytes)
+{
+    size_t need = 0;
+    dispatch(c.p, [&](auto tag) {
+        using I = typename decltype(tag)::I;
+        need = I::ws_size(c, op);
+        return 0;
+    });
+    if (ws_bytes < need || (need > 0 && !ws)) {
+        set_error("workspace too small: need " + std::to_string(need) + " bytes");
+        return PSS_EWORKSPACE;
+    }
+    return PSS_OK;
+}
+
+} // namespace pss
+
+using namespace pss;
+
+#define PSS_GUARD(expr)                                                                          \
+    do {                                                                                         \
+        try {                                                                                    \
+            return (expr);                                                                       \
+        } catch (const std::exception &ex) {                                                     \
+            set_error(ex.what());                                                                \
+            return PSS_EINVAL;                                                                   \
+        } catch (...) {                                                                          \
+            set_error("unknown exception");                                                      \
+            return PSS_EINVAL;                                                                   \
+        }                                                                                        \
+    } while (0)
+
+extern "C" {
+
+const char *pss_last_error(void) { return g_last_error.c_str(); }
+
+const char *pss_version(void) { return "pss 0.1 (gfx950)"; }
+
+int pss_validate(const pss_problem *p)
+{
+    PSS_GUARD(validate(p));
+}
+
+size_t pss_workspace_size(const pss_problem *p, int32_t op)
+{
+    try {
+        if (validate(p) != PSS_OK)
+            return 0;
+        const Ctx c = make_ctx(p, nullptr);
+        size_t n = 0;
+        dispatch(p, [&](auto tag) {
+            using I = typename decltype(tag)::I;
+            n = I::ws_size(c, op);
+            return 0;
+        });
+        return n;
+    } catch (...) {
+        set_error("exception in pss_workspace_size");
+        return 0;
+    }
+}
+
+int pss_slr_linearize(const pss_problem *p, const void *m_nom, const void *N_nom, const void *y,
+                      const pss_gamma *out, hipStream_t stream)
+{
+    PSS_GUARD(([&]() -> int {
+        int rc = validate(p);
+        if (rc)
+            return rc;
+        if (p->model != PSS_MODEL_CT_BEARINGS) {
+            set_error("slr_linearize needs a nonlinear model");
+            return PSS_EUNSUPPORTED;
+        }
+        if (!m_nom || !N_nom || !y || !gamma_ok(out) || out->stride != 1) {
+            set_error("slr_linearize: null buffer or output stride != 1");
+            return PSS_EINVAL;
+        }
+        const Ctx c = make_ctx(p, stream);
+        return dispatch(p, [&](auto tag) {
+            using I = typename decltype(tag)::I;
+            return I::slr(c, m_nom, N_nom, y, out);
+        });
+    }()));
+}
+
+int pss_sqrt_filter_elements(const pss_problem *p, const pss_gamma *g, const void *y,
+                             const pss_felem *out, hipStream_t stream)
+{
+    PSS_GUARD(([&]() -> int {
+        int rc = validate(p);
+        if (rc)
+            return rc;
+        if (!gamma_ok(g) || !y || !out || !out->A || !out->b || !out->U || !out->eta ||
+            !out->Z) {
+            set_error("sqrt_filter_elements: null buffer");
+            return PSS_EINVAL;
+        }
+        const Ctx c = make_ctx(p, stream);
+        return dispatch(p, [&](auto tag) {
+            using I = typename decltype(tag)::I;
+            return I::felem(c, g, y, out);
+        });
+    }()));
+}
+
+int pss_sqrt_filter_scan(const pss_problem *p, const pss_felem *el, void *m_f, void *N_f,
+                         void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    PSS_GUARD(([&]() -> int {
+        int rc = validate(p);
+        if (rc)
+            return rc;
+        if (!el || !el->A || !el->b || !el->U || !el->eta || !el->Z || !m_f || !N_f) {
+            set_error("sqrt_filter_scan: null buffer");
+            return PSS_EINVAL;
+        }
+        const Ctx c = make_ctx(p, stream);
+        if ((rc = check_ws(c, PSS_OP_FILTER_SCAN, ws, ws_bytes)))
+            return rc;
+        return dispatch(p, [&](auto tag) {
+            using I = typename decltype(tag)::I;
+            return I::fscan(c, el, m_f, N_f, ws);
+        });
+    }()));
+}
+
+int pss_sqrt_smoother_scan(const pss_problem *p, const pss_gamma *g, const void *m_f,
+                           const void *N_f, void *m_s, void *N_s, void *ws, size_t ws_bytes,
+                           hipStream_t stream)
+{
+    PSS_GUARD(([&]() -> int {
+        int rc = validate(p);
+        if (rc)
+            return rc;
+        if (!gamma_ok(g) || !m_f || !N_f || !m_s || !N_s) {
+            set_error("sqrt_smoother_scan: null buffer");
+            return PSS_EINVAL;
+        }
+        const Ctx c = make_ctx(p, stream);
+        if ((rc = check_ws(c, PSS_OP_SMOOTHER_SCAN, ws, ws_bytes)))
+            return rc;
+        return dispatch(p, [&](auto tag) {
+            using I = typename decltype(tag)::I;
+            return I::sscan(c, g, m_f, N_f, m_s, N_s, ws);
+        });
+    }()));
+}
+
+int pss_ipls_iterate(const pss_problem *p, const pss_gamma *g, const void *y, int32_t n_iter,
+                     void *m_nom, void *N_nom, void *m_f, void *N_f, void *ws, size_t ws_bytes,
+                     hipStream_t stream)
+{
+    PSS_GUARD(([&]() -> int {
+        int rc = validate(p);
+        if (rc)
+            return rc;
+        if (!y || !m_nom || !N_nom || n_iter < 0 || ((m_f == nullptr) != (N_f == nullptr))) {
+            set_error("ipls_iterate: null buffer or negative n_iter");
+            return PSS_EINVAL;
+        }
+        if (p->model == PSS_MODEL_LINEAR ? !gamma_ok(g) : g != nullptr) {
+            set_error("ipls_iterate: a linear model needs g, the CT model takes g = NULL");
+            return PSS_EINVAL;
+        }
+        const Ctx c = make_ctx(p, stream);
+        if ((rc = check_ws(c, PSS_OP_IPLS, ws, ws_bytes)))
+            return rc;
+        return dispatch(p, [&](auto tag) {
+            using I = typename decltype(tag)::I;
+            return I::ipls(c, g, y, n_iter, m_nom, N_nom, m_f, N_f, ws);
+        });
+    }()));
+}
+
+int pss_loglik(const pss_problem *p, const pss_gamma *g, const void *m_nom, const void *N_nom,
+               const void *y, double *ll, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    PSS_GUARD(([&]() -> int {
+        int rc = validate(p);
+        if (rc)
+            return rc;
+        if (!y || !ll) {
+            set_error("loglik: null buffer");
+            return PSS_EINVAL;
+        }
+        if (p->model == PSS_MODEL_LINEAR ? !gamma_ok(g) : (!m_nom || !N_nom)) {
+            set_error("loglik: a linear model needs g, the CT model needs the nominal");
+            return PSS_EINVAL;
+        }
+        const Ctx c = make_ctx(p, stream);
+        if ((rc = check_ws(c, PSS_OP_LOGLIK, ws, ws_bytes)))
+            return rc;
+        return dispatch(p, [&](auto tag) {
+            using I = typename decltype(tag)::I;
+            return I::loglik(c, g, m_nom, N_nom, y, ll, ws);
+        });
+    }()));
+}
+
+int pss_loglik_grad(const pss_problem *p, const void *m_nom, const void *N_nom, const void *y,
+                    const double *ll_bar, double *ll, double *grad, double *theta_bar, void *ws,
+                    size_t ws_bytes, hipStream_t stream)
+{
+    PSS_GUARD(([&]() -> int {
+        int rc = validate(p);
+        if (rc)
+            return rc;
+        if (p->model != PSS_MODEL_CT_BEARINGS) {
+            set_error("loglik_grad: theta is defined for the coordinated-turn model");
+            return PSS_EUNSUPPORTED;
+        }
+        if (!m_nom || !N_nom || !y || !ll) {
+            set_error("loglik_grad: null buffer");
+            return PSS_EINVAL;
+        }
+        const Ctx c = make_ctx(p, stream);
+        if ((rc = check_ws(c, PSS_OP_LOGLIK_GRAD, ws, ws_bytes)))
+            return rc;
+        return dispatch(p, [&](auto tag) {
+            using I = typename decltype(tag)::I;
+            return I::loglik_grad(c, m_nom, N_nom, y, ll_bar, ll, grad, theta_bar, ws);
+        });
+    }()));
+}
+
+int pss_sequential_smoother(const pss_problem *p, const pss_gamma *g, const void *y,
+                            int32_t n_iter, void *m_nom, void *N_nom, void *m_f, void *N_f,
+                            void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    PSS_GUARD(([&]() -> int {
+        int rc = validate(p);
+        if (rc)
+            return rc;
+        if (!y || !m_nom || !N_nom || n_iter < 0 || ((m_f == nullptr) != (N_f == nullptr))) {
+            set_error("sequential_smoother: null buffer or negative n_iter");
+            return PSS_EINVAL;
+        }
+        if (p->model == PSS_MODEL_LINEAR ? !gamma_ok(g) : g != nullptr) {
+            set_error("sequential_smoother: a linear model needs g, the CT model takes g = NULL");
+            return PSS_EINVAL;
+        }
+        const Ctx c = make_ctx(p, stream);
+        if ((rc = check_ws(c, PSS_OP_SEQUENTIAL, ws, ws_bytes)))
+            return rc;
+        return dispatch(p, [&](auto tag) {
+            using I = typename decltype(tag)::I;
+            return I::sequential(c, g, y, n_iter, m_nom, N_nom, m_f, N_f, ws);
+        });
+    }()));
+}
+
+} // extern "C"

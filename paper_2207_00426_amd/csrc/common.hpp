@@ -1,0 +1,86 @@
+// Declarations shared by the C-ABI unit and the per-dimension units.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/pss.h"
+
+namespace pss {
+
+constexpr int kMaxLevels = 8;
+
+void set_error(const std::string &msg);
+int hip_check(hipError_t e, const char *what);
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// bump allocator over the caller's workspace
+struct Carver {
+    char *base;
+    size_t used = 0;
+    template <typename X>
+    X *take(size_t count)
+    {
+        X *p = base ? reinterpret_cast<X *>(base + used) : nullptr;
+        used = align256(used + count * sizeof(X));
+        return p;
+    }
+};
+
+// resolved call context
+struct Ctx {
+    const pss_problem *p;
+    int B;
+    int64_t T_y, T_x;
+    hipStream_t s;
+};
+
+// shape of one scan (filter: n_b elements per sequence, smoother: n_b + 1)
+struct ScanShape {
+    int L = 0;
+    int T[kMaxLevels];
+    int E[kMaxLevels];
+    int64_t ntiles[kMaxLevels];
+    int64_t nelem[kMaxLevels];
+};
+
+ScanShape plan_scan(const Ctx &c, int extra, int T0, int E0, int Tup, int Eup);
+int launch_plan(const Ctx &c, const ScanShape &sh, int extra, int64_t *const *tile_off);
+int launch_seq_sum(const Ctx &c, int nc, const double *terms, int64_t ld, double *out);
+int launch_weighted_grad(const Ctx &c, const double *grad, const double *w, double *theta_bar);
+
+// coordinated-turn constants from the problem (host, double precision)
+struct CTHost {
+    double dt, q1, q2, sigma, LQ[5][5], L1[5][5], L2[5][5];
+    double s1x, s1y, s2x, s2y;
+};
+CTHost ct_host(const pss_problem *p);
+
+// one implementation per (dtype, nx, ny); defined in impl.hpp, explicitly
+// instantiated in inst.hip
+template <typename T, int NX, int NY>
+struct Impl {
+    static size_t ws_size(const Ctx &c, int op);
+    static int slr(const Ctx &c, const void *m, const void *N, const void *y,
+                   const pss_gamma *out);
+    static int felem(const Ctx &c, const pss_gamma *g, const void *y, const pss_felem *out);
+    static int fscan(const Ctx &c, const pss_felem *el, void *mf, void *Nf, void *ws);
+    static int sscan(const Ctx &c, const pss_gamma *g, const void *mf, const void *Nf, void *ms,
+                     void *Ns, void *ws);
+    static int ipls(const Ctx &c, const pss_gamma *g, const void *y, int n_iter, void *m_nom,
+                    void *N_nom, void *mf_out, void *Nf_out, void *ws);
+    static int loglik(const Ctx &c, const pss_gamma *g, const void *m_nom, const void *N_nom,
+                      const void *y, double *ll, void *ws);
+    static int loglik_grad(const Ctx &c, const void *m_nom, const void *N_nom, const void *y,
+                           const double *ll_bar, double *ll, double *grad, double *theta_bar,
+                           void *ws);
+    static int sequential(const Ctx &c, const pss_gamma *g, const void *y, int n_iter,
+                          void *m_nom, void *N_nom, void *mf_out, void *Nf_out, void *ws);
+};
+
+#define PSS_DIMS(X) X(1, 1) X(2, 1) X(2, 3) X(3, 2) X(3, 3) X(4, 2) X(5, 2)
+
+} // namespace pss

@@ -1,0 +1,728 @@
+// Square-root parallel filter / smoother elements and associative operators
+// (Lemmas 1-4 and Tables 1-5 of the paper), cubature statistical linear
+// regression (Section 4.3) and the coordinated-turn bearings model
+// (Section 6.2), as per-thread register code for gfx950.
+#pragma once
+
+#include "device_math.hpp"
+
+namespace pss {
+
+// filtering / smoothing marginal: mean and lower factor
+template <typename T, int NX>
+struct Marg {
+    T m[NX];
+    T N[NX][NX];
+};
+
+// filter element Pi^f = {A, b, U, eta, Z} (eq. pi-f); U, Z lower
+template <typename T, int NX>
+struct FElem {
+    T A[NX][NX];
+    T b[NX];
+    T U[NX][NX];
+    T eta[NX];
+    T Z[NX][NX];
+};
+
+// smoother element Pi^s = {E, g, D}; D lower
+template <typename T, int NX>
+struct SElem {
+    T E[NX][NX];
+    T g[NX];
+    T D[NX][NX];
+};
+
+// ---- component visitors: the flat SoA component order of each object ----
+template <typename T, int NX, class Fn>
+PSS_INL void visit(Marg<T, NX> &x, Fn &&f)
+{
+    int c = 0;
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+        f(c++, x.m[i]);
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+#pragma unroll
+        for (int j = 0; j <= i; ++j)
+            f(c++, x.N[i][j]);
+}
+
+template <typename T, int NX, class Fn>
+PSS_INL void visit(FElem<T, NX> &x, Fn &&f)
+{
+    int c = 0;
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+#pragma unroll
+        for (int j = 0; j < NX; ++j)
+            f(c++, x.A[i][j]);
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+        f(c++, x.b[i]);
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+#pragma unroll
+        for (int j = 0; j <= i; ++j)
+            f(c++, x.U[i][j]);
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+        f(c++, x.eta[i]);
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+#pragma unroll
+        for (int j = 0; j <= i; ++j)
+            f(c++, x.Z[i][j]);
+}
+
+template <typename T, int NX, class Fn>
+PSS_INL void visit(SElem<T, NX> &x, Fn &&f)
+{
+    int c = 0;
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+#pragma unroll
+        for (int j = 0; j < NX; ++j)
+            f(c++, x.E[i][j]);
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+        f(c++, x.g[i]);
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+#pragma unroll
+        for (int j = 0; j <= i; ++j)
+            f(c++, x.D[i][j]);
+}
+
+template <int NX> struct Sizes {
+    static constexpr int P = tri_size(NX);
+    static constexpr int marg = NX + P;
+    static constexpr int felem = NX * NX + NX + P + NX + P;
+    static constexpr int selem = NX * NX + NX + P;
+};
+
+// --------------------------------------------------------------------------
+// Lemma 1: filter elements.
+// --------------------------------------------------------------------------
+
+// Psi = Tria([[H L, S_Omega], [L, 0]]) (eq. sqrt-filter-init-2 with L =
+// S_Lambda_{k-1}; eq. sqrt-filter-step1 with L = N_1^-), returning the blocks
+// Psi11 (ny x ny), Psi21 (nx x ny), Psi22 (nx x nx).
+template <typename T, int NX, int NY>
+PSS_INL void psi_blocks(const T (&H)[NY][NX], const T (&L)[NX][NX], const T (&SO)[NY][NY],
+                        T (&P11)[NY][NY], T (&P21)[NX][NY], T (&P22)[NX][NX])
+{
+    constexpr int R = NY + NX, C = NX + NY;
+    T M[R][C];
+    T HL[NY][NX];
+    mm_lower(H, L, HL);
+#pragma unroll
+    for (int i = 0; i < NY; ++i) {
+#pragma unroll
+        for (int j = 0; j < NX; ++j)
+            M[i][j] = HL[i][j];
+#pragma unroll
+        for (int j = 0; j < NY; ++j)
+            M[i][NX + j] = (j <= i) ? SO[i][j] : T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+#pragma unroll
+        for (int j = 0; j < NX; ++j)
+            M[NY + i][j] = (j <= i) ? L[i][j] : T(0);
+#pragma unroll
+        for (int j = 0; j < NY; ++j)
+            M[NY + i][NX + j] = T(0);
+    }
+    lq_rows<R, NX>(M);
+#pragma unroll
+    for (int i = 0; i < NY; ++i)
+#pragma unroll
+        for (int j = 0; j <= i; ++j)
+            P11[i][j] = M[i][j];
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+#pragma unroll
+        for (int j = 0; j < NY; ++j)
+            P21[i][j] = M[NY + i][j];
+#pragma unroll
+        for (int j = 0; j <= i; ++j)
+            P22[i][j] = M[NY + i][NY + j];
+    }
+}
+
+// Z_k = F^T H^T Y^{-T} (nx x ny), stored squared as Tria([Z_k, 0]); and
+// eta_k = Z_k Y^{-1} r with r = y_k - H_k c_{k-1} - d_k.
+template <typename T, int NX, int NY>
+PSS_INL void info_part(const T (&F)[NX][NX], const T (&H)[NY][NX], const T (&Y)[NY][NY],
+                       const T (&r)[NY], FElem<T, NX> &e)
+{
+    T HF[NY][NX];
+    mm(H, F, HF);
+    T HFt[NX][NY];
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+#pragma unroll
+        for (int a = 0; a < NY; ++a)
+            HFt[i][a] = HF[a][i];
+    T Zr[NX][NY];
+    rsolve_lower_t(HFt, Y, Zr);
+    T u[NY];
+    lsolve_lower(Y, r, u);
+    mv(Zr, u, e.eta);
+    tria_rect(Zr, e.Z);
+}
+
+// Table 2 (1 < k <= n), square-root column.  b_k uses d_k.
+template <typename T, int NX, int NY>
+PSS_INL void filter_element(const T (&F)[NX][NX], const T (&c)[NX], const T (&SL)[NX][NX],
+                            const T (&H)[NY][NX], const T (&d)[NY], const T (&SO)[NY][NY],
+                            const T (&y)[NY], FElem<T, NX> &e)
+{
+    T P11[NY][NY], P21[NX][NY];
+    psi_blocks(H, SL, SO, P11, P21, e.U);
+    T K[NX][NY];
+    rsolve_lower(P21, P11, K);
+    // A = (I - K H) F
+    T IKH[NX][NX];
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+#pragma unroll
+        for (int j = 0; j < NX; ++j) {
+            T s = (i == j) ? T(1) : T(0);
+#pragma unroll
+            for (int a = 0; a < NY; ++a)
+                s = pfma(-K[i][a], H[a][j], s);
+            IKH[i][j] = s;
+        }
+    mm(IKH, F, e.A);
+    T Hc[NY], r[NY];
+    mv(H, c, Hc);
+#pragma unroll
+    for (int a = 0; a < NY; ++a)
+        r[a] = y[a] - Hc[a] - d[a];
+    T Kr[NX];
+    mv(K, r, Kr);
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+        e.b[i] = c[i] + Kr[i];
+    info_part(F, H, P11, r, e);
+}
+
+// Table 1 (k = 1), square-root column.
+template <typename T, int NX, int NY>
+PSS_INL void filter_element_first(const T (&m0)[NX], const T (&N0)[NX][NX], const T (&F)[NX][NX],
+                                  const T (&c)[NX], const T (&SL)[NX][NX], const T (&H)[NY][NX],
+                                  const T (&d)[NY], const T (&SO)[NY][NY], const T (&y)[NY],
+                                  FElem<T, NX> &e)
+{
+    T mp[NX];
+    mv(F, m0, mp);
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+        mp[i] += c[i];
+    T FN[NX][NX], Np[NX][NX];
+    mm_lower(F, N0, FN);
+    tria_dense_lower(FN, SL, Np);
+    T P11[NY][NY], P21[NX][NY];
+    psi_blocks(H, Np, SO, P11, P21, e.U);
+    T K[NX][NY];
+    rsolve_lower(P21, P11, K);
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+#pragma unroll
+        for (int j = 0; j < NX; ++j)
+            e.A[i][j] = T(0);
+    T Hm[NY], v[NY];
+    mv(H, mp, Hm);
+#pragma unroll
+    for (int a = 0; a < NY; ++a)
+        v[a] = y[a] - Hm[a] - d[a];
+    T Kv[NX];
+    mv(K, v, Kv);
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+        e.b[i] = mp[i] + Kv[i];
+    T Hc[NY], r[NY];
+    mv(H, c, Hc);
+#pragma unroll
+    for (int a = 0; a < NY; ++a)
+        r[a] = y[a] - Hc[a] - d[a];
+    info_part(F, H, P11, r, e);
+}
+
+// --------------------------------------------------------------------------
+// Lemma 2: the square-root filtering operator  (i) (x) (j)  (Table 3).
+//   Xi = Tria([[U_i^T Z_j, I], [Z_j, 0]])
+//   Tm = U_i Xi11^{-T},  G = I - Tm Xi21^T  (= (I + C_i J_j)^{-1})
+//   A  = A_j G A_i,  b = A_j G (b_i + U_i U_i^T eta_j) + b_j
+//   U  = Tria([A_j Tm, U_j])
+//   eta = A_i^T G^T (eta_j - Z_j Z_j^T b_i) + eta_i
+//   Z  = Tria([A_i^T Xi22, Z_i])
+// --------------------------------------------------------------------------
+template <typename T, int NX>
+PSS_INL void xi_matrix(const T (&Ui)[NX][NX], const T (&Zj)[NX][NX], T (&M)[2 * NX][2 * NX])
+{
+    T W[NX][NX];
+    mm_lowerT_lower(Ui, Zj, W);
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+#pragma unroll
+        for (int j = 0; j < NX; ++j) {
+            M[i][j] = W[i][j];
+            M[i][NX + j] = (i == j) ? T(1) : T(0);
+            M[NX + i][j] = (j <= i) ? Zj[i][j] : T(0);
+            M[NX + i][NX + j] = T(0);
+        }
+    }
+}
+
+template <typename T, int NX>
+PSS_INL void filter_combine(const FElem<T, NX> &ei, const FElem<T, NX> &ej, FElem<T, NX> &o)
+{
+    T M[2 * NX][2 * NX];
+    xi_matrix(ei.U, ej.Z, M);
+    lq_rows<2 * NX, NX>(M);
+    T X11[NX][NX], X21[NX][NX], X22[NX][NX];
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+#pragma unroll
+        for (int j = 0; j < NX; ++j) {
+            X11[i][j] = M[i][j];
+            X21[i][j] = M[NX + i][j];
+            X22[i][j] = M[NX + i][NX + j];
+        }
+    T Ui_full[NX][NX];
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+#pragma unroll
+        for (int j = 0; j < NX; ++j)
+            Ui_full[i][j] = (j <= i) ? ei.U[i][j] : T(0);
+    T Tm[NX][NX];
+    rsolve_lower_t(Ui_full, X11, Tm);
+    T G[NX][NX];
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+#pragma unroll
+        for (int j = 0; j < NX; ++j) {
+            T s = (i == j) ? T(1) : T(0);
+#pragma unroll
+            for (int t = 0; t < NX; ++t)
+                s = pfma(-Tm[i][t], X21[j][t], s);
+            G[i][j] = s;
+        }
+    T AG[NX][NX];
+    mm(ej.A, G, AG);
+    // b
+    T ut[NX], uu[NX], v[NX], w[NX];
+    lowerT_mv(ei.U, ej.eta, ut);
+    lower_mv(ei.U, ut, uu);
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+        v[i] = ei.b[i] + uu[i];
+    mv(AG, v, w);
+    // eta
+    T zt[NX], zz[NX], q[NX], gq[NX], aq[NX];
+    lowerT_mv(ej.Z, ei.b, zt);
+    lower_mv(ej.Z, zt, zz);
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+        q[i] = ej.eta[i] - zz[i];
+    mtv(G, q, gq);
+    mtv(ei.A, gq, aq);
+    // U = Tria([A_j Tm, U_j])
+    T AT[NX][NX];
+    mm(ej.A, Tm, AT);
+    // Z = Tria([A_i^T Xi22, Z_i])
+    T AX[NX][NX];
+#pragma unroll
+    for (int a = 0; a < NX; ++a)
+#pragma unroll
+        for (int c = 0; c < NX; ++c) {
+            T s = ei.A[c][a] * X22[c][c];
+#pragma unroll
+            for (int t = c + 1; t < NX; ++t)
+                s = pfma(ei.A[t][a], X22[t][c], s);
+            AX[a][c] = s;
+        }
+    T An[NX][NX];
+    mm(AG, ei.A, An);
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+        o.b[i] = w[i] + ej.b[i];
+        o.eta[i] = aq[i] + ei.eta[i];
+    }
+    tria_dense_lower(AT, ej.U, o.U);
+    tria_dense_lower(AX, ei.Z, o.Z);
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+#pragma unroll
+        for (int j = 0; j < NX; ++j)
+            o.A[i][j] = An[i][j];
+}
+
+// The operator with a true prefix on the left: every prefix a_1 (x) ... (x)
+// a_k has A = 0 (A_1 = 0 in Table 1), so only its b and U, i.e. the
+// filtering marginal (m, N), matter, and the result is again such a prefix.
+// This is Table 3 with A_i = 0, b_i = m, U_i = N: the Xi22 block and the
+// eta/Z outputs drop out.
+template <typename T, int NX>
+PSS_INL void filter_apply(const Marg<T, NX> &p, const FElem<T, NX> &ej, Marg<T, NX> &o)
+{
+    T M[2 * NX][2 * NX];
+    xi_matrix(p.N, ej.Z, M);
+    lq_rows<NX, NX>(M);
+    T X11[NX][NX], X21[NX][NX];
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+#pragma unroll
+        for (int j = 0; j < NX; ++j) {
+            X11[i][j] = M[i][j];
+            X21[i][j] = M[NX + i][j];
+        }
+    T Nf[NX][NX];
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+#pragma unroll
+        for (int j = 0; j < NX; ++j)
+            Nf[i][j] = (j <= i) ? p.N[i][j] : T(0);
+    T Tm[NX][NX];
+    rsolve_lower_t(Nf, X11, Tm);
+    T G[NX][NX];
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+#pragma unroll
+        for (int j = 0; j < NX; ++j) {
+            T s = (i == j) ? T(1) : T(0);
+#pragma unroll
+            for (int t = 0; t < NX; ++t)
+                s = pfma(-Tm[i][t], X21[j][t], s);
+            G[i][j] = s;
+        }
+    T AG[NX][NX];
+    mm(ej.A, G, AG);
+    T ut[NX], uu[NX], v[NX], w[NX];
+    lowerT_mv(p.N, ej.eta, ut);
+    lower_mv(p.N, ut, uu);
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+        v[i] = p.m[i] + uu[i];
+    mv(AG, v, w);
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+        o.m[i] = w[i] + ej.b[i];
+    T AT[NX][NX];
+    mm(ej.A, Tm, AT);
+    tria_dense_lower(AT, ej.U, o.N);
+}
+
+// --------------------------------------------------------------------------
+// Lemma 3: smoother element (Table 4) for 0 <= k < n.
+//   Phi = Tria([[F N^f, S_Lambda], [N^f, 0]]),  E = Phi21 Phi11^{-1},
+//   g = m^f - E (F m^f + c),  D = Phi22.
+// --------------------------------------------------------------------------
+template <typename T, int NX>
+PSS_INL void smoother_element(const T (&F)[NX][NX], const T (&c)[NX], const T (&SL)[NX][NX],
+                              const Marg<T, NX> &f, SElem<T, NX> &e)
+{
+    T M[2 * NX][2 * NX];
+    T FN[NX][NX];
+    mm_lower(F, f.N, FN);
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+#pragma unroll
+        for (int j = 0; j < NX; ++j) {
+            M[i][j] = FN[i][j];
+            M[i][NX + j] = (j <= i) ? SL[i][j] : T(0);
+            M[NX + i][j] = (j <= i) ? f.N[i][j] : T(0);
+            M[NX + i][NX + j] = T(0);
+        }
+    lq_rows<2 * NX, NX>(M);
+    T P11[NX][NX], P21[NX][NX];
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+#pragma unroll
+        for (int j = 0; j < NX; ++j) {
+            P11[i][j] = M[i][j];
+            P21[i][j] = M[NX + i][j];
+        }
+    rsolve_lower(P21, P11, e.E);
+    T Fm[NX], Eg[NX];
+    mv(F, f.m, Fm);
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+        Fm[i] += c[i];
+    mv(e.E, Fm, Eg);
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+        e.g[i] = f.m[i] - Eg[i];
+#pragma unroll
+        for (int j = 0; j <= i; ++j)
+            e.D[i][j] = M[NX + i][NX + j];
+    }
+}
+
+// last element of a sequence: E = 0, g = m^f_n, D = N^f_n
+template <typename T, int NX>
+PSS_INL void smoother_element_last(const Marg<T, NX> &f, SElem<T, NX> &e)
+{
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+        e.g[i] = f.m[i];
+#pragma unroll
+        for (int j = 0; j < NX; ++j)
+            e.E[i][j] = T(0);
+#pragma unroll
+        for (int j = 0; j <= i; ++j)
+            e.D[i][j] = f.N[i][j];
+    }
+}
+
+// Lemma 4 / Table 5:  (i) (x) (j) = {E_i E_j, E_i g_j + g_i, Tria([E_i D_j, D_i])}
+template <typename T, int NX>
+PSS_INL void smoother_combine(const SElem<T, NX> &ei, const SElem<T, NX> &ej, SElem<T, NX> &o)
+{
+    T ED[NX][NX], Eg[NX], EE[NX][NX];
+    mm_lower(ei.E, ej.D, ED);
+    mv(ei.E, ej.g, Eg);
+    mm(ei.E, ej.E, EE);
+    tria_dense_lower(ED, ei.D, o.D);
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+        o.g[i] = Eg[i] + ei.g[i];
+#pragma unroll
+        for (int j = 0; j < NX; ++j)
+            o.E[i][j] = EE[i][j];
+    }
+}
+
+// element (x) true suffix: a suffix a_k (x) ... (x) a_n has E = 0, so it is a
+// smoothing marginal (g, D) = (m^s, N^s); Table 5 with E_j = 0.
+template <typename T, int NX>
+PSS_INL void smoother_apply(const SElem<T, NX> &ei, const Marg<T, NX> &s, Marg<T, NX> &o)
+{
+    T ED[NX][NX], Eg[NX];
+    mm_lower(ei.E, s.N, ED);
+    mv(ei.E, s.m, Eg);
+    tria_dense_lower(ED, ei.D, o.N);
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+        o.m[i] = Eg[i] + ei.g[i];
+}
+
+// --------------------------------------------------------------------------
+// Coordinated-turn bearings-only model (Section 6.2).
+// --------------------------------------------------------------------------
+template <typename T>
+struct CTParams {
+    T dt;
+    T s1x, s1y, s2x, s2y;
+    T sigma;
+    T LQ[5][5]; // lower factor of Q(theta)
+};
+
+PSS_INL double psin(double x) { return sin(x); }
+PSS_INL float psin(float x) { return sinf(x); }
+PSS_INL double pcos(double x) { return cos(x); }
+PSS_INL float pcos(float x) { return cosf(x); }
+PSS_INL double patan2(double y, double x) { return atan2(y, x); }
+PSS_INL float patan2(float y, float x) { return atan2f(y, x); }
+PSS_INL double pfloor(double x) { return floor(x); }
+PSS_INL float pfloor(float x) { return floorf(x); }
+
+template <typename T>
+PSS_INL T sinc_(T u)
+{
+    return (fabs(u) < T(1e-4)) ? T(1) - u * u / T(6) : psin(u) / u;
+}
+
+// transition mean: the exact flow of p' = v, v' = w J v, w' = 0 over dt
+template <typename T>
+PSS_INL void ct_f(const CTParams<T> &P, const T (&x)[5], T (&o)[5])
+{
+    const T a = x[4] * P.dt;
+    const T h = T(0.5) * a;
+    const T sh = sinc_(h);
+    const T s1 = P.dt * sinc_(a);        // sin(w dt) / w
+    const T s2 = P.dt * h * sh * sh;     // (1 - cos(w dt)) / w
+    const T ca = pcos(a), sa = psin(a);
+    o[0] = x[0] + s1 * x[2] - s2 * x[3];
+    o[1] = x[1] + s2 * x[2] + s1 * x[3];
+    o[2] = ca * x[2] - sa * x[3];
+    o[3] = sa * x[2] + ca * x[3];
+    o[4] = x[4];
+}
+
+template <typename T>
+PSS_INL T wrap_near(T a, T ref)
+{ // ref + (a - ref) reduced to [-pi, pi)
+    const T pi = T(3.14159265358979323846);
+    const T tp = T(6.28318530717958647692);
+    T dlt = a - ref;
+    dlt = dlt - tp * pfloor((dlt + pi) / tp);
+    return ref + dlt;
+}
+
+// bearings of both sensors, on the branch nearest to y
+template <typename T>
+PSS_INL void ct_h(const CTParams<T> &P, const T (&x)[5], const T (&y)[2], T (&o)[2])
+{
+    o[0] = wrap_near(patan2(x[1] - P.s1y, x[0] - P.s1x), y[0]);
+    o[1] = wrap_near(patan2(x[1] - P.s2y, x[0] - P.s2x), y[1]);
+}
+
+// --------------------------------------------------------------------------
+// Cubature SLR (Section 4.3) in the residual form.  With the sigma points
+// X+-_i = m +- sqrt(nx) N e_i (equal weights 1/(2 nx)) and their images
+// written as z+-_i = r + e+-_i (a common reference r plus deviations),
+//   zbar = r + mean(e),
+//   G    = [(e+_i - e-_i) / (2 sqrt(nx))]_i N^{-1},   off = zbar - G m,
+//   S    = Tria([R, S_noise]),  R = [((e+_i + e-_i)/2 - mean(e)) / sqrt(nx)]_i.
+// R R^T equals Zx Zx^T - G N N^T G^T exactly, so S is the paper's
+// DownDate(Tria([S_noise, Zx]), G N) without the subtraction.  Passing
+// deviations instead of raw images keeps the differences free of
+// cancellation when |r| >> |e| (positions far from the origin, bearings).
+// --------------------------------------------------------------------------
+template <typename T, int NX, int NZ>
+PSS_INL void cubature_from_dev(const Marg<T, NX> &mg, const T (&Sn)[NZ][NZ],
+                               const T (&ep)[NZ][NX], const T (&em)[NZ][NX], const T (&r)[NZ],
+                               T (&G)[NZ][NX], T (&off)[NZ], T (&S)[NZ][NZ])
+{
+    const T sq = psqrt(T(NX));
+    const T w = T(1) / T(2 * NX);
+    T Dp[NZ][NX], ebar[NZ];
+#pragma unroll
+    for (int a = 0; a < NZ; ++a) {
+        T s = T(0);
+#pragma unroll
+        for (int i = 0; i < NX; ++i)
+            s += ep[a][i] + em[a][i];
+        ebar[a] = s * w;
+    }
+    const T hd = T(1) / (T(2) * sq);
+#pragma unroll
+    for (int a = 0; a < NZ; ++a)
+#pragma unroll
+        for (int i = 0; i < NX; ++i)
+            Dp[a][i] = (ep[a][i] - em[a][i]) * hd;
+    rsolve_lower(Dp, mg.N, G);
+    T Gm[NZ];
+    mv(G, mg.m, Gm);
+#pragma unroll
+    for (int a = 0; a < NZ; ++a)
+        off[a] = (r[a] + ebar[a]) - Gm[a];
+    const T rs = T(1) / sq;
+    T A[NZ][NX + NZ];
+#pragma unroll
+    for (int a = 0; a < NZ; ++a) {
+#pragma unroll
+        for (int i = 0; i < NX; ++i)
+            A[a][i] = (T(0.5) * (ep[a][i] + em[a][i]) - ebar[a]) * rs;
+#pragma unroll
+        for (int b = 0; b < NZ; ++b)
+            A[a][NX + b] = (b <= a) ? Sn[a][b] : T(0);
+    }
+    lq_rows<NZ, NX>(A);
+#pragma unroll
+    for (int a = 0; a < NZ; ++a)
+#pragma unroll
+        for (int b = 0; b <= a; ++b)
+            S[a][b] = A[a][b];
+}
+
+// column i of sqrt(nx) N: the sigma-point offset d_i
+template <typename T, int NX>
+PSS_INL void sigma_offset(const Marg<T, NX> &mg, int i, T (&dlt)[NX])
+{
+    const T sq = psqrt(T(NX));
+#pragma unroll
+    for (int j = 0; j < NX; ++j)
+        dlt[j] = (j >= i) ? sq * mg.N[j][i] : T(0);
+}
+
+// Transition SLR of the CT model.  The mean map is f(x) = x + phi(v, w)
+// with phi = (s1 vx - s2 vy, s2 vx + s1 vy, -w (s2 vx + s1 vy),
+// w (s1 vx - s2 vy), 0), s1 = sin(w dt)/w, s2 = (1 - cos(w dt))/w.  SLR is
+// linear in the map and exact for the identity, so F = I + G_phi,
+// c = off_phi and the residual is phi's alone; phi only sees the velocity
+// and turn-rate coordinates of the sigma points.
+template <typename T>
+PSS_INL void ct_phi(const CTParams<T> &P, T vx, T vy, T w, T (&o)[5])
+{
+    const T a = w * P.dt;
+    const T h = T(0.5) * a;
+    const T sh = sinc_(h);
+    const T s1 = P.dt * sinc_(a);
+    const T s2 = P.dt * h * sh * sh;
+    o[0] = s1 * vx - s2 * vy;
+    o[1] = s2 * vx + s1 * vy;
+    o[2] = -w * o[1];
+    o[3] = w * o[0];
+    o[4] = T(0);
+}
+
+template <typename T>
+PSS_INL void ct_slr_transition(const CTParams<T> &P, const Marg<T, 5> &mg, T (&F)[5][5],
+                               T (&c)[5], T (&S)[5][5])
+{
+    T ep[5][5], em[5][5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        T dlt[5], zp[5], zm[5];
+        sigma_offset(mg, i, dlt);
+        ct_phi(P, mg.m[2] + dlt[2], mg.m[3] + dlt[3], mg.m[4] + dlt[4], zp);
+        ct_phi(P, mg.m[2] - dlt[2], mg.m[3] - dlt[3], mg.m[4] - dlt[4], zm);
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+            ep[a][i] = zp[a];
+            em[a][i] = zm[a];
+        }
+    }
+    const T r0[5] = {T(0), T(0), T(0), T(0), T(0)};
+    cubature_from_dev(mg, P.LQ, ep, em, r0, F, c, S);
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+        F[i][i] += T(1);
+}
+
+// Measurement SLR of the two bearings.  With u0 = p(m) - s and a sigma point
+// at u0 + du, the bearing is the bearing of u0 plus the angle from u0 to
+// u0 + du, atan2(u0 x du, |u0|^2 + u0 . du), so deviations never subtract
+// two absolute angles.  Images are read on the branch nearest to y: with
+// D0 = wrap(bearing(u0) - y), image - y = wrap(D0 + angle); the deviation
+// from D0 carries the 2 pi branch jumps explicitly.
+template <typename T>
+PSS_INL void ct_slr_bearings(const CTParams<T> &P, const Marg<T, 5> &mg, const T (&y)[2],
+                             T (&H)[2][5], T (&d)[2], T (&S)[2][2])
+{
+    const T pi = T(3.14159265358979323846);
+    const T tp = T(6.28318530717958647692);
+    T ep[2][5], em[2][5], r[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const T sx = q == 0 ? P.s1x : P.s2x, sy = q == 0 ? P.s1y : P.s2y;
+        const T ux = mg.m[0] - sx, uy = mg.m[1] - sy;
+        const T r2 = ux * ux + uy * uy;
+        T D0 = patan2(uy, ux) - y[q];
+        D0 = D0 - tp * pfloor((D0 + pi) / tp);
+        r[q] = y[q] + D0;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            T dlt[5];
+            sigma_offset(mg, i, dlt);
+            const T cr = ux * dlt[1] - uy * dlt[0];
+            const T dt = ux * dlt[0] + uy * dlt[1];
+            const T ap = patan2(cr, r2 + dt);
+            const T am = patan2(-cr, r2 - dt);
+            // branch jumps of D0 + angle back into [-pi, pi)
+            const T kp = pfloor((D0 + ap + pi) / tp);
+            const T km = pfloor((D0 + am + pi) / tp);
+            ep[q][i] = ap - tp * kp;
+            em[q][i] = am - tp * km;
+        }
+    }
+    const T Sn[2][2] = {{P.sigma, T(0)}, {T(0), P.sigma}};
+    cubature_from_dev(mg, Sn, ep, em, r, H, d, S);
+}
+
+} // namespace pss

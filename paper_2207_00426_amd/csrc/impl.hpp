@@ -1,0 +1,594 @@
+// Host-side launch logic: workspace layout, scan level planning and the
+// per-(dtype, nx, ny) implementations behind the C ABI.
+#pragma once
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace pss {
+
+template <typename T>
+inline const T *cptr(const void *p) { return static_cast<const T *>(p); }
+template <typename T>
+inline T *mptr(void *p) { return static_cast<T *>(p); }
+
+// default launch shapes (overridable through pss_problem)
+template <typename T, int NX>
+struct Defaults {
+    static constexpr int T0 = (sizeof(T) == 8 && NX >= 5) ? 128 : 256;
+    static constexpr int E0 = 4;
+    static constexpr int Tup = (sizeof(T) == 8 && NX >= 5) ? 128 : 256;
+    static constexpr int Eup = 2;
+};
+
+template <typename T, int NX, int NY>
+struct Core {
+    using FS = FilterScan<T, NX>;
+    using SS = SmootherScan<T, NX>;
+    static constexpr int P = tri_size(NX);
+    static constexpr int PY = tri_size(NY);
+
+    // ------------------------------------------------------------------
+    static void shapes(const Ctx &c, int &T0, int &E0, int &Tup, int &Eup)
+    {
+        T0 = c.p->scan_threads > 0 ? c.p->scan_threads : Defaults<T, NX>::T0;
+        E0 = c.p->scan_elems > 0 ? c.p->scan_elems : Defaults<T, NX>::E0;
+        Tup = Defaults<T, NX>::Tup;
+        Eup = Defaults<T, NX>::Eup;
+        if (Tup > T0)
+            Tup = T0;
+    }
+
+    // workspace of one scan; with base == nullptr only sizes
+    template <class Op>
+    struct ScanWs {
+        int64_t *tile_off[kMaxLevels];
+        T *agg[kMaxLevels];  // elements of level l >= 1
+        T *pre[kMaxLevels];  // exclusive prefixes of level l >= 1
+        T *tree[kMaxLevels]; // LDS tree of level l < L-1
+    };
+
+    template <class Op>
+    static ScanWs<Op> carve_scan(Carver &cv, const Ctx &c, const ScanShape &sh)
+    {
+        ScanWs<Op> w{};
+        for (int l = 0; l < sh.L; ++l)
+            w.tile_off[l] = cv.template take<int64_t>(c.B + 1);
+        for (int l = 1; l < sh.L; ++l) {
+            w.agg[l] = cv.template take<T>((size_t)Op::NE * sh.nelem[l]);
+            w.pre[l] = cv.template take<T>((size_t)Op::NP * sh.nelem[l]);
+        }
+        for (int l = 0; l + 1 < sh.L; ++l)
+            w.tree[l] = cv.template take<T>((size_t)Op::NE * sh.ntiles[l] * sh.T[l]);
+        return w;
+    }
+
+    static FElemRef<T, NX> felem_ref(T *base, int64_t ld)
+    {
+        FElemRef<T, NX> r;
+        r.ld = ld;
+        r.A = base;
+        r.b = r.A + (int64_t)NX * NX * ld;
+        r.U = r.b + (int64_t)NX * ld;
+        r.eta = r.U + (int64_t)P * ld;
+        r.Z = r.eta + (int64_t)NX * ld;
+        return r;
+    }
+    static SElemRef<T, NX> selem_ref(T *base, int64_t ld)
+    {
+        SElemRef<T, NX> r;
+        r.ld = ld;
+        r.E = base;
+        r.g = r.E + (int64_t)NX * NX * ld;
+        r.D = r.g + (int64_t)NX * ld;
+        return r;
+    }
+    static MargRef<T, NX> marg_ref(T *base, int64_t ld)
+    {
+        MargRef<T, NX> r;
+        r.ld = ld;
+        r.m = base;
+        r.N = base + (int64_t)NX * ld;
+        return r;
+    }
+    static MargRef<T, NX> marg_ref2(const void *m, const void *N, int64_t ld)
+    {
+        MargRef<T, NX> r;
+        r.ld = ld;
+        r.m = const_cast<T *>(cptr<T>(m));
+        r.N = const_cast<T *>(cptr<T>(N));
+        return r;
+    }
+    static GammaRef<T, NX, NY> gamma_ref(const pss_gamma *g, int64_t T_y)
+    {
+        GammaRef<T, NX, NY> r;
+        r.F = mptr<T>(g->F);
+        r.c = mptr<T>(g->c);
+        r.SL = mptr<T>(g->SL);
+        r.H = mptr<T>(g->H);
+        r.d = mptr<T>(g->d);
+        r.SO = mptr<T>(g->SO);
+        r.stride = g->stride;
+        r.ld = g->stride ? T_y : 1;
+        return r;
+    }
+    // a linearisation buffer carved from the workspace (stride 1)
+    static pss_gamma carve_gamma(Carver &cv, int64_t T_y)
+    {
+        pss_gamma g;
+        g.F = cv.template take<T>((size_t)NX * NX * T_y);
+        g.c = cv.template take<T>((size_t)NX * T_y);
+        g.SL = cv.template take<T>((size_t)P * T_y);
+        g.H = cv.template take<T>((size_t)NY * NX * T_y);
+        g.d = cv.template take<T>((size_t)NY * T_y);
+        g.SO = cv.template take<T>((size_t)PY * T_y);
+        g.stride = 1;
+        return g;
+    }
+
+    template <class Op>
+    static size_t lds_bytes(int Tb) { return (size_t)Tb * Op::NE * sizeof(T); }
+
+    template <class K>
+    static int prep_lds(K kernel, size_t bytes)
+    {
+        return hip_check(hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)bytes),
+                         "hipFuncSetAttribute");
+    }
+
+    // generic multi-level scan driver
+    template <class Op, class Src0, class Dst0, class AggRef, class Start>
+    static int run_scan(const Ctx &c, const ScanShape &sh, const ScanWs<Op> &w, int extra,
+                        const Src0 &src0, const Dst0 &dst0, const Start &start,
+                        AggRef (*agg_ref)(T *, int64_t))
+    {
+        int rc = launch_plan(c, sh, extra, w.tile_off);
+        if (rc)
+            return rc;
+        using LvSrc = RefSrc<Op, AggRef>;
+        using LvDst = PreDst<Op, MargRef<T, NX>>;
+        auto geom = [&](int l) {
+            LevelGeom g;
+            g.y_off = c.p->y_off;
+            g.prev_tiles = l > 0 ? w.tile_off[l - 1] : nullptr;
+            g.tile_off = w.tile_off[l];
+            g.level = l;
+            g.extra = extra;
+            g.B = c.B;
+            g.E = sh.E[l];
+            return g;
+        };
+        // up-sweeps of the lower levels
+        for (int l = 0; l + 1 < sh.L; ++l) {
+            const LevelGeom g = geom(l);
+            const int64_t tree_ld = sh.ntiles[l] * sh.T[l];
+            AggRef agg = agg_ref(w.agg[l + 1], sh.nelem[l + 1]);
+            const size_t lb = lds_bytes<Op>(sh.T[l]);
+            if (l == 0) {
+                auto k = k_scan_up<Op, Src0, AggRef>;
+                if ((rc = prep_lds(k, lb)))
+                    return rc;
+                hipLaunchKernelGGL(k, dim3((unsigned)sh.ntiles[l]), dim3(sh.T[l]), lb, c.s, g,
+                                   src0, agg, w.tree[l], tree_ld);
+            } else {
+                LvSrc s{agg_ref(w.agg[l], sh.nelem[l])};
+                auto k = k_scan_up<Op, LvSrc, AggRef>;
+                if ((rc = prep_lds(k, lb)))
+                    return rc;
+                hipLaunchKernelGGL(k, dim3((unsigned)sh.ntiles[l]), dim3(sh.T[l]), lb, c.s, g, s,
+                                   agg, w.tree[l], tree_ld);
+            }
+            if ((rc = hip_check(hipGetLastError(), "scan up launch")))
+                return rc;
+        }
+        // top level
+        {
+            const int l = sh.L - 1;
+            const LevelGeom g = geom(l);
+            const size_t lb = lds_bytes<Op>(sh.T[l]);
+            if (l == 0) {
+                auto k = k_scan_top<Op, Src0, Dst0, Start>;
+                if ((rc = prep_lds(k, lb)))
+                    return rc;
+                hipLaunchKernelGGL(k, dim3((unsigned)sh.ntiles[l]), dim3(sh.T[l]), lb, c.s, g,
+                                   src0, dst0, start);
+            } else {
+                LvSrc s{agg_ref(w.agg[l], sh.nelem[l])};
+                LvDst d{marg_ref(w.pre[l], sh.nelem[l])};
+                auto k = k_scan_top<Op, LvSrc, LvDst, Start>;
+                if ((rc = prep_lds(k, lb)))
+                    return rc;
+                hipLaunchKernelGGL(k, dim3((unsigned)sh.ntiles[l]), dim3(sh.T[l]), lb, c.s, g, s,
+                                   d, start);
+            }
+            if ((rc = hip_check(hipGetLastError(), "scan top launch")))
+                return rc;
+        }
+        // down-sweeps of the lower levels
+        for (int l = sh.L - 2; l >= 0; --l) {
+            const LevelGeom g = geom(l);
+            const int64_t tree_ld = sh.ntiles[l] * sh.T[l];
+            const size_t lb = lds_bytes<Op>(sh.T[l]);
+            MargRef<T, NX> pin = marg_ref(w.pre[l + 1], sh.nelem[l + 1]);
+            if (l == 0) {
+                auto k = k_scan_down<Op, Src0, Dst0, MargRef<T, NX>>;
+                if ((rc = prep_lds(k, lb)))
+                    return rc;
+                hipLaunchKernelGGL(k, dim3((unsigned)sh.ntiles[l]), dim3(sh.T[l]), lb, c.s, g,
+                                   src0, dst0, w.tree[l], tree_ld, pin);
+            } else {
+                LvSrc s{agg_ref(w.agg[l], sh.nelem[l])};
+                LvDst d{marg_ref(w.pre[l], sh.nelem[l])};
+                auto k = k_scan_down<Op, LvSrc, LvDst, MargRef<T, NX>>;
+                if ((rc = prep_lds(k, lb)))
+                    return rc;
+                hipLaunchKernelGGL(k, dim3((unsigned)sh.ntiles[l]), dim3(sh.T[l]), lb, c.s, g, s,
+                                   d, w.tree[l], tree_ld, pin);
+            }
+            if ((rc = hip_check(hipGetLastError(), "scan down launch")))
+                return rc;
+        }
+        return PSS_OK;
+    }
+
+    // ------------------------------------------------------------------
+    // filter scan (elements read from `el`)
+    static ScanShape filter_shape(const Ctx &c)
+    {
+        int T0, E0, Tup, Eup;
+        shapes(c, T0, E0, Tup, Eup);
+        return plan_scan(c, 0, T0, E0, Tup, Eup);
+    }
+    static ScanShape smoother_shape(const Ctx &c)
+    {
+        int T0, E0, Tup, Eup;
+        shapes(c, T0, E0, Tup, Eup);
+        return plan_scan(c, 1, T0, E0, Tup, Eup);
+    }
+
+    static size_t fscan_bytes(const Ctx &c)
+    {
+        Carver cv{nullptr};
+        carve_scan<FS>(cv, c, filter_shape(c));
+        return cv.used;
+    }
+    static size_t sscan_bytes(const Ctx &c)
+    {
+        Carver cv{nullptr};
+        carve_scan<SS>(cv, c, smoother_shape(c));
+        cv.template take<T>((size_t)Sizes<NX>::selem * c.T_x); // element stash
+        return cv.used;
+    }
+
+    static int fscan(const Ctx &c, const pss_felem *el, void *mf, void *Nf, void *ws)
+    {
+        const ScanShape sh = filter_shape(c);
+        Carver cv{static_cast<char *>(ws)};
+        auto w = carve_scan<FS>(cv, c, sh);
+        FElemRef<T, NX> er;
+        er.A = mptr<T>(el->A);
+        er.b = mptr<T>(el->b);
+        er.U = mptr<T>(el->U);
+        er.eta = mptr<T>(el->eta);
+        er.Z = mptr<T>(el->Z);
+        er.ld = c.T_y;
+        RefSrc<FS, FElemRef<T, NX>> src{er};
+        FiltDst<T, NX> dst{marg_ref2(mf, Nf, c.T_x), c.p->y_off};
+        StartPre<T, NX> st{cptr<T>(c.p->m0), cptr<T>(c.p->N0)};
+        return run_scan<FS>(c, sh, w, 0, src, dst, st, &felem_ref);
+    }
+
+    static int sscan(const Ctx &c, const pss_gamma *g, const void *mf, const void *Nf, void *ms,
+                     void *Ns, void *ws)
+    {
+        const ScanShape sh = smoother_shape(c);
+        Carver cv{static_cast<char *>(ws)};
+        auto w = carve_scan<SS>(cv, c, sh);
+        T *stash = cv.template take<T>((size_t)Sizes<NX>::selem * c.T_x);
+        SmootherSrc<T, NX, NY> src{gamma_ref(g, c.T_y), marg_ref2(mf, Nf, c.T_x),
+                                   selem_ref(stash, c.T_x), c.p->y_off};
+        SmoothDst<T, NX> dst{marg_ref2(ms, Ns, c.T_x)};
+        StartPre<T, NX> st{nullptr, nullptr};
+        return run_scan<SS>(c, sh, w, 1, src, dst, st, &selem_ref);
+    }
+
+    static int felem(const Ctx &c, const pss_gamma *g, const void *y, const pss_felem *out)
+    {
+        FElemRef<T, NX> er;
+        er.A = mptr<T>(out->A);
+        er.b = mptr<T>(out->b);
+        er.U = mptr<T>(out->U);
+        er.eta = mptr<T>(out->eta);
+        er.Z = mptr<T>(out->Z);
+        er.ld = c.T_y;
+        const int tb = 128;
+        hipLaunchKernelGGL((k_filter_elements<T, NX, NY>), dim3((unsigned)((c.T_y + tb - 1) / tb)),
+                           dim3(tb), 0, c.s, c.p->y_off, c.B, c.T_y, gamma_ref(g, c.T_y),
+                           cptr<T>(y), cptr<T>(c.p->m0), cptr<T>(c.p->N0), er);
+        return hip_check(hipGetLastError(), "filter elements launch");
+    }
+
+    // ------------------------------------------------------------------
+    // model-specific pieces
+    static int slr(const Ctx &c, const void *m, const void *N, const void *y,
+                   const pss_gamma *out);
+    static int grad_terms(const Ctx &c, const pss_gamma *g, const void *y, const void *mf,
+                          const void *Nf, const void *ms, const void *Ns, double *gterms);
+
+    // ------------------------------------------------------------------
+    // composite operations
+    static size_t felem_bytes(const Ctx &c)
+    {
+        return align256((size_t)Sizes<NX>::felem * c.T_y * sizeof(T));
+    }
+    static size_t marg_bytes(const Ctx &c)
+    {
+        return align256((size_t)Sizes<NX>::marg * c.T_x * sizeof(T));
+    }
+    static size_t gamma_bytes(const Ctx &c)
+    {
+        Carver cv{nullptr};
+        carve_gamma(cv, c.T_y);
+        return cv.used;
+    }
+    static bool is_ct(const Ctx &c) { return c.p->model == PSS_MODEL_CT_BEARINGS; }
+
+    static size_t ws_size(const Ctx &c, int op)
+    {
+        const size_t scans = fscan_bytes(c) > sscan_bytes(c) ? fscan_bytes(c) : sscan_bytes(c);
+        switch (op) {
+        case PSS_OP_SLR:
+        case PSS_OP_FILTER_ELEMENTS:
+            return 0;
+        case PSS_OP_FILTER_SCAN:
+            return fscan_bytes(c);
+        case PSS_OP_SMOOTHER_SCAN:
+            return sscan_bytes(c);
+        case PSS_OP_IPLS:
+            return gamma_bytes(c) + felem_bytes(c) + marg_bytes(c) + scans;
+        case PSS_OP_LOGLIK:
+            return gamma_bytes(c) + felem_bytes(c) + marg_bytes(c) + fscan_bytes(c) +
+                   align256(c.T_y * sizeof(double));
+        case PSS_OP_LOGLIK_GRAD:
+            return gamma_bytes(c) + felem_bytes(c) + marg_bytes(c) +
+                   align256(c.T_y * sizeof(double)) + scans + marg_bytes(c) +
+                   align256(3 * c.T_y * sizeof(double)) + align256(3 * c.B * sizeof(double));
+        case PSS_OP_SEQUENTIAL:
+            return gamma_bytes(c) + marg_bytes(c);
+        default:
+            return 0;
+        }
+    }
+
+    static int ipls(const Ctx &c, const pss_gamma *gin, const void *y, int n_iter, void *m_nom,
+                    void *N_nom, void *mf_out, void *Nf_out, void *ws)
+    {
+        Carver cv{static_cast<char *>(ws)};
+        pss_gamma gw = carve_gamma(cv, c.T_y);
+        T *fel = cv.template take<T>((size_t)Sizes<NX>::felem * c.T_y);
+        T *mfb = cv.template take<T>((size_t)Sizes<NX>::marg * c.T_x);
+        void *scan_ws = cv.base + cv.used;
+        const pss_gamma *g = is_ct(c) ? &gw : gin;
+        FElemRef<T, NX> fr = felem_ref(fel, c.T_y);
+        pss_felem el{fr.A, fr.b, fr.U, fr.eta, fr.Z};
+        void *mf = mf_out ? mf_out : (void *)mfb;
+        void *Nf = mf_out ? Nf_out : (void *)(mfb + (size_t)NX * c.T_x);
+        int rc = PSS_OK;
+        for (int it = 0; it < n_iter && rc == PSS_OK; ++it) {
+            if (is_ct(c) && (rc = slr(c, m_nom, N_nom, y, &gw)))
+                break;
+            if ((rc = felem(c, g, y, &el)))
+                break;
+            if ((rc = fscan(c, &el, mf, Nf, scan_ws)))
+                break;
+            rc = sscan(c, g, mf, Nf, m_nom, N_nom, scan_ws);
+        }
+        return rc;
+    }
+
+    // filter pass shared by loglik and loglik_grad; returns the carved state
+    static int loglik_core(const Ctx &c, const pss_gamma *gin, const void *m_nom,
+                           const void *N_nom, const void *y, double *ll, Carver &cv,
+                           pss_gamma &gw, T *&mfb, void *&scan_ws)
+    {
+        gw = carve_gamma(cv, c.T_y);
+        T *fel = cv.template take<T>((size_t)Sizes<NX>::felem * c.T_y);
+        mfb = cv.template take<T>((size_t)Sizes<NX>::marg * c.T_x);
+        double *ell = cv.template take<double>((size_t)c.T_y);
+        scan_ws = cv.base + cv.used;
+        const pss_gamma *g = is_ct(c) ? &gw : gin;
+        if (!is_ct(c))
+            gw = *gin;
+        FElemRef<T, NX> fr = felem_ref(fel, c.T_y);
+        pss_felem el{fr.A, fr.b, fr.U, fr.eta, fr.Z};
+        int rc;
+        if (is_ct(c) && (rc = slr(c, m_nom, N_nom, y, &gw)))
+            return rc;
+        if ((rc = felem(c, g, y, &el)))
+            return rc;
+        if ((rc = fscan(c, &el, mfb, mfb + (size_t)NX * c.T_x, scan_ws)))
+            return rc;
+        const int tb = 128;
+        hipLaunchKernelGGL((k_loglik_terms<T, NX, NY>),
+                           dim3((unsigned)((c.T_y + tb - 1) / tb)), dim3(tb), 0, c.s,
+                           c.p->y_off, c.B, c.T_y, c.T_x, gamma_ref(g, c.T_y), cptr<T>(y),
+                           marg_ref(mfb, c.T_x), ell);
+        if ((rc = hip_check(hipGetLastError(), "loglik launch")))
+            return rc;
+        return launch_seq_sum(c, 1, ell, c.T_y, ll);
+    }
+
+    static int loglik(const Ctx &c, const pss_gamma *gin, const void *m_nom, const void *N_nom,
+                      const void *y, double *ll, void *ws)
+    {
+        Carver cv{static_cast<char *>(ws)};
+        pss_gamma gw;
+        T *mfb;
+        void *scan_ws;
+        return loglik_core(c, gin, m_nom, N_nom, y, ll, cv, gw, mfb, scan_ws);
+    }
+
+    static int loglik_grad(const Ctx &c, const void *m_nom, const void *N_nom, const void *y,
+                           const double *ll_bar, double *ll, double *grad, double *theta_bar,
+                           void *ws)
+    {
+        // layout: [gamma | felem | mf | ell | scan ws ...] then the grad part
+        // after the largest scan workspace
+        Carver cv{static_cast<char *>(ws)};
+        pss_gamma gw;
+        T *mfb;
+        void *scan_ws;
+        const size_t scans =
+            fscan_bytes(c) > sscan_bytes(c) ? fscan_bytes(c) : sscan_bytes(c);
+        Carver tail{static_cast<char *>(ws) + gamma_bytes(c) + felem_bytes(c) + marg_bytes(c) +
+                    align256(c.T_y * sizeof(double)) + scans};
+        T *msb = tail.template take<T>((size_t)Sizes<NX>::marg * c.T_x);
+        double *gterms = tail.template take<double>((size_t)3 * c.T_y);
+        double *gseq = tail.template take<double>((size_t)3 * c.B);
+        int rc = loglik_core(c, nullptr, m_nom, N_nom, y, ll, cv, gw, mfb, scan_ws);
+        if (rc)
+            return rc;
+        T *mf = mfb, *Nf = mfb + (size_t)NX * c.T_x;
+        T *ms = msb, *Ns = msb + (size_t)NX * c.T_x;
+        if ((rc = sscan(c, &gw, mf, Nf, ms, Ns, scan_ws)))
+            return rc;
+        if ((rc = grad_terms(c, &gw, y, mf, Nf, ms, Ns, gterms)))
+            return rc;
+        double *gout = grad ? grad : gseq;
+        // per-sequence sums land component-major [3][B]
+        if ((rc = launch_seq_sum(c, 3, gterms, c.T_y, gout)))
+            return rc;
+        if (theta_bar)
+            rc = launch_weighted_grad(c, gout, ll_bar, theta_bar);
+        return rc;
+    }
+
+    static int sequential(const Ctx &c, const pss_gamma *gin, const void *y, int n_iter,
+                          void *m_nom, void *N_nom, void *mf_out, void *Nf_out, void *ws)
+    {
+        Carver cv{static_cast<char *>(ws)};
+        pss_gamma gw = carve_gamma(cv, c.T_y);
+        T *mfb = cv.template take<T>((size_t)Sizes<NX>::marg * c.T_x);
+        const pss_gamma *g = is_ct(c) ? &gw : gin;
+        void *mf = mf_out ? mf_out : (void *)mfb;
+        void *Nf = mf_out ? Nf_out : (void *)(mfb + (size_t)NX * c.T_x);
+        int rc = PSS_OK;
+        for (int it = 0; it < n_iter && rc == PSS_OK; ++it) {
+            if (is_ct(c) && (rc = slr(c, m_nom, N_nom, y, &gw)))
+                break;
+            const int tb = 64;
+            hipLaunchKernelGGL((k_sequential<T, NX, NY>), dim3((unsigned)((c.B + tb - 1) / tb)),
+                               dim3(tb), 0, c.s, c.p->y_off, c.B, c.T_y, gamma_ref(g, c.T_y),
+                               cptr<T>(y), cptr<T>(c.p->m0), cptr<T>(c.p->N0),
+                               marg_ref2(mf, Nf, c.T_x), marg_ref2(m_nom, N_nom, c.T_x));
+            rc = hip_check(hipGetLastError(), "sequential launch");
+        }
+        return rc;
+    }
+};
+
+template <typename T, int NX, int NY>
+int Core<T, NX, NY>::slr(const Ctx &c, const void *m, const void *N, const void *y,
+                         const pss_gamma *out)
+{
+    if constexpr (NX == 5 && NY == 2) {
+        const CTHost h = ct_host(c.p);
+        CTParams<T> P;
+        P.dt = (T)h.dt;
+        P.s1x = (T)h.s1x;
+        P.s1y = (T)h.s1y;
+        P.s2x = (T)h.s2x;
+        P.s2y = (T)h.s2y;
+        P.sigma = (T)h.sigma;
+        for (int i = 0; i < 5; ++i)
+            for (int j = 0; j < 5; ++j)
+                P.LQ[i][j] = (T)h.LQ[i][j];
+        const int tb = 128;
+        hipLaunchKernelGGL((k_slr_ct<T>), dim3((unsigned)((c.T_x + tb - 1) / tb)), dim3(tb), 0,
+                           c.s, c.p->y_off, c.B, c.T_x, c.T_y, P, marg_ref2(m, N, c.T_x),
+                           cptr<T>(y), gamma_ref(out, c.T_y));
+        return hip_check(hipGetLastError(), "slr launch");
+    } else {
+        set_error("the coordinated-turn model needs nx = 5, ny = 2");
+        return PSS_EUNSUPPORTED;
+    }
+}
+
+template <typename T, int NX, int NY>
+int Core<T, NX, NY>::grad_terms(const Ctx &c, const pss_gamma *g, const void *y, const void *mf,
+                                const void *Nf, const void *ms, const void *Ns, double *gterms)
+{
+    if constexpr (NX == 5 && NY == 2) {
+        const CTHost h = ct_host(c.p);
+        CTGradParams<T> gp;
+        for (int i = 0; i < 5; ++i)
+            for (int j = 0; j < 5; ++j) {
+                gp.L1[i][j] = (T)h.L1[i][j];
+                gp.L2[i][j] = (T)h.L2[i][j];
+            }
+        gp.sig2 = (T)(h.sigma * h.sigma);
+        const int tb = 128;
+        hipLaunchKernelGGL((k_grad_ct<T>), dim3((unsigned)((c.T_y + tb - 1) / tb)), dim3(tb), 0,
+                           c.s, c.p->y_off, c.B, c.T_y, gamma_ref(g, c.T_y), cptr<T>(y),
+                           marg_ref2(mf, Nf, c.T_x), marg_ref2(ms, Ns, c.T_x), gp, gterms);
+        return hip_check(hipGetLastError(), "grad launch");
+    } else {
+        set_error("the gradient needs the coordinated-turn model");
+        return PSS_EUNSUPPORTED;
+    }
+}
+
+// forwarding definitions of the public per-dimension interface
+template <typename T, int NX, int NY>
+size_t Impl<T, NX, NY>::ws_size(const Ctx &c, int op) { return Core<T, NX, NY>::ws_size(c, op); }
+template <typename T, int NX, int NY>
+int Impl<T, NX, NY>::slr(const Ctx &c, const void *m, const void *N, const void *y,
+                         const pss_gamma *out)
+{
+    return Core<T, NX, NY>::slr(c, m, N, y, out);
+}
+template <typename T, int NX, int NY>
+int Impl<T, NX, NY>::felem(const Ctx &c, const pss_gamma *g, const void *y, const pss_felem *out)
+{
+    return Core<T, NX, NY>::felem(c, g, y, out);
+}
+template <typename T, int NX, int NY>
+int Impl<T, NX, NY>::fscan(const Ctx &c, const pss_felem *el, void *mf, void *Nf, void *ws)
+{
+    return Core<T, NX, NY>::fscan(c, el, mf, Nf, ws);
+}
+template <typename T, int NX, int NY>
+int Impl<T, NX, NY>::sscan(const Ctx &c, const pss_gamma *g, const void *mf, const void *Nf,
+                           void *ms, void *Ns, void *ws)
+{
+    return Core<T, NX, NY>::sscan(c, g, mf, Nf, ms, Ns, ws);
+}
+template <typename T, int NX, int NY>
+int Impl<T, NX, NY>::ipls(const Ctx &c, const pss_gamma *g, const void *y, int n_iter,
+                          void *m_nom, void *N_nom, void *mf_out, void *Nf_out, void *ws)
+{
+    return Core<T, NX, NY>::ipls(c, g, y, n_iter, m_nom, N_nom, mf_out, Nf_out, ws);
+}
+template <typename T, int NX, int NY>
+int Impl<T, NX, NY>::loglik(const Ctx &c, const pss_gamma *g, const void *m_nom,
+                            const void *N_nom, const void *y, double *ll, void *ws)
+{
+    return Core<T, NX, NY>::loglik(c, g, m_nom, N_nom, y, ll, ws);
+}
+template <typename T, int NX, int NY>
+int Impl<T, NX, NY>::loglik_grad(const Ctx &c, const void *m_nom, const void *N_nom,
+                                 const void *y, const double *ll_bar, double *ll, double *grad,
+                                 double *theta_bar, void *ws)
+{
+    return Core<T, NX, NY>::loglik_grad(c, m_nom, N_nom, y, ll_bar, ll, grad, theta_bar, ws);
+}
+template <typename T, int NX, int NY>
+int Impl<T, NX, NY>::sequential(const Ctx &c, const pss_gamma *g, const void *y, int n_iter,
+                                void *m_nom, void *N_nom, void *mf_out, void *Nf_out, void *ws)
+{
+    return Core<T, NX, NY>::sequential(c, g, y, n_iter, m_nom, N_nom, mf_out, Nf_out, ws);
+}
+
+} // namespace pss

@@ -1,0 +1,958 @@
+// HIP kernels of the parallel square-root smoother for gfx950.
+//
+// Scan structure (one per direction): a reduce-then-scan over tiles with a
+// fixed bracketing, so results are bitwise reproducible and a sequence's
+// result does not depend on the rest of its batch.
+//   level 0 elements are the paper's elements; a tile is TS = T * E
+//   consecutive elements of ONE sequence, handled by a block of T threads:
+//     fold    - thread t folds its E elements left to right (full operator)
+//     up      - in-LDS up-sweep over the T thread aggregates (Blelloch)
+//     down    - in-LDS down-sweep seeded with the tile's exclusive prefix;
+//               prefixes are true prefixes (A = 0 / E = 0), so only the
+//               marginal (m, N) travels and the cheap "apply" form is used
+//     apply   - thread t walks its E elements again, producing the outputs
+//   the tile aggregates of level l are the elements of level l + 1, until a
+//   level has one tile per sequence; that top level runs fold, up, down and
+//   apply in one kernel; lower levels run an "up" kernel (fold + up-sweep,
+//   LDS tree saved to global) and later a "down" kernel.
+// LDS holds one object per thread, component-major ([c * T + slot]) so that
+// consecutive lanes touch consecutive words.
+#pragma once
+
+#include "common.hpp"
+#include "device_ops.hpp"
+
+namespace pss {
+
+// ---------------------------------------------------------------------------
+// SoA references and loads / stores
+// ---------------------------------------------------------------------------
+template <typename T, int NX>
+struct MargRef {
+    T *m;
+    T *N;
+    int64_t ld;
+    PSS_INL void load(int64_t t, Marg<T, NX> &x) const
+    {
+#pragma unroll
+        for (int i = 0; i < NX; ++i)
+            x.m[i] = m[i * ld + t];
+#pragma unroll
+        for (int i = 0; i < NX; ++i)
+#pragma unroll
+            for (int j = 0; j <= i; ++j)
+                x.N[i][j] = N[tri_idx(i, j) * ld + t];
+    }
+    PSS_INL void store(int64_t t, const Marg<T, NX> &x) const
+    {
+#pragma unroll
+        for (int i = 0; i < NX; ++i)
+            m[i * ld + t] = x.m[i];
+#pragma unroll
+        for (int i = 0; i < NX; ++i)
+#pragma unroll
+            for (int j = 0; j <= i; ++j)
+                N[tri_idx(i, j) * ld + t] = x.N[i][j];
+    }
+};
+
+template <typename T, int NX>
+struct FElemRef {
+    T *A, *b, *U, *eta, *Z;
+    int64_t ld;
+    PSS_INL void load(int64_t t, FElem<T, NX> &e) const
+    {
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+#pragma unroll
+            for (int j = 0; j < NX; ++j)
+                e.A[i][j] = A[(i * NX + j) * ld + t];
+            e.b[i] = b[i * ld + t];
+            e.eta[i] = eta[i * ld + t];
+#pragma unroll
+            for (int j = 0; j <= i; ++j) {
+                e.U[i][j] = U[tri_idx(i, j) * ld + t];
+                e.Z[i][j] = Z[tri_idx(i, j) * ld + t];
+            }
+        }
+    }
+    PSS_INL void store(int64_t t, const FElem<T, NX> &e) const
+    {
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+#pragma unroll
+            for (int j = 0; j < NX; ++j)
+                A[(i * NX + j) * ld + t] = e.A[i][j];
+            b[i * ld + t] = e.b[i];
+            eta[i * ld + t] = e.eta[i];
+#pragma unroll
+            for (int j = 0; j <= i; ++j) {
+                U[tri_idx(i, j) * ld + t] = e.U[i][j];
+                Z[tri_idx(i, j) * ld + t] = e.Z[i][j];
+            }
+        }
+    }
+};
+
+template <typename T, int NX>
+struct SElemRef {
+    T *E, *g, *D;
+    int64_t ld;
+    PSS_INL void load(int64_t t, SElem<T, NX> &e) const
+    {
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+#pragma unroll
+            for (int j = 0; j < NX; ++j)
+                e.E[i][j] = E[(i * NX + j) * ld + t];
+            e.g[i] = g[i * ld + t];
+#pragma unroll
+            for (int j = 0; j <= i; ++j)
+                e.D[i][j] = D[tri_idx(i, j) * ld + t];
+        }
+    }
+    PSS_INL void store(int64_t t, const SElem<T, NX> &e) const
+    {
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+#pragma unroll
+            for (int j = 0; j < NX; ++j)
+                E[(i * NX + j) * ld + t] = e.E[i][j];
+            g[i * ld + t] = e.g[i];
+#pragma unroll
+            for (int j = 0; j <= i; ++j)
+                D[tri_idx(i, j) * ld + t] = e.D[i][j];
+        }
+    }
+};
+
+// linearisation parameters (stride 0: one shared set)
+template <typename T, int NX, int NY>
+struct GammaRef {
+    T *F, *c, *SL, *H, *d, *SO;
+    int64_t ld;     // T_y (or 1 when shared)
+    int64_t stride; // 0 or 1
+    PSS_INL void load_trans(int64_t t, T (&Fm)[NX][NX], T (&cv)[NX], T (&S)[NX][NX]) const
+    {
+        const int64_t u = t * stride;
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+#pragma unroll
+            for (int j = 0; j < NX; ++j)
+                Fm[i][j] = F[(i * NX + j) * ld + u];
+            cv[i] = c[i * ld + u];
+#pragma unroll
+            for (int j = 0; j <= i; ++j)
+                S[i][j] = SL[tri_idx(i, j) * ld + u];
+        }
+    }
+    PSS_INL void load_obs(int64_t t, T (&Hm)[NY][NX], T (&dv)[NY], T (&S)[NY][NY]) const
+    {
+        const int64_t u = t * stride;
+#pragma unroll
+        for (int a = 0; a < NY; ++a) {
+#pragma unroll
+            for (int j = 0; j < NX; ++j)
+                Hm[a][j] = H[(a * NX + j) * ld + u];
+            dv[a] = d[a * ld + u];
+#pragma unroll
+            for (int j = 0; j <= a; ++j)
+                S[a][j] = SO[tri_idx(a, j) * ld + u];
+        }
+    }
+    PSS_INL void store_trans(int64_t t, const T (&Fm)[NX][NX], const T (&cv)[NX],
+                             const T (&S)[NX][NX]) const
+    {
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+#pragma unroll
+            for (int j = 0; j < NX; ++j)
+                F[(i * NX + j) * ld + t] = Fm[i][j];
+            c[i * ld + t] = cv[i];
+#pragma unroll
+            for (int j = 0; j <= i; ++j)
+                SL[tri_idx(i, j) * ld + t] = S[i][j];
+        }
+    }
+    PSS_INL void store_obs(int64_t t, const T (&Hm)[NY][NX], const T (&dv)[NY],
+                           const T (&S)[NY][NY]) const
+    {
+#pragma unroll
+        for (int a = 0; a < NY; ++a) {
+#pragma unroll
+            for (int j = 0; j < NX; ++j)
+                H[(a * NX + j) * ld + t] = Hm[a][j];
+            d[a * ld + t] = dv[a];
+#pragma unroll
+            for (int j = 0; j <= a; ++j)
+                SO[tri_idx(a, j) * ld + t] = S[a][j];
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// sequence lookup
+// ---------------------------------------------------------------------------
+// largest b in [0, B) with off[b] + b * shift <= v
+PSS_INL int find_seq(const int64_t *off, int B, int64_t v, int shift)
+{
+    int lo = 0, hi = B - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] + (int64_t)mid * shift <= v)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
+// scan operator policies
+// ---------------------------------------------------------------------------
+template <typename T_, int NX_>
+struct FilterScan {
+    using T = T_;
+    static constexpr int NX = NX_;
+    using Elem = FElem<T, NX>;
+    using Pre = Marg<T, NX>;
+    static constexpr int NE = Sizes<NX>::felem;
+    static constexpr int NP = Sizes<NX>::marg;
+    PSS_INL static void combine(const Elem &a, const Elem &b, Elem &o) { filter_combine(a, b, o); }
+    PSS_INL static void apply(const Pre &p, const Elem &a, Pre &o) { filter_apply(p, a, o); }
+};
+
+// Reverse associative scan of the smoother, run as a forward scan over the
+// time-reversed elements with the arguments of the operator swapped.
+template <typename T_, int NX_>
+struct SmootherScan {
+    using T = T_;
+    static constexpr int NX = NX_;
+    using Elem = SElem<T, NX>;
+    using Pre = Marg<T, NX>;
+    static constexpr int NE = Sizes<NX>::selem;
+    static constexpr int NP = Sizes<NX>::marg;
+    PSS_INL static void combine(const Elem &a, const Elem &b, Elem &o) { smoother_combine(b, a, o); }
+    PSS_INL static void apply(const Pre &p, const Elem &a, Pre &o) { smoother_apply(a, p, o); }
+};
+
+// LDS object access, component-major
+template <class Obj, typename T>
+PSS_INL void lds_get(Obj &o, const T *lds, int Tb, int s)
+{
+    visit(o, [&](int c, T &v) { v = lds[c * Tb + s]; });
+}
+template <class Obj, typename T>
+PSS_INL void lds_put(Obj &o, T *lds, int Tb, int s)
+{
+    visit(o, [&](int c, T &v) { lds[c * Tb + s] = v; });
+}
+
+// ---------------------------------------------------------------------------
+// in-LDS Blelloch sweeps over the T thread aggregates of a tile.  Slots past
+// `nvalid` hold no data; a node whose right half is empty takes its left
+// half, a node whose left half is empty is empty.  Active jobs are packed
+// onto the lowest threads.
+// ---------------------------------------------------------------------------
+template <class Op>
+PSS_INL void tree_up(typename Op::T *lds, int Tb, int nvalid)
+{
+    using T = typename Op::T;
+    for (int d = 1; d < Tb; d <<= 1) {
+        __syncthreads();
+        const int jobs = Tb / (2 * d);
+        const int j = threadIdx.x;
+        if (j < jobs) {
+            const int r = (j + 1) * 2 * d - 1, l = r - d;
+            if (r - 2 * d + 1 < nvalid) {
+                if (r - d + 1 < nvalid) {
+                    typename Op::Elem a, b, c;
+                    lds_get(a, lds, Tb, l);
+                    lds_get(b, lds, Tb, r);
+                    Op::combine(a, b, c);
+                    lds_put(c, lds, Tb, r);
+                } else {
+                    for (int c = 0; c < Op::NE; ++c)
+                        lds[c * Tb + r] = lds[c * Tb + l];
+                }
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Exclusive down-sweep: on return slot t (t < nvalid) holds, in its first NP
+// components, the prefix preceding thread t's first element.
+template <class Op>
+PSS_INL void tree_down(typename Op::T *lds, int Tb, int nvalid, const typename Op::Pre &root)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        typename Op::Pre r0 = root;
+        lds_put(r0, lds, Tb, Tb - 1);
+    }
+    for (int d = Tb / 2; d >= 1; d >>= 1) {
+        __syncthreads();
+        const int jobs = Tb / (2 * d);
+        const int j = threadIdx.x;
+        if (j < jobs) {
+            const int r = (j + 1) * 2 * d - 1, l = r - d;
+            if (r - 2 * d + 1 < nvalid) {
+                typename Op::Pre P;
+                typename Op::Elem a;
+                lds_get(P, lds, Tb, r);
+                lds_get(a, lds, Tb, l);
+                lds_put(P, lds, Tb, l);
+                if (r - d + 1 < nvalid) {
+                    typename Op::Pre Q;
+                    Op::apply(P, a, Q);
+                    lds_put(Q, lds, Tb, r);
+                }
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// geometry of one scan level
+struct LevelGeom {
+    const int64_t *y_off;      // level 0: measurement offsets
+    const int64_t *prev_tiles; // level >= 1: tile offsets of the level below
+    const int64_t *tile_off;   // this level's tile offsets [B + 1]
+    int level;
+    int extra; // level 0: elements per sequence = n_b + extra, element offset y_off[b] + extra*b
+    int B;
+    int E;
+};
+
+PSS_INL void seq_range(const LevelGeom &g, int b, int64_t &off, int64_t &cnt)
+{
+    if (g.level == 0) {
+        const int64_t a = g.y_off[b], z = g.y_off[b + 1];
+        off = a + (int64_t)g.extra * b;
+        cnt = z - a + g.extra;
+    } else {
+        off = g.prev_tiles[b];
+        cnt = g.prev_tiles[b + 1] - off;
+    }
+}
+
+struct TileInfo {
+    int b;
+    int64_t off, cnt, start;
+    int tcnt, nvalid;
+};
+
+PSS_INL TileInfo tile_info(const LevelGeom &g)
+{
+    TileInfo ti;
+    const int64_t tile = blockIdx.x;
+    ti.b = find_seq(g.tile_off, g.B, tile, 0);
+    const int64_t tin = tile - g.tile_off[ti.b];
+    seq_range(g, ti.b, ti.off, ti.cnt);
+    const int64_t TS = (int64_t)blockDim.x * g.E;
+    ti.start = tin * TS;
+    const int64_t rem = ti.cnt - ti.start;
+    ti.tcnt = (int)(rem < TS ? rem : TS);
+    ti.nvalid = (ti.tcnt + g.E - 1) / g.E;
+    return ti;
+}
+
+// --- element sources --------------------------------------------------------
+// plain SoA source (filter elements, or aggregates of a level below)
+template <class Op, class Ref>
+struct RefSrc {
+    Ref ref;
+    PSS_INL void up(int b, int64_t off, int64_t cnt, int64_t p, typename Op::Elem &e) const
+    {
+        ref.load(off + p, e);
+    }
+    PSS_INL void down(int b, int64_t off, int64_t cnt, int64_t p, typename Op::Elem &e) const
+    {
+        ref.load(off + p, e);
+    }
+};
+
+// smoother level 0: element of state k = n - p built from the transition
+// linearisation of slot (b, k) and the filtering marginal at k (Table 4),
+// stashed at its state slot during the up phase and re-read afterwards.
+template <typename T, int NX, int NY>
+struct SmootherSrc {
+    GammaRef<T, NX, NY> gam;
+    MargRef<T, NX> filt; // ld = T_x
+    SElemRef<T, NX> stash; // ld = T_x
+    const int64_t *y_off;
+    PSS_INL void up(int b, int64_t off, int64_t cnt, int64_t p, SElem<T, NX> &e) const
+    {
+        const int64_t n = cnt - 1, k = n - p;
+        Marg<T, NX> f;
+        filt.load(off + k, f);
+        if (k == n) {
+            smoother_element_last(f, e);
+        } else {
+            T F[NX][NX], c[NX], S[NX][NX];
+            gam.load_trans(y_off[b] + k, F, c, S);
+            smoother_element(F, c, S, f, e);
+        }
+        stash.store(off + k, e);
+    }
+    PSS_INL void down(int b, int64_t off, int64_t cnt, int64_t p, SElem<T, NX> &e) const
+    {
+        stash.load(off + (cnt - 1 - p), e);
+    }
+};
+
+// --- output sinks -------------------------------------------------------------
+// levels >= 1: exclusive prefix of each element
+template <class Op, class Ref>
+struct PreDst {
+    Ref ref;
+    PSS_INL void put(int b, int64_t off, int64_t cnt, int64_t p, const typename Op::Pre &excl,
+                     const typename Op::Pre &incl) const
+    {
+        ref.store(off + p, excl);
+    }
+};
+
+// filter level 0: inclusive prefix of step p+1 is the filtering marginal of
+// state p+1; the first step also writes state 0 (its exclusive prefix, the
+// prior)
+template <typename T, int NX>
+struct FiltDst {
+    MargRef<T, NX> out; // ld = T_x
+    const int64_t *y_off;
+    PSS_INL void put(int b, int64_t off, int64_t cnt, int64_t p, const Marg<T, NX> &excl,
+                     const Marg<T, NX> &incl) const
+    {
+        const int64_t x0 = y_off[b] + b;
+        if (p == 0)
+            out.store(x0, excl);
+        out.store(x0 + p + 1, incl);
+    }
+};
+
+// smoother level 0: inclusive suffix of position p is the smoothing marginal
+// of state n - p
+template <typename T, int NX>
+struct SmoothDst {
+    MargRef<T, NX> out;
+    PSS_INL void put(int b, int64_t off, int64_t cnt, int64_t p, const Marg<T, NX> &excl,
+                     const Marg<T, NX> &incl) const
+    {
+        out.store(off + (cnt - 1 - p), incl);
+    }
+};
+
+// sequence-start prefix: the prior for the filter, zero for the smoother (the
+// first element in scan order has A = 0 / E = 0, so its value never matters)
+template <typename T, int NX>
+struct StartPre {
+    const T *m0; // may be null: zeros
+    const T *N0; // packed lower
+    PSS_INL void get(Marg<T, NX> &p) const
+    {
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+            p.m[i] = m0 ? m0[i] : T(0);
+#pragma unroll
+            for (int j = 0; j <= i; ++j)
+                p.N[i][j] = m0 ? N0[tri_idx(i, j)] : T(0);
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// scan kernels
+// ---------------------------------------------------------------------------
+template <class Op, class Src>
+PSS_INL void fold_phase(const LevelGeom &g, const TileInfo &ti, const Src &src,
+                        typename Op::T *lds, int Tb)
+{
+    const int tid = threadIdx.x;
+    if (tid < ti.nvalid) {
+        const int64_t p0 = ti.start + (int64_t)tid * g.E;
+        int64_t pe = p0 + g.E;
+        if (pe > ti.start + ti.tcnt)
+            pe = ti.start + ti.tcnt;
+        typename Op::Elem acc;
+        src.up(ti.b, ti.off, ti.cnt, p0, acc);
+        for (int64_t p = p0 + 1; p < pe; ++p) {
+            typename Op::Elem e, o;
+            src.up(ti.b, ti.off, ti.cnt, p, e);
+            Op::combine(acc, e, o);
+            acc = o;
+        }
+        lds_put(acc, lds, Tb, tid);
+    }
+}
+
+template <class Op, class Src, class Dst>
+PSS_INL void apply_phase(const LevelGeom &g, const TileInfo &ti, const Src &src, const Dst &dst,
+                         typename Op::T *lds, int Tb)
+{
+    const int tid = threadIdx.x;
+    if (tid < ti.nvalid) {
+        typename Op::Pre P;
+        lds_get(P, lds, Tb, tid);
+        const int64_t p0 = ti.start + (int64_t)tid * g.E;
+        int64_t pe = p0 + g.E;
+        if (pe > ti.start + ti.tcnt)
+            pe = ti.start + ti.tcnt;
+        for (int64_t p = p0; p < pe; ++p) {
+            typename Op::Elem e;
+            typename Op::Pre Q;
+            src.down(ti.b, ti.off, ti.cnt, p, e);
+            Op::apply(P, e, Q);
+            dst.put(ti.b, ti.off, ti.cnt, p, P, Q);
+            P = Q;
+        }
+    }
+}
+
+// lower levels, first half: fold + up-sweep; saves the LDS tree and the
+// tile aggregate (an element of the next level)
+template <class Op, class Src, class AggRef>
+__global__ __launch_bounds__(256) void k_scan_up(LevelGeom g, Src src, AggRef agg,
+                                                 typename Op::T *tree, int64_t tree_ld)
+{
+    using T = typename Op::T;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *lds = reinterpret_cast<T *>(smem_raw);
+    const int Tb = blockDim.x;
+    const TileInfo ti = tile_info(g);
+    fold_phase<Op>(g, ti, src, lds, Tb);
+    tree_up<Op>(lds, Tb, ti.nvalid);
+    const int64_t base = (int64_t)blockIdx.x * Tb + threadIdx.x;
+    for (int c = 0; c < Op::NE; ++c)
+        tree[c * tree_ld + base] = lds[c * Tb + threadIdx.x];
+    if (threadIdx.x == 0) {
+        typename Op::Elem a;
+        lds_get(a, lds, Tb, Tb - 1);
+        agg.store(blockIdx.x, a);
+    }
+}
+
+// lower levels, second half: restore the tree, down-sweep from the tile's
+// exclusive prefix (written by the level above), apply, emit
+template <class Op, class Src, class Dst, class PreRef>
+__global__ __launch_bounds__(256) void k_scan_down(LevelGeom g, Src src, Dst dst,
+                                                   const typename Op::T *tree, int64_t tree_ld,
+                                                   PreRef pre_in)
+{
+    using T = typename Op::T;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *lds = reinterpret_cast<T *>(smem_raw);
+    const int Tb = blockDim.x;
+    const TileInfo ti = tile_info(g);
+    const int64_t base = (int64_t)blockIdx.x * Tb + threadIdx.x;
+    for (int c = 0; c < Op::NE; ++c)
+        lds[c * Tb + threadIdx.x] = tree[c * tree_ld + base];
+    typename Op::Pre root;
+    pre_in.load(blockIdx.x, root);
+    tree_down<Op>(lds, Tb, ti.nvalid, root);
+    apply_phase<Op>(g, ti, src, dst, lds, Tb);
+}
+
+// top level (one tile per sequence): everything in one kernel
+template <class Op, class Src, class Dst, class Start>
+__global__ __launch_bounds__(256) void k_scan_top(LevelGeom g, Src src, Dst dst, Start start)
+{
+    using T = typename Op::T;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *lds = reinterpret_cast<T *>(smem_raw);
+    const int Tb = blockDim.x;
+    const TileInfo ti = tile_info(g);
+    fold_phase<Op>(g, ti, src, lds, Tb);
+    tree_up<Op>(lds, Tb, ti.nvalid);
+    typename Op::Pre root;
+    start.get(root);
+    tree_down<Op>(lds, Tb, ti.nvalid, root);
+    apply_phase<Op>(g, ti, src, dst, lds, Tb);
+}
+
+// tile offsets of every level, one thread per sequence + a block scan
+struct PlanArgs {
+    const int64_t *y_off;
+    int B;
+    int extra;
+    int L;
+    int64_t TS[kMaxLevels];
+    int64_t *tile_off[kMaxLevels];
+};
+
+__global__ __launch_bounds__(1024) void k_plan(PlanArgs a);
+
+// ---------------------------------------------------------------------------
+// element-wise kernels
+// ---------------------------------------------------------------------------
+template <typename T, int NX, int NY>
+__global__ __launch_bounds__(128) void k_filter_elements(const int64_t *y_off, int B, int64_t T_y,
+                                                         GammaRef<T, NX, NY> gam, const T *y,
+                                                         const T *m0, const T *N0,
+                                                         FElemRef<T, NX> out)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T_y)
+        return;
+    const int b = find_seq(y_off, B, t, 0);
+    const int64_t k = t - y_off[b];
+    T F[NX][NX], c[NX], SL[NX][NX], H[NY][NX], d[NY], SO[NY][NY], yy[NY];
+    gam.load_trans(t, F, c, SL);
+    gam.load_obs(t, H, d, SO);
+#pragma unroll
+    for (int a = 0; a < NY; ++a)
+        yy[a] = y[a * T_y + t];
+    FElem<T, NX> e;
+    if (k == 0) {
+        T m[NX], N[NX][NX];
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+            m[i] = m0[i];
+#pragma unroll
+            for (int j = 0; j <= i; ++j)
+                N[i][j] = N0[tri_idx(i, j)];
+        }
+        filter_element_first(m, N, F, c, SL, H, d, SO, yy, e);
+    } else {
+        filter_element(F, c, SL, H, d, SO, yy, e);
+    }
+    out.store(t, e);
+}
+
+// pseudo-log-likelihood terms (Section 5.1) from the filtering marginal of the
+// previous state: ell[t] = log N(y; H m^- + d, Y Y^T)
+template <typename T, int NX, int NY>
+__global__ __launch_bounds__(128) void k_loglik_terms(const int64_t *y_off, int B, int64_t T_y,
+                                                      int64_t T_x, GammaRef<T, NX, NY> gam,
+                                                      const T *y, MargRef<T, NX> filt,
+                                                      double *ell)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T_y)
+        return;
+    const int b = find_seq(y_off, B, t, 0);
+    T F[NX][NX], c[NX], SL[NX][NX], H[NY][NX], d[NY], SO[NY][NY];
+    gam.load_trans(t, F, c, SL);
+    gam.load_obs(t, H, d, SO);
+    Marg<T, NX> f;
+    filt.load(t + b, f);
+    T mp[NX], FN[NX][NX], Np[NX][NX];
+    mv(F, f.m, mp);
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+        mp[i] += c[i];
+    mm_lower(F, f.N, FN);
+    tria_dense_lower(FN, SL, Np);
+    T HN[NY][NX];
+    mm_lower(H, Np, HN);
+    T M[NY][NX + NY];
+#pragma unroll
+    for (int a = 0; a < NY; ++a) {
+#pragma unroll
+        for (int j = 0; j < NX; ++j)
+            M[a][j] = HN[a][j];
+#pragma unroll
+        for (int j = 0; j < NY; ++j)
+            M[a][NX + j] = (j <= a) ? SO[a][j] : T(0);
+    }
+    lq_rows<NY, NX>(M);
+    T Y[NY][NY], v[NY], Hm[NY], u[NY];
+#pragma unroll
+    for (int a = 0; a < NY; ++a)
+#pragma unroll
+        for (int j = 0; j <= a; ++j)
+            Y[a][j] = M[a][j];
+    mv(H, mp, Hm);
+#pragma unroll
+    for (int a = 0; a < NY; ++a)
+        v[a] = y[a * T_y + t] - Hm[a] - d[a];
+    lsolve_lower(Y, v, u);
+    double l = -0.5 * NY * 1.8378770664093454835606594728112; // log(2 pi)
+#pragma unroll
+    for (int a = 0; a < NY; ++a)
+        l -= (double)plog(Y[a][a]) + 0.5 * (double)u[a] * (double)u[a];
+    ell[t] = l;
+}
+
+// deterministic per-sequence sums: fixed per-thread strides then a fixed tree
+template <int NC>
+__global__ __launch_bounds__(256) void k_seq_sum(const int64_t *y_off, const double *terms,
+                                                 int64_t ld, double *out)
+{
+    __shared__ double red[NC][256];
+    const int b = blockIdx.x;
+    const int64_t a = y_off[b], z = y_off[b + 1];
+    double s[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+        s[c] = 0.0;
+    for (int64_t t = a + threadIdx.x; t < z; t += blockDim.x)
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            s[c] += terms[c * ld + t];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+        red[c][threadIdx.x] = s[c];
+    for (int w = blockDim.x / 2; w >= 1; w >>= 1) {
+        __syncthreads();
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                red[c][threadIdx.x] += red[c][threadIdx.x + w];
+    }
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            out[c * (int64_t)gridDim.x + b] = red[c][0];
+}
+
+// theta_bar[c] = sum_b w[b] grad[c][b] in a fixed order (one block)
+__global__ __launch_bounds__(256) void k_weighted_grad(const double *grad, const double *w, int B,
+                                                       double *theta_bar);
+
+// sequential square-root comparator: one thread per sequence runs the
+// filter recursion forward (m^f, N^f stored) and the RTS recursion back.
+template <typename T, int NX, int NY>
+__global__ __launch_bounds__(64) void k_sequential(const int64_t *y_off, int B, int64_t T_y,
+                                                   GammaRef<T, NX, NY> gam, const T *y,
+                                                   const T *m0, const T *N0,
+                                                   MargRef<T, NX> filt, MargRef<T, NX> smooth)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B)
+        return;
+    const int64_t a = y_off[b], n = y_off[b + 1] - a, x0 = a + b;
+    Marg<T, NX> f;
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+        f.m[i] = m0[i];
+#pragma unroll
+        for (int j = 0; j <= i; ++j)
+            f.N[i][j] = N0[tri_idx(i, j)];
+    }
+    filt.store(x0, f);
+    for (int64_t k = 0; k < n; ++k) {
+        T F[NX][NX], c[NX], SL[NX][NX], H[NY][NX], d[NY], SO[NY][NY];
+        gam.load_trans(a + k, F, c, SL);
+        gam.load_obs(a + k, H, d, SO);
+        T mp[NX], FN[NX][NX], Np[NX][NX];
+        mv(F, f.m, mp);
+#pragma unroll
+        for (int i = 0; i < NX; ++i)
+            mp[i] += c[i];
+        mm_lower(F, f.N, FN);
+        tria_dense_lower(FN, SL, Np);
+        T P11[NY][NY], P21[NX][NY];
+        psi_blocks(H, Np, SO, P11, P21, f.N);
+        T Hm[NY], v[NY], u[NY], Ku[NX];
+        mv(H, mp, Hm);
+#pragma unroll
+        for (int q = 0; q < NY; ++q)
+            v[q] = y[q * T_y + a + k] - Hm[q] - d[q];
+        lsolve_lower(P11, v, u);
+        mv(P21, u, Ku);
+#pragma unroll
+        for (int i = 0; i < NX; ++i)
+            f.m[i] = mp[i] + Ku[i];
+        filt.store(x0 + k + 1, f);
+    }
+    Marg<T, NX> s = f;
+    smooth.store(x0 + n, s);
+    for (int64_t k = n - 1; k >= 0; --k) {
+        T F[NX][NX], c[NX], SL[NX][NX];
+        gam.load_trans(a + k, F, c, SL);
+        Marg<T, NX> fk, o;
+        filt.load(x0 + k, fk);
+        SElem<T, NX> e;
+        smoother_element(F, c, SL, fk, e);
+        smoother_apply(e, s, o);
+        s = o;
+        smooth.store(x0 + k, s);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// coordinated-turn model kernels
+// ---------------------------------------------------------------------------
+// one thread per state: transition SLR from state k (slot k, k < n) and
+// measurement SLR from state k (slot k-1, k >= 1)
+template <typename T>
+__global__ __launch_bounds__(128) void k_slr_ct(const int64_t *y_off, int B, int64_t T_x,
+                                                int64_t T_y, CTParams<T> P, MargRef<T, 5> nom,
+                                                const T *y, GammaRef<T, 5, 2> out)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= T_x)
+        return;
+    const int b = find_seq(y_off, B, s, 1);
+    const int64_t x0 = y_off[b] + b, k = s - x0, n = y_off[b + 1] - y_off[b];
+    Marg<T, 5> mg;
+    nom.load(s, mg);
+    if (k < n) {
+        T G[5][5], off[5], S[5][5];
+        ct_slr_transition(P, mg, G, off, S);
+        out.store_trans(y_off[b] + k, G, off, S);
+    }
+    if (k >= 1) {
+        const int64_t t = y_off[b] + k - 1;
+        T yy[2] = {y[t], y[T_y + t]};
+        T G[2][5], off[2], S[2][2];
+        ct_slr_bearings(P, mg, yy, G, off, S);
+        out.store_obs(t, G, off, S);
+    }
+}
+
+// Score terms at a frozen nominal (Fisher's identity on the linearised
+// model): for slot t (transition x_k -> x_{k+1}, measurement y_{k+1})
+//   Sig  = r r^T + Var(x_{k+1} - F x_k | y),  r = m^s_{k+1} - F m^s_k - c,
+//          Var = Tria([(I - F E_k) N^s_{k+1}, F D_k])^2 (smoother element
+//          of Table 4: x_k = E_k x_{k+1} + g_k + N(0, D_k D_k^T)),
+//   dl/dtheta_j += 1/2 tr(Lam^{-1} Sig Lam^{-1} dQ_j) - 1/2 tr(Lam^{-1} dQ_j)
+//   and the same for the measurement with Sig' = v v^T + H P^s_{k+1} H^T.
+// dQ_j = L_j L_j^T are passed as lower factors; dR/dlog sigma = 2 sigma^2 I.
+template <typename T>
+struct CTGradParams {
+    T L1[5][5];
+    T L2[5][5];
+    T sig2; // sigma^2
+};
+
+template <typename T>
+__global__ __launch_bounds__(128) void k_grad_ct(const int64_t *y_off, int B, int64_t T_y,
+                                                 GammaRef<T, 5, 2> gam, const T *y,
+                                                 MargRef<T, 5> filt, MargRef<T, 5> smooth,
+                                                 CTGradParams<T> gp, double *gterms)
+{
+    constexpr int NX = 5, NY = 2;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T_y)
+        return;
+    const int b = find_seq(y_off, B, t, 0);
+    const int64_t xs = t + b; // state k
+    T F[NX][NX], c[NX], SL[NX][NX], H[NY][NX], d[NY], SO[NY][NY];
+    gam.load_trans(t, F, c, SL);
+    gam.load_obs(t, H, d, SO);
+    Marg<T, NX> fk, sk, sk1;
+    filt.load(xs, fk);
+    smooth.load(xs, sk);
+    smooth.load(xs + 1, sk1);
+    SElem<T, NX> e;
+    smoother_element(F, c, SL, fk, e);
+    // V = Tria([(I - F E) N^s_{k+1}, F D])
+    T FE[NX][NX], IFE[NX][NX], X1[NX][NX], X2[NX][NX];
+    mm(F, e.E, FE);
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+#pragma unroll
+        for (int j = 0; j < NX; ++j)
+            IFE[i][j] = ((i == j) ? T(1) : T(0)) - FE[i][j];
+    mm_lower(IFE, sk1.N, X1);
+    mm_lower(F, e.D, X2);
+    T Wm[NX][2 * NX + 1];
+    T Fm[NX];
+    mv(F, sk.m, Fm);
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+#pragma unroll
+        for (int j = 0; j < NX; ++j) {
+            Wm[i][j] = X1[i][j];
+            Wm[i][NX + j] = X2[i][j];
+        }
+        Wm[i][2 * NX] = sk1.m[i] - Fm[i] - c[i];
+    }
+    // K = S^{-T} S^{-1} [V1 V2 r]  (columns of Lam^{-1} [sqrt(Sig)])
+    T Kc[NX][2 * NX + 1];
+#pragma unroll
+    for (int col = 0; col < 2 * NX + 1; ++col) {
+        T x[NX], z[NX], w[NX];
+#pragma unroll
+        for (int i = 0; i < NX; ++i)
+            x[i] = Wm[i][col];
+        lsolve_lower(SL, x, z);
+        // w = S^{-T} z
+#pragma unroll
+        for (int i = NX - 1; i >= 0; --i) {
+            T s = z[i];
+#pragma unroll
+            for (int q = i + 1; q < NX; ++q)
+                s = pfma(-SL[q][i], w[q], s);
+            w[i] = s / SL[i][i];
+        }
+#pragma unroll
+        for (int i = 0; i < NX; ++i)
+            Kc[i][col] = w[i];
+    }
+    double g1 = 0.0, g2 = 0.0;
+    // 1/2 sum_cols |L_j^T k|^2
+#pragma unroll
+    for (int col = 0; col < 2 * NX + 1; ++col) {
+#pragma unroll
+        for (int q = 0; q < NX; ++q) {
+            T s1 = T(0), s2 = T(0);
+#pragma unroll
+            for (int i = q; i < NX; ++i) {
+                s1 = pfma(gp.L1[i][q], Kc[i][col], s1);
+                s2 = pfma(gp.L2[i][q], Kc[i][col], s2);
+            }
+            g1 += 0.5 * (double)s1 * (double)s1;
+            g2 += 0.5 * (double)s2 * (double)s2;
+        }
+    }
+    // - 1/2 |S^{-1} L_j|_F^2
+#pragma unroll
+    for (int q = 0; q < NX; ++q) {
+        T x1[NX], x2[NX], z1[NX], z2[NX];
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+            x1[i] = (i >= q) ? gp.L1[i][q] : T(0);
+            x2[i] = (i >= q) ? gp.L2[i][q] : T(0);
+        }
+        lsolve_lower(SL, x1, z1);
+        lsolve_lower(SL, x2, z2);
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+            g1 -= 0.5 * (double)z1[i] * (double)z1[i];
+            g2 -= 0.5 * (double)z2[i] * (double)z2[i];
+        }
+    }
+    // measurement: Sig' = [v, H N^s_{k+1}] [...]^T, dR = 2 sigma^2 I
+    T HN[NY][NX], Hm[NY];
+    mm_lower(H, sk1.N, HN);
+    mv(H, sk1.m, Hm);
+    double g3 = 0.0;
+#pragma unroll
+    for (int col = 0; col <= NX; ++col) {
+        T x[NY], z[NY], w[NY];
+#pragma unroll
+        for (int a = 0; a < NY; ++a)
+            x[a] = (col < NX) ? HN[a][col] : (y[a * T_y + t] - Hm[a] - d[a]);
+        lsolve_lower(SO, x, z);
+#pragma unroll
+        for (int i = NY - 1; i >= 0; --i) {
+            T s = z[i];
+#pragma unroll
+            for (int q = i + 1; q < NY; ++q)
+                s = pfma(-SO[q][i], w[q], s);
+            w[i] = s / SO[i][i];
+        }
+#pragma unroll
+        for (int a = 0; a < NY; ++a)
+            g3 += (double)gp.sig2 * (double)w[a] * (double)w[a];
+    }
+#pragma unroll
+    for (int q = 0; q < NY; ++q) {
+        T x[NY], z[NY];
+#pragma unroll
+        for (int a = 0; a < NY; ++a)
+            x[a] = (a == q) ? T(1) : T(0);
+        lsolve_lower(SO, x, z);
+#pragma unroll
+        for (int a = 0; a < NY; ++a)
+            g3 -= (double)gp.sig2 * (double)z[a] * (double)z[a];
+    }
+    gterms[0 * T_y + t] = g1;
+    gterms[1 * T_y + t] = g2;
+    gterms[2 * T_y + t] = g3;
+}
+
+} // namespace pss

@@ -1,0 +1,446 @@
+"""Thin Python binding of libpss.so (the C ABI declared in include/pss.h).
+
+Argument marshalling only: every computation runs in the HIP library.  PyTorch
+provides device memory and the current HIP stream.  There is no fallback: if
+the library or a GPU is missing, calls raise.
+
+Layouts follow the C ABI: structure-of-arrays, component-major.
+  y      [ny, T_y]          measurements (step slots)
+  m      [nx, T_x]          means (state slots)
+  N      [nx(nx+1)/2, T_x]  packed lower factors, row-major
+  Gamma  dict F [nx*nx, S], c [nx, S], SL [P, S], H [ny*nx, S], d [ny, S],
+         SO [Py, S] with S = T_y (stride 1) or 1 (stride 0)
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpss.so")
+
+PSS_F32, PSS_F64 = 0, 1
+MODEL_LINEAR, MODEL_CT = 0, 1
+OPS = dict(slr=0, filter_elements=1, filter_scan=2, smoother_scan=3, ipls=4, loglik=5,
+           loglik_grad=6, sequential=7)
+STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported", -3: "workspace too small",
+          -4: "HIP error"}
+EXPORTS = ["pss_workspace_size", "pss_slr_linearize", "pss_sqrt_filter_elements",
+           "pss_sqrt_filter_scan", "pss_sqrt_smoother_scan", "pss_ipls_iterate", "pss_loglik",
+           "pss_loglik_grad", "pss_sequential_smoother", "pss_validate", "pss_last_error",
+           "pss_version"]
+
+
+class PssError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("pss error %d (%s): %s" % (code, STATUS.get(code, "?"), msg))
+        self.code = code
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int32), ("dtype", ctypes.c_int32), ("nx", ctypes.c_int32),
+                ("ny", ctypes.c_int32), ("B", ctypes.c_int32),
+                ("y_off", ctypes.c_void_p), ("y_off_host", ctypes.c_void_p),
+                ("m0", ctypes.c_void_p), ("N0", ctypes.c_void_p),
+                ("dt", ctypes.c_double), ("theta", ctypes.c_double * 3),
+                ("sensors", ctypes.c_double * 4),
+                ("scan_threads", ctypes.c_int32), ("scan_elems", ctypes.c_int32)]
+
+
+class GammaC(ctypes.Structure):
+    _fields_ = [("F", ctypes.c_void_p), ("c", ctypes.c_void_p), ("SL", ctypes.c_void_p),
+                ("H", ctypes.c_void_p), ("d", ctypes.c_void_p), ("SO", ctypes.c_void_p),
+                ("stride", ctypes.c_int64)]
+
+
+class FElemC(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_void_p), ("b", ctypes.c_void_p), ("U", ctypes.c_void_p),
+                ("eta", ctypes.c_void_p), ("Z", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libpss.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libpss.so not built: run __graft_entry__.build() "
+                               "(or python paper_2207_00426_amd/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+        P = ctypes.POINTER(Problem)
+        L.pss_workspace_size.restype = sz
+        L.pss_workspace_size.argtypes = [P, i32]
+        L.pss_validate.argtypes = [P]
+        L.pss_last_error.restype = ctypes.c_char_p
+        L.pss_version.restype = ctypes.c_char_p
+        L.pss_slr_linearize.argtypes = [P, vp, vp, vp, ctypes.POINTER(GammaC), vp]
+        L.pss_sqrt_filter_elements.argtypes = [P, ctypes.POINTER(GammaC), vp,
+                                               ctypes.POINTER(FElemC), vp]
+        L.pss_sqrt_filter_scan.argtypes = [P, ctypes.POINTER(FElemC), vp, vp, vp, sz, vp]
+        L.pss_sqrt_smoother_scan.argtypes = [P, ctypes.POINTER(GammaC), vp, vp, vp, vp, vp, sz,
+                                             vp]
+        L.pss_ipls_iterate.argtypes = [P, ctypes.POINTER(GammaC), vp, i32, vp, vp, vp, vp, vp,
+                                       sz, vp]
+        L.pss_loglik.argtypes = [P, ctypes.POINTER(GammaC), vp, vp, vp, vp, vp, sz, vp]
+        L.pss_loglik_grad.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.pss_sequential_smoother.argtypes = [P, ctypes.POINTER(GammaC), vp, i32, vp, vp, vp, vp,
+                                              vp, sz, vp]
+        for name in ("pss_slr_linearize", "pss_sqrt_filter_elements", "pss_sqrt_filter_scan",
+                     "pss_sqrt_smoother_scan", "pss_ipls_iterate", "pss_loglik",
+                     "pss_loglik_grad", "pss_sequential_smoother", "pss_validate"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().pss_last_error().decode()
+
+
+def version() -> str:
+    return lib().pss_version().decode()
+
+
+def _check(rc):
+    if rc != 0:
+        raise PssError(rc, last_error())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _require_gpu():
+    if not torch.cuda.is_available():
+        raise RuntimeError("the pss library needs a GPU (gfx950); none is visible")
+
+
+def tri(n):
+    return n * (n + 1) // 2
+
+
+# ---------------------------------------------------------------------------
+# layout helpers (numpy AoS <-> torch SoA)
+# ---------------------------------------------------------------------------
+def pack_lower(N):
+    """[..., n, n] -> [..., n(n+1)/2] row-major lower triangle."""
+    N = np.asarray(N)
+    n = N.shape[-1]
+    ii, jj = np.tril_indices(n)
+    return N[..., ii, jj]
+
+
+def unpack_lower(P, n):
+    P = np.asarray(P)
+    ii, jj = np.tril_indices(n)
+    out = np.zeros(P.shape[:-1] + (n, n), dtype=P.dtype)
+    out[..., ii, jj] = P
+    return out
+
+
+def to_soa(a, dtype, device):
+    """numpy [T, ...] -> torch [prod(...), T] on device."""
+    a = np.asarray(a, dtype=np.float64)
+    a2 = a.reshape(a.shape[0], -1).T
+    return torch.tensor(np.ascontiguousarray(a2), dtype=dtype, device=device)
+
+
+def from_soa(t, shape):
+    """torch [C, T] -> numpy [T, *shape]."""
+    a = t.detach().double().cpu().numpy()
+    return a.T.reshape((a.shape[1],) + tuple(shape))
+
+
+def marg_from_soa(m, N, nx):
+    """(m [nx, T], N [P, T]) -> numpy means [T, nx] and factors [T, nx, nx]."""
+    return from_soa(m, (nx,)), unpack_lower(from_soa(N, (tri(nx),)), nx)
+
+
+# ---------------------------------------------------------------------------
+# problem
+# ---------------------------------------------------------------------------
+class Batch:
+    """A batch of B sequences of one model, plus the device buffers the C ABI reads."""
+
+    def __init__(self, model, dtype, nx, ny, y_off, m0, N0, device="cuda", dt=0.0,
+                 theta=(0.0, 0.0, 0.0), sensors=(0.0, 0.0, 0.0, 0.0), scan_threads=0,
+                 scan_elems=0):
+        self.model = model
+        self.torch_dtype = dtype
+        self.nx, self.ny = nx, ny
+        self.y_off_host = np.ascontiguousarray(np.asarray(y_off, dtype=np.int64))
+        self.B = len(self.y_off_host) - 1
+        self.T_y = int(self.y_off_host[-1])
+        self.T_x = self.T_y + self.B
+        self.device = device
+        self.y_off = torch.tensor(self.y_off_host, dtype=torch.int64, device=device)
+        self.m0 = torch.tensor(np.asarray(m0, dtype=np.float64), dtype=dtype, device=device)
+        self.N0 = torch.tensor(pack_lower(np.asarray(N0, dtype=np.float64)), dtype=dtype,
+                               device=device)
+        self.dt = float(dt)
+        self.theta = tuple(float(v) for v in theta)
+        self.sensors = tuple(float(v) for v in sensors)
+        self.scan_threads = int(scan_threads)
+        self.scan_elems = int(scan_elems)
+
+    @classmethod
+    def ct(cls, y_off, model, dtype=torch.float64, device="cuda", theta=None, **kw):
+        """Coordinated-turn bearings model (workloads.CTModel)."""
+        th = model.theta if theta is None else theta
+        s = model.sensors
+        return cls(MODEL_CT, dtype, 5, 2, y_off, model.m0, np.linalg.cholesky(model.P0),
+                   device=device, dt=model.dt, theta=th,
+                   sensors=(s[0][0], s[0][1], s[1][0], s[1][1]), **kw)
+
+    @property
+    def pss_dtype(self):
+        return PSS_F64 if self.torch_dtype == torch.float64 else PSS_F32
+
+    def struct(self):
+        p = Problem()
+        p.model = self.model
+        p.dtype = self.pss_dtype
+        p.nx, p.ny, p.B = self.nx, self.ny, self.B
+        p.y_off = self.y_off.data_ptr() if self.y_off is not None else None
+        p.y_off_host = self.y_off_host.ctypes.data
+        p.m0 = self.m0.data_ptr() if self.m0 is not None else None
+        p.N0 = self.N0.data_ptr() if self.N0 is not None else None
+        p.dt = self.dt
+        p.theta = (ctypes.c_double * 3)(*self.theta)
+        p.sensors = (ctypes.c_double * 4)(*self.sensors)
+        p.scan_threads = self.scan_threads
+        p.scan_elems = self.scan_elems
+        return p
+
+    # buffers -------------------------------------------------------------
+    def empty(self, rows, cols):
+        return torch.empty((rows, cols), dtype=self.torch_dtype, device=self.device)
+
+    def new_marg(self):
+        return self.empty(self.nx, self.T_x), self.empty(tri(self.nx), self.T_x)
+
+    def prior_nominal(self):
+        """Nominal trajectory with the prior at every state (the initial IPLS nominal)."""
+        m = self.m0[:, None].repeat(1, self.T_x).contiguous()
+        N = self.N0[:, None].repeat(1, self.T_x).contiguous()
+        return m, N
+
+    def new_gamma(self, stride=1):
+        S = self.T_y if stride else 1
+        nx, ny = self.nx, self.ny
+        return dict(F=self.empty(nx * nx, S), c=self.empty(nx, S), SL=self.empty(tri(nx), S),
+                    H=self.empty(ny * nx, S), d=self.empty(ny, S), SO=self.empty(tri(ny), S),
+                    stride=stride)
+
+    def gamma_from_numpy(self, G):
+        """numpy linear model (shared or per step) -> SoA Gamma dict."""
+        F = np.asarray(G["F"])
+        stride = 1 if F.ndim == 3 else 0
+        dt, dev = self.torch_dtype, self.device
+
+        def conv(a, lower=False):
+            a = np.asarray(a, dtype=np.float64)
+            if lower:
+                a = pack_lower(a)
+            if stride == 0:
+                a = a[None]
+            return to_soa(a, dt, dev)
+
+        return dict(F=conv(G["F"]), c=conv(G["c"]), SL=conv(G["SL"], True), H=conv(G["H"]),
+                    d=conv(G["d"]), SO=conv(G["SO"], True), stride=stride)
+
+    def new_felem(self):
+        nx = self.nx
+        return dict(A=self.empty(nx * nx, self.T_y), b=self.empty(nx, self.T_y),
+                    U=self.empty(tri(nx), self.T_y), eta=self.empty(nx, self.T_y),
+                    Z=self.empty(tri(nx), self.T_y))
+
+    def workspace(self, op):
+        n = workspace_size(self, op)
+        return torch.empty(max(n, 1), dtype=torch.uint8, device=self.device), n
+
+
+def _gamma_c(g):
+    if g is None:
+        return None
+    s = GammaC()
+    for k in ("F", "c", "SL", "H", "d", "SO"):
+        setattr(s, k, g[k].data_ptr())
+    s.stride = g["stride"]
+    return ctypes.byref(s)
+
+
+def _felem_c(e):
+    s = FElemC()
+    for k in ("A", "b", "U", "eta", "Z"):
+        setattr(s, k, e[k].data_ptr())
+    return ctypes.byref(s)
+
+
+# ---------------------------------------------------------------------------
+# entry points (same names as the C ABI)
+# ---------------------------------------------------------------------------
+def validate(batch: Batch) -> int:
+    p = batch.struct()
+    return lib().pss_validate(ctypes.byref(p))
+
+
+def workspace_size(batch: Batch, op) -> int:
+    p = batch.struct()
+    code = OPS[op] if isinstance(op, str) else int(op)
+    return int(lib().pss_workspace_size(ctypes.byref(p), code))
+
+
+def slr_linearize(batch, m_nom, N_nom, y, out=None):
+    _require_gpu()
+    out = batch.new_gamma(1) if out is None else out
+    p = batch.struct()
+    _check(lib().pss_slr_linearize(ctypes.byref(p), _ptr(m_nom), _ptr(N_nom), _ptr(y),
+                                   _gamma_c(out), _stream()))
+    return out
+
+
+def sqrt_filter_elements(batch, gamma, y, out=None):
+    _require_gpu()
+    out = batch.new_felem() if out is None else out
+    p = batch.struct()
+    _check(lib().pss_sqrt_filter_elements(ctypes.byref(p), _gamma_c(gamma), _ptr(y),
+                                          _felem_c(out), _stream()))
+    return out
+
+
+def sqrt_filter_scan(batch, felem, m_f=None, N_f=None):
+    _require_gpu()
+    if m_f is None:
+        m_f, N_f = batch.new_marg()
+    ws, n = batch.workspace("filter_scan")
+    p = batch.struct()
+    _check(lib().pss_sqrt_filter_scan(ctypes.byref(p), _felem_c(felem), _ptr(m_f), _ptr(N_f),
+                                      _ptr(ws), n, _stream()))
+    return m_f, N_f
+
+
+def sqrt_smoother_scan(batch, gamma, m_f, N_f, m_s=None, N_s=None):
+    _require_gpu()
+    if m_s is None:
+        m_s, N_s = batch.new_marg()
+    ws, n = batch.workspace("smoother_scan")
+    p = batch.struct()
+    _check(lib().pss_sqrt_smoother_scan(ctypes.byref(p), _gamma_c(gamma), _ptr(m_f), _ptr(N_f),
+                                        _ptr(m_s), _ptr(N_s), _ptr(ws), n, _stream()))
+    return m_s, N_s
+
+
+def ipls_iterate(batch, y, n_iter, m_nom=None, N_nom=None, gamma=None, want_filter=False,
+                 ws=None):
+    """Algorithm 3 in place on (m_nom, N_nom); returns (m_nom, N_nom[, m_f, N_f])."""
+    _require_gpu()
+    if m_nom is None:
+        m_nom, N_nom = batch.prior_nominal()
+    m_f = N_f = None
+    if want_filter:
+        m_f, N_f = batch.new_marg()
+    if ws is None:
+        ws, n = batch.workspace("ipls")
+    else:
+        n = ws.numel()
+    p = batch.struct()
+    _check(lib().pss_ipls_iterate(ctypes.byref(p), _gamma_c(gamma), _ptr(y), int(n_iter),
+                                  _ptr(m_nom), _ptr(N_nom), _ptr(m_f), _ptr(N_f), _ptr(ws), n,
+                                  _stream()))
+    return (m_nom, N_nom, m_f, N_f) if want_filter else (m_nom, N_nom)
+
+
+def sequential_smoother(batch, y, n_iter, m_nom=None, N_nom=None, gamma=None, want_filter=False,
+                        ws=None):
+    _require_gpu()
+    if m_nom is None:
+        m_nom, N_nom = batch.prior_nominal()
+    m_f = N_f = None
+    if want_filter:
+        m_f, N_f = batch.new_marg()
+    if ws is None:
+        ws, n = batch.workspace("sequential")
+    else:
+        n = ws.numel()
+    p = batch.struct()
+    _check(lib().pss_sequential_smoother(ctypes.byref(p), _gamma_c(gamma), _ptr(y), int(n_iter),
+                                         _ptr(m_nom), _ptr(N_nom), _ptr(m_f), _ptr(N_f),
+                                         _ptr(ws), n, _stream()))
+    return (m_nom, N_nom, m_f, N_f) if want_filter else (m_nom, N_nom)
+
+
+def loglik(batch, y, m_nom=None, N_nom=None, gamma=None, ws=None):
+    """Pseudo-log-likelihood per sequence (float64 [B])."""
+    _require_gpu()
+    ll = torch.empty(batch.B, dtype=torch.float64, device=batch.device)
+    if ws is None:
+        ws, n = batch.workspace("loglik")
+    else:
+        n = ws.numel()
+    p = batch.struct()
+    _check(lib().pss_loglik(ctypes.byref(p), _gamma_c(gamma), _ptr(m_nom), _ptr(N_nom), _ptr(y),
+                            _ptr(ll), _ptr(ws), n, _stream()))
+    return ll
+
+
+def loglik_grad(batch, m_nom, N_nom, y, ll_bar=None, ws=None):
+    """(ll [B], grad [3, B], theta_bar [3]) at the frozen nominal."""
+    _require_gpu()
+    dev = batch.device
+    ll = torch.empty(batch.B, dtype=torch.float64, device=dev)
+    grad = torch.empty((3, batch.B), dtype=torch.float64, device=dev)
+    tb = torch.empty(3, dtype=torch.float64, device=dev)
+    if ws is None:
+        ws, n = batch.workspace("loglik_grad")
+    else:
+        n = ws.numel()
+    if ll_bar is not None:
+        ll_bar = ll_bar.to(device=dev, dtype=torch.float64).contiguous()
+    p = batch.struct()
+    _check(lib().pss_loglik_grad(ctypes.byref(p), _ptr(m_nom), _ptr(N_nom), _ptr(y),
+                                 _ptr(ll_bar), _ptr(ll), _ptr(grad), _ptr(tb), _ptr(ws), n,
+                                 _stream()))
+    return ll, grad, tb
+
+
+class LogLik(torch.autograd.Function):
+    """Pseudo-log-likelihood summed over the batch as a function of theta =
+    (log q1, log q2, log sigma) at a frozen nominal; backward runs the
+    library's gradient pass with the incoming cotangent."""
+
+    @staticmethod
+    def forward(ctx, theta, batch, y, m_nom, N_nom):
+        th = tuple(float(v) for v in theta.detach().cpu().tolist())
+        b2 = _with_theta(batch, th)
+        ll = loglik(b2, y, m_nom, N_nom)
+        ctx.save_for_backward(theta)
+        ctx.stuff = (b2, y, m_nom, N_nom)
+        return ll.sum().to(theta.dtype)
+
+    @staticmethod
+    def backward(ctx, g):
+        (theta,) = ctx.saved_tensors
+        b2, y, m_nom, N_nom = ctx.stuff
+        w = torch.full((b2.B,), 1.0, dtype=torch.float64, device=b2.device) * g.to(
+            device=b2.device, dtype=torch.float64)
+        _, _, tb = loglik_grad(b2, m_nom, N_nom, y, ll_bar=w)
+        return tb.to(device=theta.device, dtype=theta.dtype), None, None, None, None
+
+
+def _with_theta(batch, theta):
+    b = Batch.__new__(Batch)
+    b.__dict__.update(batch.__dict__)
+    b.theta = tuple(float(v) for v in theta)
+    return b

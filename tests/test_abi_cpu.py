@@ -1,0 +1,125 @@
+"""Host-side checks of the C ABI (no GPU, no compute calls).
+
+* libpss.so loads and exports every entry point include/pss.h declares;
+* pss_validate / pss_workspace_size reject malformed problems before any HIP
+  call, and the entry points return the documented status codes;
+* workspace sizes and the scan level plan behave as documented.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2207_00426_amd import pss
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_symbols():
+    src = open(os.path.join(ROOT, "include", "pss.h")).read()
+    decl = r"^(?:int|size_t|const char \*)\s*(pss_[a-z_]+)\s*\("
+    return sorted(set(re.findall(decl, src, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    return pss.lib()
+
+
+def test_library_exports_every_declared_symbol(L):
+    syms = _header_symbols()
+    assert len(syms) >= 10
+    for s in syms:
+        assert hasattr(L, s), s
+    assert set(pss.EXPORTS) == set(syms)
+    assert "gfx950" in pss.version()
+
+
+def _cpu_batch(**kw):
+    args = dict(model=pss.MODEL_LINEAR, dtype=torch.float64, nx=4, ny=2,
+                y_off=np.array([0, 10, 25]), m0=np.zeros(4), N0=np.eye(4), device="cpu")
+    args.update(kw)
+    return pss.Batch(**args)
+
+
+def test_validation_accepts_and_rejects(L):
+    assert pss.validate(_cpu_batch()) == 0
+    b = _cpu_batch()
+    b.y_off_host = np.array([0, 10, 10], dtype=np.int64)  # empty sequence
+    assert pss.validate(b) == -1
+    b = _cpu_batch()
+    b.y_off_host = np.array([1, 10, 25], dtype=np.int64)
+    assert pss.validate(b) == -1
+    assert pss.validate(_cpu_batch(nx=9, ny=2, m0=np.zeros(9), N0=np.eye(9))) == -1
+    assert pss.validate(_cpu_batch(nx=6, ny=2, m0=np.zeros(6), N0=np.eye(6))) == -2
+    assert pss.validate(_cpu_batch(model=pss.MODEL_CT)) == -1  # CT needs nx=5, ny=2
+    b = _cpu_batch(model=pss.MODEL_CT, nx=5, m0=np.zeros(5), N0=np.eye(5), dt=0.0)
+    assert pss.validate(b) == -1  # dt must be > 0
+    b = _cpu_batch(scan_threads=100)
+    assert pss.validate(b) == -1
+    assert "scan_threads" in pss.last_error()
+    b = _cpu_batch()
+    b.model = 7
+    assert pss.validate(b) == -1
+
+
+def test_null_arguments_rejected_before_any_hip_call(L):
+    b = _cpu_batch()
+    p = b.struct()
+    rc = L.pss_sqrt_filter_scan(ctypes.byref(p), None, None, None, None, 0, None)
+    assert rc == -1
+    rc = L.pss_slr_linearize(ctypes.byref(p), None, None, None, None, None)
+    assert rc == -2  # a linear model has no SLR
+    rc = L.pss_loglik_grad(ctypes.byref(p), None, None, None, None, None, None, None, None, 0,
+                           None)
+    assert rc == -2
+    assert L.pss_validate(None) == -1
+
+
+def test_workspace_sizes_and_too_small_workspace(L):
+    b = _cpu_batch()
+    for op in pss.OPS:
+        n = pss.workspace_size(b, op)
+        assert n >= 0 and n % 256 == 0
+    assert pss.workspace_size(b, "slr") == 0
+    big = _cpu_batch(y_off=np.array([0, 100000]))
+    assert pss.workspace_size(big, "ipls") > pss.workspace_size(b, "ipls")
+    # a workspace that is too small is refused with its own status
+    p = b.struct()
+    fe = pss.FElemC()
+    for k in ("A", "b", "U", "eta", "Z"):
+        setattr(fe, k, 8)  # non-null dummies; nothing is dereferenced
+    rc = L.pss_sqrt_filter_scan(ctypes.byref(p), ctypes.byref(fe), ctypes.c_void_p(8),
+                                ctypes.c_void_p(8), ctypes.c_void_p(8), 1, None)
+    assert rc == -3
+    assert "workspace" in pss.last_error()
+
+
+def test_scan_levels_grow_logarithmically(L):
+    # forcing tiny tiles makes the plan deeper; the workspace grows with it
+    small = _cpu_batch(y_off=np.array([0, 5000]), scan_threads=64, scan_elems=1)
+    large = _cpu_batch(y_off=np.array([0, 5000]), scan_threads=256, scan_elems=8)
+    assert pss.workspace_size(small, "filter_scan") > pss.workspace_size(large, "filter_scan")
+
+
+def test_layout_helpers_roundtrip():
+    rng = np.random.default_rng(0)
+    N = np.tril(rng.standard_normal((7, 5, 5)))
+    P = pss.pack_lower(N)
+    assert P.shape == (7, 15)
+    np.testing.assert_array_equal(pss.unpack_lower(P, 5), N)
+    t = pss.to_soa(N.reshape(7, 25), torch.float64, "cpu")
+    assert t.shape == (25, 7)
+    np.testing.assert_array_equal(pss.from_soa(t, (5, 5)), N)
+
+
+def test_compute_calls_refuse_without_gpu():
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    b = _cpu_batch()
+    with pytest.raises(RuntimeError):
+        pss.ipls_iterate(b, torch.zeros(2, 25, dtype=torch.float64), 1,
+                         gamma=b.new_gamma(0))
