@@ -1,22 +1,31 @@
 """Benchmark of the parallel square-root iterated smoother on one MI355X.
 
-Workload (default): coordinated-turn bearings-only tracking, one sequence of
-n = 1000 steps, 10 cubature IPLS passes (SLR, filter elements, filter scan,
-smoother scan), then the pseudo-log-likelihood and its gradient at the final
-nominal, in FP64.  One "step" is that whole hot path; the step is captured
-in a HIP graph and replayed.  Inputs are synthetic (seeded simulation) and
-resident in HBM before timing starts.
+Main workload: coordinated-turn bearings-only tracking, one long sequence of
+n = 10^6 steps (the long-sequence configuration), 10 cubature IPLS passes
+(SLR, filter elements, filter scan, smoother scan), then the
+pseudo-log-likelihood and its gradient at the final nominal, FP64.  One
+"step" is that whole hot path over the sequence, captured in a HIP graph and
+replayed; inputs are synthetic (seeded simulation) and already in HBM.
 
-The output is one JSON line.  value = smoothed time steps per second =
-n * passes / (seconds per step).  Beside it:
-  roofline     the dominant kernel (the filter-scan tile kernel) timed with
-               HIP events on its own stream, against the FP64 vector peak;
-               its work is the counted flops of the operators it executes;
-  cpu_baseline the FP64 oracle on the host for the same workload.
+value = smoothed time steps per second = n * passes / seconds per step.
+
+Also in the line (same run):
+  fp32            the same step in FP32
+  sequential      time per IPLS pass of the parallel scans vs the sequential
+                  square-root kernel (one thread walks the sequence) at
+                  n = 10^4 and 10^5 (prefixes of the same sequence)
+  loglik_grad_ms  one loglik + gradient evaluation on 64 CT sequences of
+                  10^4 steps (the parameter-estimation configuration)
+  roofline        the filter-scan launch group (the dominant work), timed
+                  with HIP events on its stream; work = counted flops of the
+                  operators it executes; bound = FP64 vector ALU
+  cpu_baseline    the FP64 oracle on the host, on a bounded prefix of the
+                  same sequence
 """
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -32,22 +41,20 @@ if ROOT not in sys.path:
 from paper_2207_00426_amd import pss  # noqa: E402
 from paper_2207_00426_amd import workloads as wl  # noqa: E402
 
-# Counted floating-point operations of the nx = 5, ny = 2 operators (one add,
-# multiply, divide or square root = 1, a fused multiply-add = 2), obtained by
+# Counted floating-point operations of the nx = 5, ny = 2 operators (add,
+# multiply, divide, square root = 1; fused multiply-add = 2), obtained by
 # instantiating the register code on a counting number type.
 FLOPS = dict(filter_combine=3328, filter_apply=2280, smoother_combine=730, smoother_apply=505,
              filter_element=1251, smoother_element=1502, slr_transition=937, slr_bearings=487)
-PEAK_FP64_TFLOPS = 78.6   # MI355X vector FP64
-PEAK_FP32_TFLOPS = 78.6   # vector FP32 without packed-FP32 instructions (kept off)
-PEAK_HBM_GBS = 8000.0
+PEAK = {"f64": 78.6, "f32": 78.6}  # TFLOP/s vector ALU (FP32 without packed instructions)
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=1000)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=10 ** 6)
     ap.add_argument("--passes", type=int, default=10)
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--scan-threads", type=int, default=0)
@@ -55,20 +62,121 @@ def parse():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="main line only (profiling)")
     return ap.parse_args()
 
 
-def scan_tile_flops(n, T, E):
-    """Counted flops of the filter-scan kernels for one sequence of n steps.
+def log(msg):
+    print("bench: " + msg, file=sys.stderr, flush=True)
 
-    Every element is folded once (E - 1 combines per thread plus the tree's
-    T - 1 combines per tile ~ one combine per element) and applied once, and
-    the down-sweep applies once per tree node.
-    """
-    tiles = -(-n // (T * E))
-    combines = n - tiles + (tiles - 1)  # thread folds + trees, levels >= 1 included
-    applies = n + n // max(E, 1)
-    return combines * FLOPS["filter_combine"] + applies * FLOPS["filter_apply"]
+
+def scan_plan(lengths, T0, E0, Tup, Eup):
+    """Mirror of the library's level plan: per level (T, E, elements, tiles)."""
+    cnt = np.asarray(lengths, dtype=np.int64)
+    levels = []
+    for l in range(8):
+        T, E = (T0, E0) if l == 0 else (Tup, Eup)
+        TS = T * E
+        tiles = -(-cnt // TS)
+        levels.append((T, E, int(cnt.sum()), int(tiles.sum())))
+        if cnt.max() <= TS:
+            break
+        cnt = tiles
+    return levels
+
+
+def filter_scan_flops(lengths, T0, E0, Tup, Eup):
+    """Counted flops of one filter scan: every element of every level is
+    folded once and applied once; each tile's tree adds about T combines and
+    T applies (its nodes)."""
+    tot = 0
+    for T, E, elems, tiles in scan_plan(lengths, T0, E0, Tup, Eup):
+        threads = -(-elems // E)
+        combines = elems - tiles
+        applies = elems + threads - tiles
+        tot += combines * FLOPS["filter_combine"] + applies * FLOPS["filter_apply"]
+    return tot
+
+
+def shapes(dtype, T_req, E_req):
+    T0 = T_req or (128 if dtype == "f64" else 256)
+    E0 = E_req or 4
+    Tup = min(T0, 128 if dtype == "f64" else 256)
+    return T0, E0, Tup, 2
+
+
+class Runner:
+    """Device-resident buffers and a captured step for one batch."""
+
+    def __init__(self, w, dtype, dev, stream, T=0, E=0, graph=True):
+        self.tdt = torch.float64 if dtype == "f64" else torch.float32
+        self.w = w
+        self.b = pss.Batch.ct(w.y_off, w.model, dtype=self.tdt, device=dev, scan_threads=T,
+                              scan_elems=E)
+        self.yd = pss.to_soa(w.y, self.tdt, dev)
+        self.m0, self.N0 = self.b.prior_nominal()
+        self.m, self.N = self.m0.clone(), self.N0.clone()
+        self.ws_ipls, _ = self.b.workspace("ipls")
+        self.ws_grad, _ = self.b.workspace("loglik_grad")
+        self.ws_ll, _ = self.b.workspace("loglik")
+        self.stream = stream
+        self.graph = None
+        self.want_graph = graph
+
+    def step(self):
+        self.m.copy_(self.m0)
+        self.N.copy_(self.N0)
+        pss.ipls_iterate(self.b, self.yd, self.w.M, self.m, self.N, ws=self.ws_ipls)
+        pss.loglik(self.b, self.yd, self.m, self.N, ws=self.ws_ll)
+        return pss.loglik_grad(self.b, self.m, self.N, self.yd, ws=self.ws_grad)
+
+    def prepare(self, warmup):
+        for _ in range(max(1, warmup)):
+            out = self.step()
+        torch.cuda.synchronize()
+        if self.want_graph:
+            self.graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(self.graph, stream=self.stream):
+                out = self.step()
+            for _ in range(2):  # replays agree with an eager run, bitwise
+                self.graph.replay()
+                torch.cuda.synchronize()
+                g_ll = out[0].clone()
+                e_ll = self.step()[0]
+                torch.cuda.synchronize()
+                # bitwise (NaN-safe) comparison
+                assert torch.equal(g_ll.view(torch.int64), e_ll.view(torch.int64)), \
+                    "graph replay differs from eager run"
+        return out
+
+    def run(self):
+        if self.graph is not None:
+            self.graph.replay()
+        else:
+            self.step()
+
+    def time_steps(self, steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(self.stream)
+        for _ in range(steps):
+            self.run()
+        e1.record(self.stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps, 1e3 * (time.perf_counter() - t0) / steps
+
+
+def timed(stream, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
 
 
 def main():
@@ -82,117 +190,144 @@ def main():
         sys.exit(2)
     dev = "cuda:0"
     torch.cuda.set_device(0)
-    tdt = torch.float64 if args.dtype == "f64" else torch.float32
-    n, M = args.n, args.passes
-    w = wl.ct_single(n, 1, M=M)
-    md = w.model
-    b = pss.Batch.ct(w.y_off, md, dtype=tdt, device=dev, scan_threads=args.scan_threads,
-                     scan_elems=args.scan_elems)
-    yd = pss.to_soa(w.y, tdt, dev)
-    m0, N0 = b.prior_nominal()
-    m, N = m0.clone(), N0.clone()
-    ws_ipls, _ = b.workspace("ipls")
-    ws_grad, _ = b.workspace("loglik_grad")
     stream = torch.cuda.Stream()
-
-    def step():
-        m.copy_(m0)
-        N.copy_(N0)
-        pss.ipls_iterate(b, yd, M, m, N, ws=ws_ipls)
-        return pss.loglik_grad(b, m, N, yd, ws=ws_grad)
-
-    print("bench: CT n=%d passes=%d %s, warmup %d, steps %d" % (n, M, args.dtype, args.warmup,
-                                                                 args.steps), file=sys.stderr,
-          flush=True)
+    n, M = args.n, args.passes
+    log("simulating CT n=%d" % n)
+    full = wl.ct_long(n, 2, M=M)
+    extras = {}
     with torch.cuda.stream(stream):
-        for _ in range(max(1, args.warmup)):
-            out = step()
-        torch.cuda.synchronize()
-        graph = None
-        if not args.no_graph:
-            graph = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(graph, stream=stream):
-                out = step()
-            graph.replay()
-            torch.cuda.synchronize()
-        run = graph.replay if graph is not None else step
-        # graph replays must equal eager results (checked once)
-        ll_g = out[0].clone()
-        if graph is not None:
-            ll_e = step()[0]
-            torch.cuda.synchronize()
-            assert torch.equal(ll_e, ll_g), "graph replay differs from eager run"
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ev0.record(stream)
-        for _ in range(args.steps):
-            run()
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        ms_step = ev0.elapsed_time(ev1) / args.steps
-        print("bench: %.3f ms/step (wall %.3f ms/step)" % (ms_step, 1e3 * wall / args.steps),
-              file=sys.stderr, flush=True)
-
-        # component timings (eager, events on the same stream)
-        def timed(fn, reps=10):
-            fn()
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(reps):
-                fn()
-            e1.record(stream)
-            torch.cuda.synchronize()
-            return e0.elapsed_time(e1) / reps
-
-        mi, Ni = m0.clone(), N0.clone()
-        t_ipls = timed(lambda: (mi.copy_(m0), Ni.copy_(N0),
-                                pss.ipls_iterate(b, yd, M, mi, Ni, ws=ws_ipls)))
-        t_grad = timed(lambda: pss.loglik_grad(b, m, N, yd, ws=ws_grad))
+        log("main: CT n=%d passes=%d %s" % (n, M, args.dtype))
+        R = Runner(full, args.dtype, dev, stream, args.scan_threads, args.scan_elems,
+                   graph=not args.no_graph)
+        out = R.prepare(args.warmup)
+        nan = int(torch.isnan(out[0]).sum().item())
+        ms_step, wall_step = R.time_steps(args.steps)
+        log("main: %.3f ms/step (wall %.3f)" % (ms_step, wall_step))
+        # stage timings on the final nominal
+        b, yd, m, N = R.b, R.yd, R.m, R.N
         gam = pss.slr_linearize(b, m, N, yd)
         fel = pss.sqrt_filter_elements(b, gam, yd)
         mf, Nf = b.new_marg()
         ws_f, nf = b.workspace("filter_scan")
-        t_fscan = timed(lambda: pss.lib().pss_sqrt_filter_scan(
-            pss.ctypes.byref(b.struct()), pss._felem_c(fel), pss._ptr(mf), pss._ptr(Nf),
-            pss._ptr(ws_f), nf, pss._stream()), reps=20)
-        t_slr = timed(lambda: pss.slr_linearize(b, m, N, yd, out=gam), reps=20)
-        t_fel = timed(lambda: pss.sqrt_filter_elements(b, gam, yd, out=fel), reps=20)
-        ms_s, Ns_s = b.new_marg()
-        t_sscan = timed(lambda: pss.sqrt_smoother_scan(b, gam, mf, Nf, ms_s, Ns_s), reps=20)
+        ws_s, ns = b.workspace("smoother_scan")
+        ms_, Ns_ = b.new_marg()
+        prob = b.struct()
+        L = pss.lib()
 
-    T0 = args.scan_threads or (128 if args.dtype == "f64" else 256)
-    E0 = args.scan_elems or 4
-    fl = scan_tile_flops(n, T0, E0)
-    achieved = fl / (t_fscan * 1e-3) / 1e12
-    peak = PEAK_FP64_TFLOPS if args.dtype == "f64" else PEAK_FP32_TFLOPS
-    value = n * M / (ms_step * 1e-3)
+        def fscan():
+            rc = L.pss_sqrt_filter_scan(ctypes.byref(prob), pss._felem_c(fel), pss._ptr(mf),
+                                        pss._ptr(Nf), pss._ptr(ws_f), nf, pss._stream())
+            assert rc == 0, pss.last_error()
+
+        def sscan():
+            rc = L.pss_sqrt_smoother_scan(ctypes.byref(prob), pss._gamma_c(gam), pss._ptr(mf),
+                                          pss._ptr(Nf), pss._ptr(ms_), pss._ptr(Ns_),
+                                          pss._ptr(ws_s), ns, pss._stream())
+            assert rc == 0, pss.last_error()
+
+        reps = 5 if n >= 10 ** 5 else 20
+        stage = {
+            "slr": timed(stream, lambda: pss.slr_linearize(b, m, N, yd, out=gam), reps),
+            "filter_elements": timed(stream, lambda: pss.sqrt_filter_elements(b, gam, yd, out=fel),
+                                     reps),
+            "filter_scan": timed(stream, fscan, reps),
+            "smoother_scan": timed(stream, sscan, reps),
+            "loglik_grad": timed(stream, lambda: pss.loglik_grad(b, m, N, yd, ws=R.ws_grad), reps),
+        }
+        log("stages (ms): " + ", ".join("%s %.3f" % kv for kv in stage.items()))
+        T0, E0, Tup, Eup = shapes(args.dtype, args.scan_threads, args.scan_elems)
+        fl = filter_scan_flops([n], T0, E0, Tup, Eup)
+        achieved = fl / (stage["filter_scan"] * 1e-3) / 1e12
+        del R, gam, fel, mf, Nf, ms_, Ns_, ws_f, ws_s
+        torch.cuda.empty_cache()
+
+        if not args.no_extras:
+            # FP32 of the same step
+            other = "f32" if args.dtype == "f64" else "f64"
+            R2 = Runner(full, other, dev, stream, graph=not args.no_graph)
+            out2 = R2.prepare(1)
+            ms2, _ = R2.time_steps(max(2, args.steps // 2))
+            extras[other] = {"ms_per_step": round(ms2, 4),
+                             "value": round(n * M / (ms2 * 1e-3), 1),
+                             "nan_loglik": int(torch.isnan(out2[0]).sum().item())}
+            log("%s: %.3f ms/step" % (other, ms2))
+            del R2
+            torch.cuda.empty_cache()
+            # parallel vs sequential square-root kernel, per IPLS pass
+            seq = {}
+            for nn in (10 ** 4, 10 ** 5):
+                if nn > n:
+                    continue
+                wsub = wl.Workload("prefix", full.model, full.y[:nn], np.array([0, nn]),
+                                   np.ones(1, np.int64), [], M=M)
+                for dt in ("f64", "f32"):
+                    tdt = torch.float64 if dt == "f64" else torch.float32
+                    bb = pss.Batch.ct(wsub.y_off, full.model, dtype=tdt, device=dev)
+                    yy = pss.to_soa(wsub.y, tdt, dev)
+                    m0, N0 = bb.prior_nominal()
+                    mm, NN = m0.clone(), N0.clone()
+                    wi, _ = bb.workspace("ipls")
+                    wsq, _ = bb.workspace("sequential")
+                    t_par = timed(stream, lambda: (mm.copy_(m0), NN.copy_(N0),
+                                                   pss.ipls_iterate(bb, yy, 1, mm, NN, ws=wi)), 5)
+                    t_seq = timed(stream, lambda: (mm.copy_(m0), NN.copy_(N0),
+                                                   pss.sequential_smoother(bb, yy, 1, mm, NN,
+                                                                           ws=wsq)),
+                                  1 if nn >= 10 ** 5 else 3)
+                    seq["n%d_%s" % (nn, dt)] = {"parallel_ms_per_pass": round(t_par, 4),
+                                                "sequential_ms_per_pass": round(t_seq, 4),
+                                                "speedup": round(t_seq / t_par, 2)}
+                    log("n=%d %s: parallel %.3f ms/pass, sequential %.3f ms/pass" % (nn, dt, t_par,
+                                                                                   t_seq))
+            extras["sequential"] = seq
+            # parameter-estimation configuration: loglik + gradient, 64 x 10^4
+            log("simulating CT 64 x 10^4")
+            wb = wl.ct_batch(64, 10 ** 4, 4, M=M)
+            lg = {}
+            for dt in ("f64", "f32"):
+                tdt = torch.float64 if dt == "f64" else torch.float32
+                bb = pss.Batch.ct(wb.y_off, wb.model, dtype=tdt, device=dev)
+                yy = pss.to_soa(wb.y, tdt, dev)
+                mm, NN = pss.ipls_iterate(bb, yy, M)
+                wg, _ = bb.workspace("loglik_grad")
+                wl_, _ = bb.workspace("loglik")
+                t_g = timed(stream, lambda: (pss.loglik(bb, yy, mm, NN, ws=wl_),
+                                             pss.loglik_grad(bb, mm, NN, yy, ws=wg)), 10)
+                wi, _ = bb.workspace("ipls")
+                m0, N0 = bb.prior_nominal()
+                t_i = timed(stream, lambda: (mm.copy_(m0), NN.copy_(N0),
+                                             pss.ipls_iterate(bb, yy, M, mm, NN, ws=wi)), 3)
+                lg[dt] = {"loglik_plus_grad_ms": round(t_g, 4), "ipls_ms": round(t_i, 4)}
+                log("64x1e4 %s: loglik+grad %.3f ms, IPLS %.3f ms" % (dt, t_g, t_i))
+            extras["param_estimation_64x1e4"] = lg
 
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
         oracle.build(force=False)
         prm = oracle.ct_params()
+        ns = min(n, 100000)
+        log("cpu baseline: oracle on the first %d steps" % ns)
         t0 = time.perf_counter()
         reps = 0
         while True:
-            r = oracle.ct_ipls(prm, md.m0, np.eye(5), w.y, M)
-            oracle.ct_score(prm, md.m0, np.eye(5), w.y, r["ms"], r["Ns"])
+            r = oracle.ct_ipls(prm, full.model.m0, np.eye(5), full.y[:ns], M)
+            oracle.ct_loglik(prm, full.model.m0, np.eye(5), full.y[:ns], r["ms"], r["Ns"])
+            oracle.ct_score(prm, full.model.m0, np.eye(5), full.y[:ns], r["ms"], r["Ns"])
             reps += 1
             if time.perf_counter() - t0 > args.cpu_seconds:
                 break
         dt_cpu = (time.perf_counter() - t0) / reps
-        cpu = {"value": n * M / dt_cpu, "unit": "smoothed time steps/s", "cores": 1,
+        cpu = {"value": round(ns * M / dt_cpu, 1), "unit": "smoothed time steps/s", "cores": 1,
                "kind": "oracle",
-               "sample": "%d repeats of the whole step (IPLS %d passes + loglik + score) on "
-                         "the same CT n=%d sequence, FP64, sequential in k on one core"
-                         % (reps, M, n)}
+               "sample": "first %d steps of the same sequence, %d repeat(s) of the whole step "
+                         "(IPLS %d passes + loglik + score), FP64, sequential in k, one core"
+                         % (ns, reps, M)}
 
+    peak = PEAK[args.dtype]
     line = {
         "metric": "smoothed time steps/s (sqrt filter+smoother scan) nx=5; loglik+grad ms",
-        "value": round(value, 1),
+        "value": round(n * M / (ms_step * 1e-3), 1),
         "unit": "smoothed time steps/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -203,18 +338,20 @@ def main():
         "vs_baseline": None,
         "dtype": args.dtype,
         "data": "synthetic (seeded CT bearings-only simulation)",
-        "config": {"workload": "ct_bearings_n%d_M%d_cubature" % (n, M), "B": 1, "n": n,
-                   "passes": M, "nx": 5, "ny": 2, "graph": graph is not None,
+        "config": {"workload": "ct_bearings_long_n%d_M%d_cubature" % (n, M), "B": 1, "n": n,
+                   "passes": M, "nx": 5, "ny": 2, "graph": not args.no_graph,
                    "scan_threads": T0, "scan_elems": E0},
-        "loglik_grad_ms": round(t_grad, 4),
-        "ipls_ms": round(t_ipls, 4),
-        "stage_ms": {"slr": round(t_slr, 4), "filter_elements": round(t_fel, 4),
-                     "filter_scan": round(t_fscan, 4), "smoother_scan": round(t_sscan, 4)},
-        "roofline": {"bound": "alu", "kernel": "filter scan (k_plan + k_scan_* tiles)",
+        "loglik_grad_ms": extras.get("param_estimation_64x1e4", {}).get(args.dtype, {}).get(
+            "loglik_plus_grad_ms"),
+        "nan_loglik": nan,
+        "stage_ms": {k: round(v, 4) for k, v in stage.items()},
+        "roofline": {"bound": "alu", "kernel": "filter scan launch group "
+                     "(k_plan, k_scan_up, k_scan_top, k_scan_down)",
                      "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 6), "traffic": None,
-                     "flops_per_launch": fl},
+                     "flops_per_launch": int(fl)},
         "cpu_baseline": cpu,
+        "extras": extras,
     }
     print(json.dumps(line), flush=True)
 
