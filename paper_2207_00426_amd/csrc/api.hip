@@ -109,12 +109,46 @@ int launch_plan(const Ctx &c, const ScanShape &sh, int extra, int64_t *const *ti
     return hip_check(hipGetLastError(), "plan launch");
 }
 
-int launch_seq_sum(const Ctx &c, int nc, const double *terms, int64_t ld, double *out)
+static int64_t seq_chunks(const Ctx &c)
 {
-    if (nc == 1)
-        hipLaunchKernelGGL(k_seq_sum<1>, dim3(c.B), dim3(256), 0, c.s, c.p->y_off, terms, ld, out);
-    else
-        hipLaunchKernelGGL(k_seq_sum<3>, dim3(c.B), dim3(256), 0, c.s, c.p->y_off, terms, ld, out);
+    int64_t tot = 0;
+    for (int b = 0; b < c.B; ++b)
+        tot += (c.p->y_off_host[b + 1] - c.p->y_off_host[b] + kSumChunk - 1) / kSumChunk;
+    return tot;
+}
+
+size_t seq_sum_bytes(const Ctx &c, int nc)
+{
+    Carver cv{nullptr};
+    cv.take<int64_t>(c.B + 1);
+    cv.take<double>((size_t)nc * seq_chunks(c));
+    return cv.used;
+}
+
+int launch_seq_sum(const Ctx &c, int nc, const double *terms, int64_t ld, double *out, void *ws)
+{
+    Carver cv{static_cast<char *>(ws)};
+    int64_t *chunk_off = cv.take<int64_t>(c.B + 1);
+    const int64_t nch = seq_chunks(c);
+    double *partial = cv.take<double>((size_t)nc * nch);
+    ScanShape sh;
+    sh.L = 1;
+    sh.T[0] = kSumChunk;
+    sh.E[0] = 1;
+    int rc = launch_plan(c, sh, 0, &chunk_off);
+    if (rc)
+        return rc;
+    if (nc == 1) {
+        hipLaunchKernelGGL(k_chunk_sum<1>, dim3((unsigned)nch), dim3(256), 0, c.s, c.p->y_off,
+                           chunk_off, c.B, terms, ld, partial, nch);
+        hipLaunchKernelGGL(k_seq_total<1>, dim3((c.B + 63) / 64), dim3(64), 0, c.s, chunk_off,
+                           partial, nch, c.B, out);
+    } else {
+        hipLaunchKernelGGL(k_chunk_sum<3>, dim3((unsigned)nch), dim3(256), 0, c.s, c.p->y_off,
+                           chunk_off, c.B, terms, ld, partial, nch);
+        hipLaunchKernelGGL(k_seq_total<3>, dim3((c.B + 63) / 64), dim3(64), 0, c.s, chunk_off,
+                           partial, nch, c.B, out);
+    }
     return hip_check(hipGetLastError(), "sequence sum launch");
 }
 

@@ -49,7 +49,10 @@ struct ScanShape {
 
 ScanShape plan_scan(const Ctx &c, int extra, int T0, int E0, int Tup, int Eup);
 int launch_plan(const Ctx &c, const ScanShape &sh, int extra, int64_t *const *tile_off);
-int launch_seq_sum(const Ctx &c, int nc, const double *terms, int64_t ld, double *out);
+// per-sequence sums of step terms (two deterministic stages); the workspace
+// part (seq_sum_bytes) comes from the caller
+size_t seq_sum_bytes(const Ctx &c, int nc);
+int launch_seq_sum(const Ctx &c, int nc, const double *terms, int64_t ld, double *out, void *ws);
 int launch_weighted_grad(const Ctx &c, const double *grad, const double *w, double *theta_bar);
 
 // coordinated-turn constants from the problem (host, double precision)

@@ -2,6 +2,8 @@
 // per-(dtype, nx, ny) implementations behind the C ABI.
 #pragma once
 
+#include <algorithm>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -349,12 +351,14 @@ struct Core {
         case PSS_OP_IPLS:
             return gamma_bytes(c) + felem_bytes(c) + marg_bytes(c) + scans;
         case PSS_OP_LOGLIK:
-            return gamma_bytes(c) + felem_bytes(c) + marg_bytes(c) + fscan_bytes(c) +
-                   align256(c.T_y * sizeof(double));
+            return gamma_bytes(c) + felem_bytes(c) + marg_bytes(c) +
+                   align256(c.T_y * sizeof(double)) +
+                   std::max(fscan_bytes(c), seq_sum_bytes(c, 1));
         case PSS_OP_LOGLIK_GRAD:
             return gamma_bytes(c) + felem_bytes(c) + marg_bytes(c) +
-                   align256(c.T_y * sizeof(double)) + scans + marg_bytes(c) +
-                   align256(3 * c.T_y * sizeof(double)) + align256(3 * c.B * sizeof(double));
+                   align256(c.T_y * sizeof(double)) + std::max(scans, seq_sum_bytes(c, 3)) +
+                   marg_bytes(c) + align256(3 * c.T_y * sizeof(double)) +
+                   align256(3 * c.B * sizeof(double));
         case PSS_OP_SEQUENTIAL:
             return gamma_bytes(c) + marg_bytes(c);
         default:
@@ -417,7 +421,7 @@ struct Core {
                            marg_ref(mfb, c.T_x), ell);
         if ((rc = hip_check(hipGetLastError(), "loglik launch")))
             return rc;
-        return launch_seq_sum(c, 1, ell, c.T_y, ll);
+        return launch_seq_sum(c, 1, ell, c.T_y, ll, scan_ws);
     }
 
     static int loglik(const Ctx &c, const pss_gamma *gin, const void *m_nom, const void *N_nom,
@@ -440,8 +444,8 @@ struct Core {
         pss_gamma gw;
         T *mfb;
         void *scan_ws;
-        const size_t scans =
-            fscan_bytes(c) > sscan_bytes(c) ? fscan_bytes(c) : sscan_bytes(c);
+        const size_t scans = std::max(std::max(fscan_bytes(c), sscan_bytes(c)),
+                                      seq_sum_bytes(c, 3));
         Carver tail{static_cast<char *>(ws) + gamma_bytes(c) + felem_bytes(c) + marg_bytes(c) +
                     align256(c.T_y * sizeof(double)) + scans};
         T *msb = tail.template take<T>((size_t)Sizes<NX>::marg * c.T_x);
@@ -458,7 +462,7 @@ struct Core {
             return rc;
         double *gout = grad ? grad : gseq;
         // per-sequence sums land component-major [3][B]
-        if ((rc = launch_seq_sum(c, 3, gterms, c.T_y, gout)))
+        if ((rc = launch_seq_sum(c, 3, gterms, c.T_y, gout, scan_ws)))
             return rc;
         if (theta_bar)
             rc = launch_weighted_grad(c, gout, ll_bar, theta_bar);

@@ -674,18 +674,30 @@ __global__ __launch_bounds__(128) void k_loglik_terms(const int64_t *y_off, int 
     ell[t] = l;
 }
 
-// deterministic per-sequence sums: fixed per-thread strides then a fixed tree
+// Deterministic per-sequence sums in two stages.  Stage 1: one block per
+// chunk of kSumChunk consecutive step slots of ONE sequence (chunk offsets
+// from the tile plan with tile size kSumChunk); fixed thread strides, then a
+// fixed LDS tree.  Stage 2: one block per sequence adds its chunk partials in
+// order.  The bracketing depends only on the sequence lengths.
+constexpr int kSumChunk = 8192;
+
 template <int NC>
-__global__ __launch_bounds__(256) void k_seq_sum(const int64_t *y_off, const double *terms,
-                                                 int64_t ld, double *out)
+__global__ __launch_bounds__(256) void k_chunk_sum(const int64_t *y_off, const int64_t *chunk_off,
+                                                   int B, const double *terms, int64_t ld,
+                                                   double *partial, int64_t nchunks)
 {
     __shared__ double red[NC][256];
-    const int b = blockIdx.x;
-    const int64_t a = y_off[b], z = y_off[b + 1];
+    const int64_t ch = blockIdx.x;
+    const int b = find_seq(chunk_off, B, ch, 0);
+    const int64_t a = y_off[b] + (ch - chunk_off[b]) * kSumChunk;
+    int64_t z = a + kSumChunk;
+    if (z > y_off[b + 1])
+        z = y_off[b + 1];
     double s[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c)
         s[c] = 0.0;
+#pragma unroll 8
     for (int64_t t = a + threadIdx.x; t < z; t += blockDim.x)
 #pragma unroll
         for (int c = 0; c < NC; ++c)
@@ -703,7 +715,23 @@ __global__ __launch_bounds__(256) void k_seq_sum(const int64_t *y_off, const dou
     if (threadIdx.x == 0)
 #pragma unroll
         for (int c = 0; c < NC; ++c)
-            out[c * (int64_t)gridDim.x + b] = red[c][0];
+            partial[c * nchunks + ch] = red[c][0];
+}
+
+template <int NC>
+__global__ __launch_bounds__(64) void k_seq_total(const int64_t *chunk_off, const double *partial,
+                                                  int64_t nchunks, int B, double *out)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B)
+        return;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        double s = 0.0;
+        for (int64_t k = chunk_off[b]; k < chunk_off[b + 1]; ++k)
+            s += partial[c * nchunks + k];
+        out[(int64_t)c * B + b] = s;
+    }
 }
 
 // theta_bar[c] = sum_b w[b] grad[c][b] in a fixed order (one block)
