@@ -43,8 +43,22 @@ PSS_INL float pfma(float a, float b, float c) { return fmaf(a, b, c); }
 //
 // The reflector uses the cancellation-free form of the pivot update
 // (v0 = -sigma / (alpha + |x|) when alpha > 0), so the new diagonal is
-// +|x| without a sign fix-up; an all-zero row is left untouched.
+// +|x| without a sign fix-up.  Each row is first scaled by its largest
+// magnitude, so squares neither overflow nor fall into the subnormal range
+// (in FP32 a tail of norm^2 ~ 1e-39 would otherwise give tau = 2/vv = inf);
+// a tail below machine epsilon relative to a positive pivot is left alone
+// (its reflection is the identity to working precision), and an all-zero row
+// is untouched.
 // --------------------------------------------------------------------------
+template <typename T> struct Eps;
+template <> struct Eps<double> { static constexpr double v = 2.220446049250313e-16; };
+template <> struct Eps<float> { static constexpr float v = 1.1920929e-07f; };
+
+PSS_INL double pabs(double x) { return fabs(x); }
+PSS_INL float pabs(float x) { return fabsf(x); }
+PSS_INL double pmax(double a, double b) { return fmax(a, b); }
+PSS_INL float pmax(float a, float b) { return fmaxf(a, b); }
+
 template <int K, int Z0, typename T, int R, int C>
 PSS_INL void lq_rows(T (&A)[R][C])
 {
@@ -52,15 +66,23 @@ PSS_INL void lq_rows(T (&A)[R][C])
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         const int jend = cmin(C, Z0 + i + 1);
-        T sig = T(0);
+        T sc = pabs(A[i][i]);
 #pragma unroll
         for (int j = i + 1; j < jend; ++j)
+            sc = pmax(sc, pabs(A[i][j]));
+        const T inv = (sc > T(0)) ? T(1) / sc : T(0);
+        T sig = T(0);
+#pragma unroll
+        for (int j = i + 1; j < jend; ++j) {
+            A[i][j] *= inv; // row i now holds the scaled reflector tail
             sig = pfma(A[i][j], A[i][j], sig);
-        const T al = A[i][i];
+        }
+        const T al = A[i][i] * inv;
         const T nr = psqrt(pfma(al, al, sig));
         const T v0 = (al > T(0)) ? -sig / (al + nr) : (al - nr);
         const T vv = pfma(v0, v0, sig);
-        const T tau = (vv > T(0)) ? T(2) / vv : T(0);
+        const bool skip = !(vv > T(0)) || (al > T(0) && sig <= Eps<T>::v * Eps<T>::v);
+        const T tau = skip ? T(0) : T(2) / vv;
 #pragma unroll
         for (int r = i + 1; r < R; ++r) {
             T w = A[r][i] * v0;
@@ -73,7 +95,7 @@ PSS_INL void lq_rows(T (&A)[R][C])
             for (int j = i + 1; j < jend; ++j)
                 A[r][j] = pfma(-tw, A[i][j], A[r][j]);
         }
-        A[i][i] = nr;
+        A[i][i] = (skip && al > T(0)) ? sc * al : nr * sc;
     }
 }
 
