@@ -206,6 +206,50 @@ int pss_sequential_smoother(const pss_problem *p, const pss_gamma *g, const void
                             int32_t n_iter, void *m_nom, void *N_nom, void *m_f, void *N_f,
                             void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* ---- ragged batches of several model groups in one persistent launch ---- */
+
+/* One model group of a batched call: a ragged batch of sequences of one
+   model.  Supported groups: PSS_MODEL_CT_BEARINGS (nx 5, ny 2) and
+   PSS_MODEL_LINEAR with nx 4, ny 2 (e.g. constant velocity).  All groups of a
+   call share the dtype and the launch-shape overrides. */
+typedef struct pss_group {
+    const pss_problem *p;  /* model, dimensions, batch offsets, prior        */
+    const pss_gamma *g;    /* linear: its parameters (stride 0/1); CT: NULL  */
+    const void *y;         /* [ny][T_y] measurements                         */
+    void *m_nom, *N_nom;   /* in: initial nominal; out: after n_iter passes */
+} pss_group;
+
+/* Workspace bytes of pss_ipls_batched for these groups (0 if invalid). */
+size_t pss_batched_workspace_size(const pss_group *groups, int32_t n_groups);
+
+/* Algorithm 3 for up to 4 groups of ragged sequences, each pass ONE
+   persistent kernel launch (plus a flag-clearing kernel): a work queue of
+   filter tiles then smoother tiles of every sequence of every group; a tile
+   fuses the SLR of Section 4.3 (CT), the elements of Lemma 1 / Table 4, the
+   sequential fold, the in-LDS tree and the down-sweep, and chains with its
+   neighbour tile (inclusive prefix of tile t = prefix of tile t-1 (x) tile
+   aggregate).  Waits only target earlier queue items, are bounded, and set
+   bit flags in `status` (device int, nullable; 0 = ok) if a bound is hit.
+   Launch shape: the problem's overrides, else the autotuned shape for this
+   batch signature (pss_autotune, or the file named by the environment
+   variable PSS_TUNE_CACHE), else defaults.  Bitwise reproducible for a
+   given shape.  The pass sequence can be captured in a HIP graph. */
+int pss_ipls_batched(const pss_group *groups, int32_t n_groups, int32_t n_iter, int32_t *status,
+                     void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Workspace bytes of pss_autotune. */
+size_t pss_autotune_workspace_size(const pss_group *groups, int32_t n_groups);
+
+/* Autotuner: times one batched pass for each candidate launch shape (block
+   threads 64/128/256, filter and smoother elements per thread 1..8) on the
+   caller's data (the nominal is copied, not modified), keeps the fastest for
+   this batch signature (dtype, models, batch sizes, log2 of total steps) in a
+   host cache used by pss_ipls_batched, and writes the cache to
+   cache_path_host if not NULL.  best_host (nullable, 3 ints) receives
+   (threads, filter elements, smoother elements).  Synchronises the stream. */
+int pss_autotune(const pss_group *groups, int32_t n_groups, void *ws, size_t ws_bytes,
+                 const char *cache_path_host, int32_t *best_host, hipStream_t stream);
+
 /* Validation only: returns the status the entry points would return for
    this problem before enqueuing work (no HIP call is made). */
 int pss_validate(const pss_problem *p);

@@ -1,0 +1,434 @@
+// Persistent, work-queue form of one IPLS pass for ragged batches of several
+// model groups in ONE launch (gfx950).
+//
+// Work items are (group, sequence, tile) triples handed out in a fixed order
+// by one atomic counter: first every filter tile of every group, sequences in
+// order, tiles in time order; then every smoother tile, tiles in reverse time
+// order.  A filter tile builds its elements on the fly (SLR at the previous
+// nominal for the CT model, then Lemma 1), folds them, runs the in-LDS
+// up-sweep, then chains with its predecessor: it waits for tile t-1's
+// published inclusive prefix (a filtering marginal), publishes its own
+// inclusive prefix = prefix(t-1) (x) aggregate(t), and finishes with the
+// down-sweep and the apply pass.  Smoother tiles mirror this backwards in
+// time, after waiting for the filter tiles whose marginals and transition
+// parameters they read.  Every wait is on an item with a SMALLER index, so
+// the lowest unfinished item never waits and the queue always drains; waits
+// are bounded and raise an error flag instead of spinning forever.
+// The bracketing inside and across tiles depends only on the sequence
+// lengths and launch shape, so results are bitwise reproducible.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace pss {
+
+constexpr int kMaxGroups = 4;
+constexpr int kGroupCT = 1;      // coordinated-turn bearings, nx 5, ny 2
+constexpr int kGroupLinear4 = 2; // linear model, nx 4, ny 2
+
+template <typename T>
+struct PGroup {
+    int kind;
+    int B;
+    int E_f, E_s;
+    const int64_t *y_off;
+    int64_t T_y, T_x;
+    const T *y;
+    const T *m0, *N0;
+    // nominal trajectory: read from *_in, smoothing marginals written to *_out
+    const T *nom_in_m, *nom_in_N;
+    T *nom_out_m, *nom_out_N;
+    // workspace
+    T *mf, *Nf;            // filtering marginals [P_marg][T_x]
+    T *fstash;             // filter elements [NE_f][T_y]
+    T *gstash;             // transition linearisation [NX^2 + NX + P][T_y]
+    T *sstash;             // smoother elements [NE_s][T_x]
+    T *pre_f, *pre_s;      // published inclusive prefixes / suffixes [P_marg][tiles]
+    int *flag_f, *done_f;  // per filter tile: prefix published, outputs written
+    int *flag_s;           // per smoother tile: suffix published
+    const int64_t *tile_f, *tile_s; // per-sequence tile offsets [B+1]
+    int64_t item_f0, item_s0;       // first global item of this group's phases
+    int64_t ntiles_f, ntiles_s;
+    // linear model parameters (kind == kGroupLinear4)
+    const T *gF, *gc, *gSL, *gH, *gd, *gSO;
+    int64_t gstride;
+    // CT model constants (kind == kGroupCT)
+    CTParams<T> ct;
+};
+
+template <typename T>
+struct PArgs {
+    PGroup<T> g[kMaxGroups];
+    int n_groups;
+    int64_t total_items;
+    int *counter;   // work counter (reset before each pass)
+    int *error;     // set if a wait exceeded its bound
+    int spin_limit; // bounded waits
+};
+
+// ---- synchronisation helpers (vector atomics on global memory) ------------
+PSS_INL int flag_load(int *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+PSS_INL void flag_store(int *p, int v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+// thread 0 waits until *p != 0 (bounded); returns false on timeout
+PSS_INL bool wait_flag(int *p, int limit)
+{
+    for (int it = 0; it < limit; ++it) {
+        if (flag_load(p) != 0)
+            return true;
+        __builtin_amdgcn_s_sleep(4);
+    }
+    return false;
+}
+
+template <typename T, int NX>
+PSS_INL MargRef<T, NX> pre_ref(T *base, int64_t ld)
+{
+    MargRef<T, NX> r;
+    r.ld = ld;
+    r.m = base;
+    r.N = base + (int64_t)NX * ld;
+    return r;
+}
+
+template <typename T, int NX>
+PSS_INL FElemRef<T, NX> felem_ref_dev(T *base, int64_t ld)
+{
+    FElemRef<T, NX> r;
+    r.ld = ld;
+    r.A = base;
+    r.b = r.A + (int64_t)NX * NX * ld;
+    r.U = r.b + (int64_t)NX * ld;
+    r.eta = r.U + (int64_t)tri_size(NX) * ld;
+    r.Z = r.eta + (int64_t)NX * ld;
+    return r;
+}
+
+template <typename T, int NX>
+PSS_INL SElemRef<T, NX> selem_ref_dev(T *base, int64_t ld)
+{
+    SElemRef<T, NX> r;
+    r.ld = ld;
+    r.E = base;
+    r.g = r.E + (int64_t)NX * NX * ld;
+    r.D = r.g + (int64_t)NX * ld;
+    return r;
+}
+
+// transition part of a linearisation, stashed per step slot by filter tiles
+template <typename T, int NX>
+struct TransRef {
+    T *F, *c, *SL;
+    int64_t ld;
+    PSS_INL void store(int64_t t, const T (&Fm)[NX][NX], const T (&cv)[NX],
+                       const T (&S)[NX][NX]) const
+    {
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+#pragma unroll
+            for (int j = 0; j < NX; ++j)
+                F[(i * NX + j) * ld + t] = Fm[i][j];
+            c[i * ld + t] = cv[i];
+#pragma unroll
+            for (int j = 0; j <= i; ++j)
+                SL[tri_idx(i, j) * ld + t] = S[i][j];
+        }
+    }
+    PSS_INL void load(int64_t t, T (&Fm)[NX][NX], T (&cv)[NX], T (&S)[NX][NX]) const
+    {
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+#pragma unroll
+            for (int j = 0; j < NX; ++j)
+                Fm[i][j] = F[(i * NX + j) * ld + t];
+            cv[i] = c[i * ld + t];
+#pragma unroll
+            for (int j = 0; j <= i; ++j)
+                S[i][j] = SL[tri_idx(i, j) * ld + t];
+        }
+    }
+};
+
+template <typename T, int NX>
+PSS_INL TransRef<T, NX> trans_ref_dev(T *base, int64_t ld)
+{
+    TransRef<T, NX> r;
+    r.ld = ld;
+    r.F = base;
+    r.c = r.F + (int64_t)NX * NX * ld;
+    r.SL = r.c + (int64_t)NX * ld;
+    return r;
+}
+
+// ---- element sources of the fused pass ------------------------------------
+// filter: element of step position p (slot off + p) built from the model
+template <typename T, int NX, int NY, bool CT>
+struct FusedFiltSrc {
+    const PGroup<T> *G;
+    int64_t x0; // first state slot of the sequence
+    PSS_INL void up(int b, int64_t off, int64_t cnt, int64_t p, FElem<T, NX> &e) const
+    {
+        const int64_t s = off + p;
+        T F[NX][NX], c[NX], SL[NX][NX], H[NY][NX], d[NY], SO[NY][NY], yy[NY];
+#pragma unroll
+        for (int a = 0; a < NY; ++a)
+            yy[a] = G->y[a * G->T_y + s];
+        if constexpr (CT) {
+            MargRef<T, NX> nom;
+            nom.m = const_cast<T *>(G->nom_in_m);
+            nom.N = const_cast<T *>(G->nom_in_N);
+            nom.ld = G->T_x;
+            Marg<T, NX> prev, cur;
+            nom.load(x0 + p, prev);
+            nom.load(x0 + p + 1, cur);
+            ct_slr_transition(G->ct, prev, F, c, SL);
+            ct_slr_bearings(G->ct, cur, yy, H, d, SO);
+            trans_ref_dev<T, NX>(G->gstash, G->T_y).store(s, F, c, SL);
+        } else {
+            GammaRef<T, NX, NY> gr;
+            gr.F = const_cast<T *>(G->gF);
+            gr.c = const_cast<T *>(G->gc);
+            gr.SL = const_cast<T *>(G->gSL);
+            gr.H = const_cast<T *>(G->gH);
+            gr.d = const_cast<T *>(G->gd);
+            gr.SO = const_cast<T *>(G->gSO);
+            gr.stride = G->gstride;
+            gr.ld = G->gstride ? G->T_y : 1;
+            gr.load_trans(s, F, c, SL);
+            gr.load_obs(s, H, d, SO);
+        }
+        if (p == 0) {
+            T m[NX], N[NX][NX];
+#pragma unroll
+            for (int i = 0; i < NX; ++i) {
+                m[i] = G->m0[i];
+#pragma unroll
+                for (int j = 0; j <= i; ++j)
+                    N[i][j] = G->N0[tri_idx(i, j)];
+            }
+            filter_element_first(m, N, F, c, SL, H, d, SO, yy, e);
+        } else {
+            filter_element(F, c, SL, H, d, SO, yy, e);
+        }
+        felem_ref_dev<T, NX>(G->fstash, G->T_y).store(s, e);
+    }
+    PSS_INL void down(int b, int64_t off, int64_t cnt, int64_t p, FElem<T, NX> &e) const
+    {
+        felem_ref_dev<T, NX>(G->fstash, G->T_y).load(off + p, e);
+    }
+};
+
+// smoother: element of state k = n - p (Table 4) from the stashed transition
+// parameters (CT) or the model (linear) and the filtering marginal
+template <typename T, int NX, int NY, bool CT>
+struct FusedSmoothSrc {
+    const PGroup<T> *G;
+    int64_t ybase; // y_off[b]
+    PSS_INL void up(int b, int64_t off, int64_t cnt, int64_t p, SElem<T, NX> &e) const
+    {
+        const int64_t n = cnt - 1, k = n - p;
+        Marg<T, NX> f;
+        pre_ref<T, NX>(G->mf, G->T_x).load(off + k, f);
+        if (k == n) {
+            smoother_element_last(f, e);
+        } else {
+            T F[NX][NX], c[NX], SL[NX][NX];
+            if constexpr (CT) {
+                trans_ref_dev<T, NX>(G->gstash, G->T_y).load(ybase + k, F, c, SL);
+            } else {
+                GammaRef<T, NX, NY> gr;
+                gr.F = const_cast<T *>(G->gF);
+                gr.c = const_cast<T *>(G->gc);
+                gr.SL = const_cast<T *>(G->gSL);
+                gr.H = const_cast<T *>(G->gH);
+                gr.d = const_cast<T *>(G->gd);
+                gr.SO = const_cast<T *>(G->gSO);
+                gr.stride = G->gstride;
+                gr.ld = G->gstride ? G->T_y : 1;
+                gr.load_trans(ybase + k, F, c, SL);
+            }
+            smoother_element(F, c, SL, f, e);
+        }
+        selem_ref_dev<T, NX>(G->sstash, G->T_x).store(off + k, e);
+    }
+    PSS_INL void down(int b, int64_t off, int64_t cnt, int64_t p, SElem<T, NX> &e) const
+    {
+        selem_ref_dev<T, NX>(G->sstash, G->T_x).load(off + (cnt - 1 - p), e);
+    }
+};
+
+// ---- one tile of a phase ----------------------------------------------------
+template <typename T, int NX, int NY, bool CT>
+PSS_INL void filter_tile(const PArgs<T> &a, const PGroup<T> &G, int64_t gt, T *lds)
+{
+    using Op = FilterScan<T, NX>;
+    const int b = find_seq(G.tile_f, G.B, gt, 0);
+    const int64_t t = gt - G.tile_f[b];
+    LevelGeom g;
+    g.y_off = G.y_off;
+    g.prev_tiles = nullptr;
+    g.tile_off = G.tile_f;
+    g.level = 0;
+    g.extra = 0;
+    g.B = G.B;
+    g.E = G.E_f;
+    TileInfo ti;
+    ti.b = b;
+    seq_range(g, b, ti.off, ti.cnt);
+    const int64_t TS = (int64_t)blockDim.x * g.E;
+    ti.start = t * TS;
+    const int64_t rem = ti.cnt - ti.start;
+    ti.tcnt = (int)(rem < TS ? rem : TS);
+    ti.nvalid = (ti.tcnt + g.E - 1) / g.E;
+    const int Tb = blockDim.x;
+    FusedFiltSrc<T, NX, NY, CT> src{&G, G.y_off[b] + b};
+    fold_phase<Op>(g, ti, src, lds, Tb);
+    tree_up<Op>(lds, Tb, ti.nvalid);
+    typename Op::Pre excl;
+    if (threadIdx.x == 0) {
+        MargRef<T, NX> pub = pre_ref<T, NX>(G.pre_f, G.ntiles_f);
+        if (t == 0) {
+            StartPre<T, NX>{G.m0, G.N0}.get(excl);
+        } else {
+            if (!wait_flag(G.flag_f + gt - 1, a.spin_limit))
+                atomicOr(a.error, 1);
+            pub.load(gt - 1, excl);
+        }
+        typename Op::Elem agg;
+        lds_get(agg, lds, Tb, Tb - 1);
+        typename Op::Pre incl;
+        Op::apply(excl, agg, incl);
+        pub.store(gt, incl);
+        flag_store(G.flag_f + gt, 1);
+    }
+    tree_down<Op>(lds, Tb, ti.nvalid, excl);
+    FiltDst<T, NX> dst{pre_ref<T, NX>(G.mf, G.T_x), G.y_off};
+    apply_phase<Op>(g, ti, src, dst, lds, Tb);
+    __threadfence(); // every thread's outputs visible device-wide before the flag
+    __syncthreads();
+    if (threadIdx.x == 0)
+        flag_store(G.done_f + gt, 1);
+}
+
+template <typename T, int NX, int NY, bool CT>
+PSS_INL void smoother_tile(const PArgs<T> &a, const PGroup<T> &G, int64_t gu, T *lds)
+{
+    using Op = SmootherScan<T, NX>;
+    const int b = find_seq(G.tile_s, G.B, gu, 0);
+    const int64_t u = gu - G.tile_s[b];
+    LevelGeom g;
+    g.y_off = G.y_off;
+    g.prev_tiles = nullptr;
+    g.tile_off = G.tile_s;
+    g.level = 0;
+    g.extra = 1;
+    g.B = G.B;
+    g.E = G.E_s;
+    TileInfo ti;
+    ti.b = b;
+    seq_range(g, b, ti.off, ti.cnt);
+    const int64_t TS = (int64_t)blockDim.x * g.E;
+    ti.start = u * TS;
+    const int64_t rem = ti.cnt - ti.start;
+    ti.tcnt = (int)(rem < TS ? rem : TS);
+    ti.nvalid = (ti.tcnt + g.E - 1) / g.E;
+    const int Tb = blockDim.x;
+    const int64_t n = ti.cnt - 1;
+    // states [klo, khi] of this tile; wait for the filter tiles that wrote
+    // their marginals and the transition parameters of steps klo+1..khi+1
+    if (threadIdx.x == 0) {
+        const int64_t khi = n - ti.start, klo = n - (ti.start + ti.tcnt - 1);
+        const int64_t s_lo = klo > 1 ? klo : 1;
+        const int64_t s_hi = (khi + 1) < n ? (khi + 1) : n;
+        const int64_t TSf = (int64_t)blockDim.x * G.E_f;
+        const int64_t f0 = G.tile_f[b];
+        for (int64_t tf = (s_lo - 1) / TSf; tf <= (s_hi - 1) / TSf; ++tf)
+            if (!wait_flag(G.done_f + f0 + tf, a.spin_limit))
+                atomicOr(a.error, 2);
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    FusedSmoothSrc<T, NX, NY, CT> src{&G, G.y_off[b]};
+    fold_phase<Op>(g, ti, src, lds, Tb);
+    tree_up<Op>(lds, Tb, ti.nvalid);
+    typename Op::Pre excl;
+    if (threadIdx.x == 0) {
+        MargRef<T, NX> pub = pre_ref<T, NX>(G.pre_s, G.ntiles_s);
+        if (u == 0) {
+            StartPre<T, NX>{nullptr, nullptr}.get(excl);
+        } else {
+            if (!wait_flag(G.flag_s + gu - 1, a.spin_limit))
+                atomicOr(a.error, 4);
+            pub.load(gu - 1, excl);
+        }
+        typename Op::Elem agg;
+        lds_get(agg, lds, Tb, Tb - 1);
+        typename Op::Pre incl;
+        Op::apply(excl, agg, incl);
+        pub.store(gu, incl);
+        flag_store(G.flag_s + gu, 1);
+    }
+    tree_down<Op>(lds, Tb, ti.nvalid, excl);
+    SmoothDst<T, NX> dst{pre_ref<T, NX>(G.nom_out_m, G.T_x)};
+    dst.out.N = G.nom_out_N;
+    apply_phase<Op>(g, ti, src, dst, lds, Tb);
+    __syncthreads();
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_ipls_persistent(PArgs<T> a)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *lds = reinterpret_cast<T *>(smem_raw);
+    __shared__ int item_sh;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0)
+            item_sh = atomicAdd(a.counter, 1);
+        __syncthreads();
+        const int64_t item = item_sh;
+        if (item >= a.total_items)
+            break;
+        // filter items of all groups first, then smoother items
+        for (int gi = 0; gi < a.n_groups; ++gi) {
+            const PGroup<T> &G = a.g[gi];
+            if (item >= G.item_f0 && item < G.item_f0 + G.ntiles_f) {
+                const int64_t gt = item - G.item_f0;
+                if (G.kind == kGroupCT)
+                    filter_tile<T, 5, 2, true>(a, G, gt, lds);
+                else
+                    filter_tile<T, 4, 2, false>(a, G, gt, lds);
+            } else if (item >= G.item_s0 && item < G.item_s0 + G.ntiles_s) {
+                const int64_t gu = item - G.item_s0;
+                if (G.kind == kGroupCT)
+                    smoother_tile<T, 5, 2, true>(a, G, gu, lds);
+                else
+                    smoother_tile<T, 4, 2, false>(a, G, gu, lds);
+            }
+        }
+    }
+}
+
+// clears the per-pass flags and the work counter (a kernel, so that the pass
+// can be captured in a graph without memset nodes)
+__global__ __launch_bounds__(256) void k_clear_ints(int *p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_copy(const T *src, T *dst, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+} // namespace pss

@@ -32,7 +32,8 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported", -3: "workspace too
 EXPORTS = ["pss_workspace_size", "pss_slr_linearize", "pss_sqrt_filter_elements",
            "pss_sqrt_filter_scan", "pss_sqrt_smoother_scan", "pss_ipls_iterate", "pss_loglik",
            "pss_loglik_grad", "pss_sequential_smoother", "pss_validate", "pss_last_error",
-           "pss_version"]
+           "pss_version", "pss_batched_workspace_size", "pss_ipls_batched",
+           "pss_autotune_workspace_size", "pss_autotune"]
 
 
 class PssError(RuntimeError):
@@ -49,6 +50,11 @@ class Problem(ctypes.Structure):
                 ("dt", ctypes.c_double), ("theta", ctypes.c_double * 3),
                 ("sensors", ctypes.c_double * 4),
                 ("scan_threads", ctypes.c_int32), ("scan_elems", ctypes.c_int32)]
+
+
+class GroupC(ctypes.Structure):
+    _fields_ = [("p", ctypes.POINTER(Problem)), ("g", ctypes.c_void_p), ("y", ctypes.c_void_p),
+                ("m_nom", ctypes.c_void_p), ("N_nom", ctypes.c_void_p)]
 
 
 class GammaC(ctypes.Structure):
@@ -92,6 +98,15 @@ def lib():
         L.pss_loglik_grad.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
         L.pss_sequential_smoother.argtypes = [P, ctypes.POINTER(GammaC), vp, i32, vp, vp, vp, vp,
                                               vp, sz, vp]
+        G = ctypes.POINTER(GroupC)
+        L.pss_batched_workspace_size.restype = sz
+        L.pss_batched_workspace_size.argtypes = [G, i32]
+        L.pss_autotune_workspace_size.restype = sz
+        L.pss_autotune_workspace_size.argtypes = [G, i32]
+        L.pss_ipls_batched.argtypes = [G, i32, i32, vp, vp, sz, vp]
+        L.pss_autotune.argtypes = [G, i32, vp, sz, ctypes.c_char_p, vp, vp]
+        L.pss_ipls_batched.restype = ctypes.c_int
+        L.pss_autotune.restype = ctypes.c_int
         for name in ("pss_slr_linearize", "pss_sqrt_filter_elements", "pss_sqrt_filter_scan",
                      "pss_sqrt_smoother_scan", "pss_ipls_iterate", "pss_loglik",
                      "pss_loglik_grad", "pss_sequential_smoother", "pss_validate"):
@@ -444,3 +459,65 @@ def _with_theta(batch, theta):
     b.__dict__.update(batch.__dict__)
     b.theta = tuple(float(v) for v in theta)
     return b
+
+
+# ---------------------------------------------------------------------------
+# ragged multi-group batches (one persistent launch per pass)
+# ---------------------------------------------------------------------------
+class _Groups:
+    """ctypes array of pss_group plus the objects it points into (kept alive)."""
+
+    def __init__(self, groups):
+        self.keep = []
+        arr = (GroupC * len(groups))()
+        for i, (batch, y, m, N, gamma) in enumerate(groups):
+            p = batch.struct()
+            self.keep.append(p)
+            arr[i].p = ctypes.pointer(p)
+            if gamma is not None:
+                gc = GammaC()
+                for k in ("F", "c", "SL", "H", "d", "SO"):
+                    setattr(gc, k, gamma[k].data_ptr())
+                gc.stride = gamma["stride"]
+                self.keep.append(gc)
+                arr[i].g = ctypes.addressof(gc)
+            else:
+                arr[i].g = None
+            arr[i].y = y.data_ptr()
+            arr[i].m_nom = m.data_ptr()
+            arr[i].N_nom = N.data_ptr()
+        self.arr = arr
+        self.n = len(groups)
+
+
+def batched_workspace_size(groups) -> int:
+    g = _Groups(groups)
+    return int(lib().pss_batched_workspace_size(g.arr, g.n))
+
+
+def ipls_batched(groups, n_iter, ws=None, status=None):
+    """Algorithm 3 over several groups; groups = [(batch, y, m_nom, N_nom, gamma|None)].
+    The nominals are updated in place.  Returns the device status tensor."""
+    _require_gpu()
+    g = _Groups(groups)
+    if ws is None:
+        n = int(lib().pss_batched_workspace_size(g.arr, g.n))
+        ws = torch.empty(max(n, 1), dtype=torch.uint8, device=groups[0][0].device)
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device=groups[0][0].device)
+    _check(lib().pss_ipls_batched(g.arr, g.n, int(n_iter), _ptr(status), _ptr(ws), ws.numel(),
+                                  _stream()))
+    return status
+
+
+def autotune(groups, cache_path=None):
+    """Time the candidate launch shapes on these groups; returns (T, E_f, E_s)."""
+    _require_gpu()
+    g = _Groups(groups)
+    n = int(lib().pss_autotune_workspace_size(g.arr, g.n))
+    ws = torch.empty(max(n, 1), dtype=torch.uint8, device=groups[0][0].device)
+    best = (ctypes.c_int32 * 3)()
+    _check(lib().pss_autotune(g.arr, g.n, _ptr(ws), n,
+                              cache_path.encode() if cache_path else None,
+                              ctypes.cast(best, ctypes.c_void_p), _stream()))
+    return tuple(best)

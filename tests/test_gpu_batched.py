@@ -1,0 +1,131 @@
+"""GPU parity of the persistent multi-group batched IPLS (pss_ipls_batched)
+and its autotuner against the FP64 oracle.
+
+A ragged batch mixes a linear constant-velocity group (nx 4) and a
+coordinated-turn group (nx 5) in one persistent launch per pass; tiles are
+forced small so every sequence chains several tiles."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as orc
+from paper_2207_00426_amd import pss
+from paper_2207_00426_amd import workloads as wl
+from tests import parity as par
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _cv_gamma(md):
+    return dict(F=md.F(), c=np.zeros(4), SL=np.linalg.cholesky(md.Q()), H=md.H(), d=np.zeros(2),
+                SO=np.linalg.cholesky(md.R()))
+
+
+def _groups(lens_cv, lens_ct, dtype, seed, T=0, E=0):
+    rng = np.random.default_rng(seed)
+    cv, ct = wl.CVModel(), wl.CTModel()
+    ys_cv = [wl.simulate_cv(int(n), rng, cv)[1] for n in lens_cv]
+    ys_ct = [wl.simulate_ct(int(n), rng, ct)[1] for n in lens_ct]
+    off_cv = np.concatenate([[0], np.cumsum(lens_cv)]).astype(np.int64)
+    off_ct = np.concatenate([[0], np.cumsum(lens_ct)]).astype(np.int64)
+    b_cv = pss.Batch(pss.MODEL_LINEAR, dtype, 4, 2, off_cv, cv.m0, np.eye(4), device=DEV,
+                     scan_threads=T, scan_elems=E)
+    b_ct = pss.Batch.ct(off_ct, ct, dtype=dtype, device=DEV, scan_threads=T, scan_elems=E)
+    g_cv = b_cv.gamma_from_numpy(_cv_gamma(cv))
+    y_cv = pss.to_soa(np.concatenate(ys_cv), dtype, DEV)
+    y_ct = pss.to_soa(np.concatenate(ys_ct), dtype, DEV)
+    m_cv, N_cv = b_cv.prior_nominal()
+    m_ct, N_ct = b_ct.prior_nominal()
+    groups = [(b_cv, y_cv, m_cv, N_cv, g_cv), (b_ct, y_ct, m_ct, N_ct, None)]
+    return groups, (ys_cv, ys_ct, off_cv, off_ct, cv, ct)
+
+
+def _oracle(meta, M):
+    ys_cv, ys_ct, off_cv, off_ct, cv, ct = meta
+    G = _cv_gamma(cv)
+    ref_cv = []
+    for y in ys_cv:
+        mf, Nf, _ = orc.sqrt_filter(cv.m0, np.eye(4), G, y)
+        ms, Ns, _ = orc.sqrt_smoother(G, mf, Nf)
+        ref_cv.append((ms, Ns))
+    ref_ct = [orc.ct_ipls(orc.ct_params(), ct.m0, np.eye(5), y, M) for y in ys_ct]
+    return ref_cv, [(r["ms"], r["Ns"]) for r in ref_ct]
+
+
+def _check(groups, meta, ref, tol):
+    (b_cv, _, m_cv, N_cv, _), (b_ct, _, m_ct, N_ct, _) = groups
+    _, _, off_cv, off_ct, _, _ = meta
+    for (m, N, off, nx, refs) in ((m_cv, N_cv, off_cv, 4, ref[0]), (m_ct, N_ct, off_ct, 5, ref[1])):
+        ma, Na = pss.marg_from_soa(m, N, nx)
+        for s, (rm, rN) in enumerate(refs):
+            a, z = off[s] + s, off[s + 1] + s + 1
+            em, eP = par.marg_errs(ma[a:z], Na[a:z], rm, rN)
+            assert em < tol["m"] and eP < tol["P"], (nx, s, em, eP)
+
+
+@pytest.mark.parametrize("tag,T,E,M", [("f64", 64, 1, 3), ("f64", 64, 2, 2), ("f32", 64, 2, 3),
+                                       ("f64", 0, 0, 3), ("f32", 0, 0, 2)])
+def test_batched_two_groups_match_oracle(tag, T, E, M):
+    dtype = torch.float64 if tag == "f64" else torch.float32
+    groups, meta = _groups([1, 37, 700, 129], [2, 300, 1000, 64], dtype, 11, T, E)
+    status = pss.ipls_batched(groups, M)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    _check(groups, meta, _oracle(meta, M), par.TOL[tag])
+
+
+def test_batched_is_deterministic_and_matches_single_group_calls():
+    groups, meta = _groups([50, 400], [300, 777], torch.float64, 5, 64, 2)
+    pss.ipls_batched(groups, 3)
+    torch.cuda.synchronize()
+    first = [g[2].clone() for g in groups] + [g[3].clone() for g in groups]
+    groups2, _ = _groups([50, 400], [300, 777], torch.float64, 5, 64, 2)
+    pss.ipls_batched(groups2, 3)
+    # the CT group alone gives the same bits as inside the two-group launch
+    groups3, _ = _groups([50, 400], [300, 777], torch.float64, 5, 64, 2)
+    pss.ipls_batched([groups3[1]], 3)
+    torch.cuda.synchronize()
+    again = [g[2] for g in groups2] + [g[3] for g in groups2]
+    for a, b in zip(first, again):
+        assert torch.equal(a, b)
+    assert torch.equal(groups3[1][2], groups[1][2]) and torch.equal(groups3[1][3], groups[1][3])
+
+
+def test_batched_graph_capture_replays_match_eager():
+    groups, meta = _groups([100, 33], [250, 600], torch.float32, 8, 64, 2)
+    m0 = [g[2].clone() for g in groups]
+    N0 = [g[3].clone() for g in groups]
+    ws = torch.empty(pss.batched_workspace_size(groups), dtype=torch.uint8, device=DEV)
+    status = torch.zeros(1, dtype=torch.int32, device=DEV)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        pss.ipls_batched(groups, 2, ws=ws, status=status)
+        torch.cuda.synchronize()
+        eager = [g[2].clone() for g in groups]
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=s):
+            for g, a, b in zip(groups, m0, N0):
+                g[2].copy_(a)
+                g[3].copy_(b)
+            pss.ipls_batched(groups, 2, ws=ws, status=status)
+        for _ in range(3):
+            for g in groups:
+                g[2].zero_()
+            graph.replay()
+            torch.cuda.synchronize()
+            for g, e in zip(groups, eager):
+                assert torch.equal(g[2], e)
+    assert int(status.item()) == 0
+
+
+def test_autotune_picks_a_valid_shape_and_is_used():
+    groups, meta = _groups([200, 900], [400, 1500], torch.float32, 3)
+    m_before = groups[1][2].clone()
+    best = pss.autotune(groups)
+    torch.cuda.synchronize()
+    assert best[0] in (64, 128, 256) and best[1] in (1, 2, 4, 8) and best[2] in (1, 2, 4, 8)
+    assert torch.equal(groups[1][2], m_before)  # the tuner does not touch the nominal
+    pss.ipls_batched(groups, 2)
+    torch.cuda.synchronize()
+    _check(groups, meta, _oracle(meta, 2), par.TOL["f32"])
