@@ -179,6 +179,94 @@ def timed(stream, fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
+def bench_batched(stream, dev, M, B=512, seed=3):
+    """Ragged batch: B sequences, lengths uniform in [100, 20000], half linear
+    constant-velocity, half coordinated-turn, FP32; each IPLS pass is one
+    persistent launch over both groups (autotuned shape, graph-captured)."""
+    log("simulating ragged batch of %d sequences" % B)
+    groups_w, lengths, kinds = wl.ragged_mixed(B, 100, 20000, seed, M=M)
+    tdt = torch.float32
+    cvm = wl.CVModel()
+    G = dict(F=cvm.F(), c=np.zeros(4), SL=np.linalg.cholesky(cvm.Q()), H=cvm.H(), d=np.zeros(2),
+             SO=np.linalg.cholesky(cvm.R()))
+    wcv, _ = groups_w["cv"]
+    wct, _ = groups_w["ct"]
+    b_cv = pss.Batch(pss.MODEL_LINEAR, tdt, 4, 2, wcv.y_off, cvm.m0, np.eye(4), device=dev)
+    b_ct = pss.Batch.ct(wct.y_off, wct.model, dtype=tdt, device=dev)
+    g_cv = b_cv.gamma_from_numpy(G)
+    y_cv = pss.to_soa(wcv.y, tdt, dev)
+    y_ct = pss.to_soa(wct.y, tdt, dev)
+    m_cv0, N_cv0 = b_cv.prior_nominal()
+    m_ct0, N_ct0 = b_ct.prior_nominal()
+    m_cv, N_cv, m_ct, N_ct = m_cv0.clone(), N_cv0.clone(), m_ct0.clone(), N_ct0.clone()
+    groups = [(b_cv, y_cv, m_cv, N_cv, g_cv), (b_ct, y_ct, m_ct, N_ct, None)]
+    steps = int(lengths.sum())
+    best = pss.autotune(groups)
+    log("batched: autotuned shape T=%d E_f=%d E_s=%d" % best)
+    ws = torch.empty(pss.batched_workspace_size(groups), dtype=torch.uint8, device=dev)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+
+    def step():
+        m_cv.copy_(m_cv0)
+        N_cv.copy_(N_cv0)
+        m_ct.copy_(m_ct0)
+        N_ct.copy_(N_ct0)
+        pss.ipls_batched(groups, M, ws=ws, status=status)
+
+    step()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        step()
+    graph.replay()
+    torch.cuda.synchronize()
+    t_batched = timed(stream, graph.replay, 3)
+    ok = int(status.item()) == 0
+    nan = int(torch.isnan(m_ct).any().item() or torch.isnan(m_cv).any().item())
+    log("batched: %.3f ms for %d step-passes (status %s)" % (t_batched, steps * M, ok))
+    # comparators: the multi-launch path per group, and one call per sequence
+    wsi_cv, _ = b_cv.workspace("ipls")
+    wsi_ct, _ = b_ct.workspace("ipls")
+
+    def multi_launch():
+        m_cv.copy_(m_cv0)
+        N_cv.copy_(N_cv0)
+        m_ct.copy_(m_ct0)
+        N_ct.copy_(N_ct0)
+        pss.ipls_iterate(b_cv, y_cv, M, m_cv, N_cv, gamma=g_cv, ws=wsi_cv)
+        pss.ipls_iterate(b_ct, y_ct, M, m_ct, N_ct, ws=wsi_ct)
+
+    t_multi = timed(stream, multi_launch, 2)
+    singles = []
+    for wgrp, bgrp, ygrp, gam in ((wcv, b_cv, y_cv, g_cv), (wct, b_ct, y_ct, None)):
+        for s in range(len(wgrp.y_off) - 1):
+            a, z = int(wgrp.y_off[s]), int(wgrp.y_off[s + 1])
+            bs = pss.Batch(bgrp.model, tdt, bgrp.nx, 2, [0, z - a], bgrp.m0.cpu().numpy(),
+                           pss.unpack_lower(bgrp.N0.cpu().numpy(), bgrp.nx), device=dev,
+                           dt=bgrp.dt, theta=bgrp.theta, sensors=bgrp.sensors)
+            ys = ygrp[:, a:z].contiguous()
+            mm, NN = bs.prior_nominal()
+            wsi, _ = bs.workspace("ipls")
+            singles.append((bs, ys, mm, NN, gam, wsi))
+
+    def loop_singles():
+        for bs, ys, mm, NN, gam, wsi in singles:
+            pss.ipls_iterate(bs, ys, M, mm, NN, gamma=gam, ws=wsi)
+
+    t_loop = timed(stream, loop_singles, 1)
+    log("batched: multi-launch %.3f ms, %d single-sequence calls %.3f ms" % (t_multi, B, t_loop))
+    return {"B": B, "total_steps": steps, "passes": M, "dtype": "f32",
+            "autotuned_shape": {"threads": best[0], "filter_elems": best[1],
+                                "smoother_elems": best[2]},
+            "persistent_graph_ms": round(t_batched, 4),
+            "value": round(steps * M / (t_batched * 1e-3), 1),
+            "unit": "smoothed time steps/s",
+            "multi_launch_ms": round(t_multi, 4),
+            "looped_single_sequence_ms": round(t_loop, 4),
+            "speedup_vs_looped": round(t_loop / t_batched, 2),
+            "status_ok": ok, "nan": nan}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -300,6 +388,9 @@ def main():
                 lg[dt] = {"loglik_plus_grad_ms": round(t_g, 4), "ipls_ms": round(t_i, 4)}
                 log("64x1e4 %s: loglik+grad %.3f ms, IPLS %.3f ms" % (dt, t_g, t_i))
             extras["param_estimation_64x1e4"] = lg
+
+        if not args.no_extras:
+            extras["batched_ragged_512"] = bench_batched(stream, dev, M)
 
     cpu = None
     if not args.no_cpu_baseline:

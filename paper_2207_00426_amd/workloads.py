@@ -134,17 +134,25 @@ def simulate_ct(n: int, rng: np.random.Generator, model: CTModel | None = None):
 
 
 def simulate_cv(n: int, rng: np.random.Generator, model: CVModel | None = None):
+    """Simulate one CV trajectory; returns (x[n+1, 4], y[n, 2]).
+
+    The recursion v_k = v_{k-1} + w^v_k, p_k = p_{k-1} + dt v_{k-1} + w^p_k is
+    evaluated with cumulative sums (same draws as the step-by-step form).
+    """
     md = CVModel() if model is None else model
     LQ = np.linalg.cholesky(md.Q())
     LP = np.linalg.cholesky(md.P0)
-    F, H = md.F(), md.H()
-    x = np.zeros((n + 1, 4))
-    x[0] = md.m0 + LP @ rng.standard_normal(4)
+    x0 = md.m0 + LP @ rng.standard_normal(4)
     e = rng.standard_normal((n, 6))
-    y = np.zeros((n, 2))
-    for k in range(n):
-        x[k + 1] = F @ x[k] + LQ @ e[k, :4]
-        y[k] = H @ x[k + 1] + md.r * e[k, 4:]
+    w = e[:, :4] @ LQ.T
+    x = np.zeros((n + 1, 4))
+    x[0] = x0
+    v = x0[2:] + np.cumsum(w[:, 2:], axis=0)
+    v_prev = np.vstack([x0[2:][None], v[:-1]])
+    p = x0[:2] + np.cumsum(md.dt * v_prev + w[:, :2], axis=0)
+    x[1:, :2] = p
+    x[1:, 2:] = v
+    y = p + md.r * e[:, 4:]
     return x, y
 
 
