@@ -16,9 +16,13 @@ Also in the line (same run):
                   n = 10^4 and 10^5 (prefixes of the same sequence)
   loglik_grad_ms  one loglik + gradient evaluation on 64 CT sequences of
                   10^4 steps (the parameter-estimation configuration)
-  roofline        the filter-scan launch group (the dominant work), timed
-                  with HIP events on its stream; work = counted flops of the
-                  operators it executes; bound = FP64 vector ALU
+  kernels         every scan kernel of one filter and one smoother scan,
+                  timed per launch with HIP events on its stream, with the
+                  counted flops it executes
+  roofline        the kernel with the largest time among those; bound =
+                  vector ALU; traffic = counter HBM bytes per launch from the
+                  committed rocprofv3 summary, when it was taken on these
+                  kernels
   cpu_baseline    the FP64 oracle on the host, on a bounded prefix of the
                   same sequence
 """
@@ -71,31 +75,93 @@ def log(msg):
 
 
 def scan_plan(lengths, T0, E0, Tup, Eup):
-    """Mirror of the library's level plan: per level (T, E, elements, tiles)."""
+    """Mirror of the library's level plan: per level (T, E, elements, tiles,
+    active threads)."""
     cnt = np.asarray(lengths, dtype=np.int64)
     levels = []
     for l in range(8):
         T, E = (T0, E0) if l == 0 else (Tup, Eup)
         TS = T * E
         tiles = -(-cnt // TS)
-        levels.append((T, E, int(cnt.sum()), int(tiles.sum())))
+        last = cnt - (tiles - 1) * TS
+        threads = (tiles - 1) * T + (-(-last // E))
+        levels.append((T, E, int(cnt.sum()), int(tiles.sum()), int(threads.sum())))
         if cnt.max() <= TS:
             break
         cnt = tiles
     return levels
 
 
-def filter_scan_flops(lengths, T0, E0, Tup, Eup):
-    """Counted flops of one filter scan: every element of every level is
-    folded once and applied once; each tile's tree adds about T combines and
-    T applies (its nodes)."""
-    tot = 0
-    for T, E, elems, tiles in scan_plan(lengths, T0, E0, Tup, Eup):
-        threads = -(-elems // E)
-        combines = elems - tiles
-        applies = elems + threads - tiles
-        tot += combines * FLOPS["filter_combine"] + applies * FLOPS["filter_apply"]
-    return tot
+def scan_kernel_flops(op, lengths, T0, E0, Tup, Eup):
+    """Counted flops of each kernel of one scan, keyed (kernel, level).
+
+    Up-sweep (and the first half of the top kernel): the fold and the tile
+    tree combine every element but the first of each tile, elems - tiles
+    combines.  Down-sweep: the tree applies threads - tiles times and every
+    element is applied once.  The smoother's level-0 up-sweep also builds its
+    elements (one per state)."""
+    comb, app = FLOPS[op + "_combine"], FLOPS[op + "_apply"]
+    plan = scan_plan(lengths, T0, E0, Tup, Eup)
+    out = {}
+    for l, (T, E, elems, tiles, threads) in enumerate(plan):
+        up = (elems - tiles) * comb
+        if op == "smoother" and l == 0:
+            up += elems * FLOPS["smoother_element"]
+        down = (elems + threads - tiles) * app
+        if l == len(plan) - 1:
+            out[(op + "_top", l)] = up + down
+        else:
+            out[(op + "_up", l)] = up
+            out[(op + "_down", l)] = down
+    return out
+
+
+def kernel_source_hash():
+    """Hash of the HIP sources and build flags: a counter summary taken from
+    other kernels than the ones built here is not used."""
+    import hashlib
+    from paper_2207_00426_amd import build as hipbuild
+    h = hashlib.sha256(" ".join(hipbuild.FLAGS).encode())
+    csrc = os.path.join(ROOT, "paper_2207_00426_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp", ".h")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode() + fh.read())
+    with open(os.path.join(ROOT, "include", "pss.h"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(kernel, level, dtype, n):
+    """HBM bytes per launch of (kernel, level) from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary of this workload, each scaled by what the
+    same counter reads for a copy of known size; None when there is no
+    summary for the kernels built here."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_ct_n%d_%s.md" % (n, dtype))
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("traffic:"):
+                kv = dict(t.split("=", 1) for t in line.split()[1:])
+                rec[(kv["kernel"], int(kv["level"]))] = kv
+    kv = rec.get((kernel, level))
+    if kv is None or kv.get("src") != kernel_source_hash():
+        return None
+    return int(float(kv["bytes"]))
+
+
+def copy_probe(stream, dev, reps=5):
+    """Plain streaming copy of known size (1 GiB read + 1 GiB written, an
+    elementwise negate): HBM bandwidth reference, and the calibration kernel
+    for the FETCH_SIZE / WRITE_SIZE counters."""
+    x = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    y = torch.empty_like(x)
+    ms = timed(stream, lambda: torch.neg(x, out=y), reps)
+    gbps = 2 * x.numel() * 8 / (ms * 1e-3) / 1e9
+    del x, y
+    return gbps
 
 
 def shapes(dtype, T_req, E_req):
@@ -284,6 +350,8 @@ def main():
     full = wl.ct_long(n, 2, M=M)
     extras = {}
     with torch.cuda.stream(stream):
+        copy_gbps = copy_probe(stream, dev)
+        log("copy probe: %.1f GB/s" % copy_gbps)
         log("main: CT n=%d passes=%d %s" % (n, M, args.dtype))
         R = Runner(full, args.dtype, dev, stream, args.scan_threads, args.scan_elems,
                    graph=not args.no_graph)
@@ -314,6 +382,14 @@ def main():
             assert rc == 0, pss.last_error()
 
         reps = 5 if n >= 10 ** 5 else 20
+        # per-kernel durations, HIP events on the launch stream
+        pss.kernel_timing(True)
+        for _ in range(reps):
+            fscan()
+            sscan()
+        torch.cuda.synchronize()
+        ktimes = pss.kernel_times()
+        pss.kernel_timing(False)
         stage = {
             "slr": timed(stream, lambda: pss.slr_linearize(b, m, N, yd, out=gam), reps),
             "filter_elements": timed(stream, lambda: pss.sqrt_filter_elements(b, gam, yd, out=fel),
@@ -324,8 +400,23 @@ def main():
         }
         log("stages (ms): " + ", ".join("%s %.3f" % kv for kv in stage.items()))
         T0, E0, Tup, Eup = shapes(args.dtype, args.scan_threads, args.scan_elems)
-        fl = filter_scan_flops([n], T0, E0, Tup, Eup)
-        achieved = fl / (stage["filter_scan"] * 1e-3) / 1e12
+        kflops = scan_kernel_flops("filter", [n], T0, E0, Tup, Eup)
+        kflops.update(scan_kernel_flops("smoother", [n + 1], T0, E0, Tup, Eup))
+        kernels = {}
+        for key, (calls, tot) in sorted(ktimes.items()):
+            avg = tot / calls
+            fl_k = kflops.get(key)
+            kernels["%s_L%d" % key] = {
+                "launches": calls, "avg_ms": round(avg, 5),
+                "flops_per_launch": fl_k,
+                "tflops": None if fl_k is None else round(fl_k / (avg * 1e-3) / 1e12, 4)}
+        dom = max(ktimes, key=lambda k: ktimes[k][1])
+        dom_ms = ktimes[dom][1] / ktimes[dom][0]
+        fl = kflops[dom]
+        achieved = fl / (dom_ms * 1e-3) / 1e12
+        traffic = counter_traffic(dom[0], dom[1], args.dtype, n)
+        log("dominant kernel %s level %d: %.4f ms, %.3f TFLOP/s" % (dom[0], dom[1], dom_ms,
+                                                                    achieved))
         del R, gam, fel, mf, Nf, ms_, Ns_, ws_f, ws_s
         torch.cuda.empty_cache()
 
@@ -436,11 +527,12 @@ def main():
             "loglik_plus_grad_ms"),
         "nan_loglik": nan,
         "stage_ms": {k: round(v, 4) for k, v in stage.items()},
-        "roofline": {"bound": "alu", "kernel": "filter scan launch group "
-                     "(k_plan, k_scan_up, k_scan_top, k_scan_down)",
+        "roofline": {"bound": "alu", "kernel": "%s level %d" % dom,
                      "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 6), "traffic": None,
-                     "flops_per_launch": int(fl)},
+                     "frac": round(achieved / peak, 6), "traffic": traffic,
+                     "flops_per_launch": int(fl), "avg_launch_ms": round(dom_ms, 5)},
+        "kernels": kernels,
+        "copy_probe_GBps": round(copy_gbps, 1),
         "cpu_baseline": cpu,
         "extras": extras,
     }

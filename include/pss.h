@@ -260,6 +260,21 @@ const char *pss_last_error(void);
 /* Library version string. */
 const char *pss_version(void);
 
+/* Instrumentation (not part of the method).  While enabled, every kernel
+   launch of the entry points above is bracketed by two HIP events recorded
+   on the caller's stream (skipped while that stream is being captured into
+   a graph).  Process-wide switch; returns PSS_OK. */
+int pss_kernel_timing(int32_t enable);
+
+/* Waits for the events recorded since the last call, then writes one text
+   line per (kernel, scan level): "<kernel> <level> <launches> <total ms>\n"
+   (kernel = filter_up, filter_top, filter_down, smoother_up, ..., slr,
+   filter_elements, loglik_terms, grad_terms, sequential, persistent_pass),
+   NUL-terminated and truncated to cap bytes, into buf (host), and clears
+   the records.  With buf NULL nothing is written or cleared.  Returns the
+   bytes needed (text + NUL), or a negative status. */
+int64_t pss_kernel_times(char *buf, size_t cap);
+
 #ifdef __cplusplus
 }
 #endif

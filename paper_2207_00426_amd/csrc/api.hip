@@ -1,9 +1,15 @@
 // C ABI of the parallel square-root smoother: validation, dispatch on
 // (dtype, nx, ny), scan planning and the few non-template kernels.
 #include <math.h>
+#include <stdio.h>
+#include <string.h>
 
 #include <algorithm>
+#include <atomic>
+#include <map>
+#include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "common.hpp"
@@ -21,6 +27,82 @@ int hip_check(hipError_t e, const char *what)
         return PSS_OK;
     set_error(std::string(what) + ": " + hipGetErrorString(e));
     return PSS_EHIP;
+}
+
+// ---------------------------------------------------------------------------
+// per-launch kernel timing (instrumentation)
+// ---------------------------------------------------------------------------
+namespace {
+struct KRec {
+    std::string key;
+    int level;
+    hipEvent_t a, b;
+};
+std::atomic<bool> g_kt_on{false};
+std::mutex g_kt_mu;
+std::vector<KRec> g_kt_recs;
+std::vector<hipEvent_t> g_kt_pool;
+
+hipEvent_t kt_event()
+{
+    hipEvent_t e = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_kt_mu);
+        if (!g_kt_pool.empty()) {
+            e = g_kt_pool.back();
+            g_kt_pool.pop_back();
+            return e;
+        }
+    }
+    if (hipEventCreate(&e) != hipSuccess)
+        return nullptr;
+    return e;
+}
+
+void kt_release(hipEvent_t e)
+{
+    if (!e)
+        return;
+    std::lock_guard<std::mutex> lk(g_kt_mu);
+    g_kt_pool.push_back(e);
+}
+
+bool kt_capturing(hipStream_t s)
+{
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) != hipSuccess)
+        return true; // unknown: do not record
+    return st != hipStreamCaptureStatusNone;
+}
+} // namespace
+
+KTime::KTime(hipStream_t s_, const char *name_, const char *phase_, int level_)
+    : s(s_), name(name_), phase(phase_), level(level_)
+{
+    if (!g_kt_on.load(std::memory_order_relaxed) || kt_capturing(s))
+        return;
+    a = kt_event();
+    if (a && hipEventRecord(a, s) != hipSuccess) {
+        kt_release(a);
+        a = nullptr;
+    }
+}
+
+KTime::~KTime()
+{
+    if (!a)
+        return;
+    hipEvent_t b = kt_event();
+    if (!b || hipEventRecord(b, s) != hipSuccess) {
+        kt_release(a);
+        kt_release(b);
+        return;
+    }
+    std::string key = name;
+    if (phase && phase[0])
+        key += std::string("_") + phase;
+    std::lock_guard<std::mutex> lk(g_kt_mu);
+    g_kt_recs.push_back(KRec{key, level, a, b});
 }
 
 // ---------------------------------------------------------------------------
@@ -356,6 +438,61 @@ extern "C" {
 const char *pss_last_error(void) { return g_last_error.c_str(); }
 
 const char *pss_version(void) { return "pss 0.1 (gfx950)"; }
+
+int pss_kernel_timing(int32_t enable)
+{
+    g_kt_on.store(enable != 0);
+    return PSS_OK;
+}
+
+int64_t pss_kernel_times(char *buf, size_t cap)
+{
+    try {
+        // a NULL buffer only asks for the size: the records stay
+        const bool take = buf != nullptr;
+        std::vector<KRec> recs;
+        {
+            std::lock_guard<std::mutex> lk(g_kt_mu);
+            if (take)
+                recs.swap(g_kt_recs);
+            else
+                recs = g_kt_recs;
+        }
+        std::map<std::pair<std::string, int>, std::pair<int64_t, double>> acc;
+        int rc = PSS_OK;
+        for (const KRec &r : recs) {
+            float ms = 0.f;
+            if (rc == PSS_OK && (rc = hip_check(hipEventSynchronize(r.b), "kernel timing sync")) ==
+                                    PSS_OK)
+                rc = hip_check(hipEventElapsedTime(&ms, r.a, r.b), "kernel timing elapsed");
+            auto &v = acc[{r.key, r.level}];
+            v.first += 1;
+            v.second += ms;
+            if (take) {
+                kt_release(r.a);
+                kt_release(r.b);
+            }
+        }
+        if (rc != PSS_OK)
+            return rc;
+        std::string out;
+        char line[192];
+        for (const auto &kv : acc) {
+            snprintf(line, sizeof line, "%s %d %lld %.6f\n", kv.first.first.c_str(), kv.first.second,
+                     (long long)kv.second.first, kv.second.second);
+            out += line;
+        }
+        if (buf && cap > 0) {
+            const size_t n = std::min(cap - 1, out.size());
+            memcpy(buf, out.data(), n);
+            buf[n] = 0;
+        }
+        return (int64_t)out.size() + 1;
+    } catch (...) {
+        set_error("exception in pss_kernel_times");
+        return PSS_EINVAL;
+    }
+}
 
 int pss_validate(const pss_problem *p)
 {

@@ -15,6 +15,20 @@ constexpr int kMaxLevels = 8;
 void set_error(const std::string &msg);
 int hip_check(hipError_t e, const char *what);
 
+// Optional per-launch kernel timing: while enabled (and the stream is not
+// being captured), a KTime scope records a HIP event on the launch stream
+// when it opens and another when it closes; pss_kernel_times() reads them.
+struct KTime {
+    hipStream_t s;
+    const char *name, *phase;
+    int level;
+    hipEvent_t a = nullptr;
+    KTime(hipStream_t s_, const char *name_, const char *phase_, int level_);
+    ~KTime();
+    KTime(const KTime &) = delete;
+    KTime &operator=(const KTime &) = delete;
+};
+
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // bump allocator over the caller's workspace

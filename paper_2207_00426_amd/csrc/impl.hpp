@@ -168,6 +168,7 @@ struct Core {
             const int64_t tree_ld = sh.ntiles[l] * sh.T[l];
             AggRef agg = agg_ref(w.agg[l + 1], sh.nelem[l + 1]);
             const size_t lb = lds_bytes<Op>(sh.T[l]);
+            KTime kt(c.s, Op::name, "up", l);
             if (l == 0) {
                 auto k = k_scan_up<Op, Src0, AggRef>;
                 if ((rc = prep_lds(k, lb)))
@@ -190,6 +191,7 @@ struct Core {
             const int l = sh.L - 1;
             const LevelGeom g = geom(l);
             const size_t lb = lds_bytes<Op>(sh.T[l]);
+            KTime kt(c.s, Op::name, "top", l);
             if (l == 0) {
                 auto k = k_scan_top<Op, Src0, Dst0, Start>;
                 if ((rc = prep_lds(k, lb)))
@@ -214,6 +216,7 @@ struct Core {
             const int64_t tree_ld = sh.ntiles[l] * sh.T[l];
             const size_t lb = lds_bytes<Op>(sh.T[l]);
             MargRef<T, NX> pin = marg_ref(w.pre[l + 1], sh.nelem[l + 1]);
+            KTime kt(c.s, Op::name, "down", l);
             if (l == 0) {
                 auto k = k_scan_down<Op, Src0, Dst0, MargRef<T, NX>>;
                 if ((rc = prep_lds(k, lb)))
@@ -306,6 +309,7 @@ struct Core {
         er.Z = mptr<T>(out->Z);
         er.ld = c.T_y;
         const int tb = 128;
+        KTime kt(c.s, "filter_elements", "", 0);
         hipLaunchKernelGGL((k_filter_elements<T, NX, NY>), dim3((unsigned)((c.T_y + tb - 1) / tb)),
                            dim3(tb), 0, c.s, c.p->y_off, c.B, c.T_y, gamma_ref(g, c.T_y),
                            cptr<T>(y), cptr<T>(c.p->m0), cptr<T>(c.p->N0), er);
@@ -415,6 +419,7 @@ struct Core {
         if ((rc = fscan(c, &el, mfb, mfb + (size_t)NX * c.T_x, scan_ws)))
             return rc;
         const int tb = 128;
+        KTime kt(c.s, "loglik_terms", "", 0);
         hipLaunchKernelGGL((k_loglik_terms<T, NX, NY>),
                            dim3((unsigned)((c.T_y + tb - 1) / tb)), dim3(tb), 0, c.s,
                            c.p->y_off, c.B, c.T_y, c.T_x, gamma_ref(g, c.T_y), cptr<T>(y),
@@ -483,6 +488,7 @@ struct Core {
             if (is_ct(c) && (rc = slr(c, m_nom, N_nom, y, &gw)))
                 break;
             const int tb = 64;
+            KTime kt(c.s, "sequential", "", 0);
             hipLaunchKernelGGL((k_sequential<T, NX, NY>), dim3((unsigned)((c.B + tb - 1) / tb)),
                                dim3(tb), 0, c.s, c.p->y_off, c.B, c.T_y, gamma_ref(g, c.T_y),
                                cptr<T>(y), cptr<T>(c.p->m0), cptr<T>(c.p->N0),
@@ -510,6 +516,7 @@ int Core<T, NX, NY>::slr(const Ctx &c, const void *m, const void *N, const void 
             for (int j = 0; j < 5; ++j)
                 P.LQ[i][j] = (T)h.LQ[i][j];
         const int tb = 128;
+        KTime kt(c.s, "slr", "", 0);
         hipLaunchKernelGGL((k_slr_ct<T>), dim3((unsigned)((c.T_x + tb - 1) / tb)), dim3(tb), 0,
                            c.s, c.p->y_off, c.B, c.T_x, c.T_y, P, marg_ref2(m, N, c.T_x),
                            cptr<T>(y), gamma_ref(out, c.T_y));
@@ -534,6 +541,7 @@ int Core<T, NX, NY>::grad_terms(const Ctx &c, const pss_gamma *g, const void *y,
             }
         gp.sig2 = (T)(h.sigma * h.sigma);
         const int tb = 128;
+        KTime kt(c.s, "grad_terms", "", 0);
         hipLaunchKernelGGL((k_grad_ct<T>), dim3((unsigned)((c.T_y + tb - 1) / tb)), dim3(tb), 0,
                            c.s, c.p->y_off, c.B, c.T_y, gamma_ref(g, c.T_y), cptr<T>(y),
                            marg_ref2(mf, Nf, c.T_x), marg_ref2(ms, Ns, c.T_x), gp, gterms);

@@ -218,6 +218,7 @@ struct FilterScan {
     using Pre = Marg<T, NX>;
     static constexpr int NE = Sizes<NX>::felem;
     static constexpr int NP = Sizes<NX>::marg;
+    static constexpr const char *name = "filter";
     PSS_INL static void combine(const Elem &a, const Elem &b, Elem &o) { filter_combine(a, b, o); }
     PSS_INL static void apply(const Pre &p, const Elem &a, Pre &o) { filter_apply(p, a, o); }
 };
@@ -232,6 +233,7 @@ struct SmootherScan {
     using Pre = Marg<T, NX>;
     static constexpr int NE = Sizes<NX>::selem;
     static constexpr int NP = Sizes<NX>::marg;
+    static constexpr const char *name = "smoother";
     PSS_INL static void combine(const Elem &a, const Elem &b, Elem &o) { smoother_combine(b, a, o); }
     PSS_INL static void apply(const Pre &p, const Elem &a, Pre &o) { smoother_apply(a, p, o); }
 };

@@ -341,7 +341,10 @@ int run(const pss_group *gs, int ng, int n_iter, int32_t *status, void *ws, size
         const int64_t nclr = L.nflags + (status ? 1 : 2);
         hipLaunchKernelGGL(k_clear_ints, dim3((unsigned)std::min<int64_t>((nclr + 255) / 256, 1024)),
                            dim3(256), 0, s, L.flags, nclr);
-        hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(sh.T), lds, s, a);
+        {
+            KTime kt(s, "persistent_pass", "", 0);
+            hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(sh.T), lds, s, a);
+        }
         if ((rc = hip_check(hipGetLastError(), "persistent pass launch")))
             return rc;
     }

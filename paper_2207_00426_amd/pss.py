@@ -33,7 +33,8 @@ EXPORTS = ["pss_workspace_size", "pss_slr_linearize", "pss_sqrt_filter_elements"
            "pss_sqrt_filter_scan", "pss_sqrt_smoother_scan", "pss_ipls_iterate", "pss_loglik",
            "pss_loglik_grad", "pss_sequential_smoother", "pss_validate", "pss_last_error",
            "pss_version", "pss_batched_workspace_size", "pss_ipls_batched",
-           "pss_autotune_workspace_size", "pss_autotune"]
+           "pss_autotune_workspace_size", "pss_autotune", "pss_kernel_timing",
+           "pss_kernel_times"]
 
 
 class PssError(RuntimeError):
@@ -107,6 +108,10 @@ def lib():
         L.pss_autotune.argtypes = [G, i32, vp, sz, ctypes.c_char_p, vp, vp]
         L.pss_ipls_batched.restype = ctypes.c_int
         L.pss_autotune.restype = ctypes.c_int
+        L.pss_kernel_timing.argtypes = [i32]
+        L.pss_kernel_timing.restype = ctypes.c_int
+        L.pss_kernel_times.argtypes = [ctypes.c_char_p, sz]
+        L.pss_kernel_times.restype = ctypes.c_int64
         for name in ("pss_slr_linearize", "pss_sqrt_filter_elements", "pss_sqrt_filter_scan",
                      "pss_sqrt_smoother_scan", "pss_ipls_iterate", "pss_loglik",
                      "pss_loglik_grad", "pss_sequential_smoother", "pss_validate"):
@@ -121,6 +126,29 @@ def last_error() -> str:
 
 def version() -> str:
     return lib().pss_version().decode()
+
+
+def kernel_timing(enable: bool) -> None:
+    """Switch per-launch HIP-event timing of the library's kernels on or off."""
+    _check(lib().pss_kernel_timing(1 if enable else 0))
+
+
+def kernel_times() -> dict:
+    """Collect the launches timed since the last call:
+    {(kernel, level): (launches, total_ms)}; waits for the recorded events."""
+    L = lib()
+    need = L.pss_kernel_times(None, 0)
+    if need < 0:
+        _check(int(need))
+    buf = ctypes.create_string_buffer(int(need) + 256)
+    got = L.pss_kernel_times(buf, len(buf))
+    if got < 0:
+        _check(int(got))
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, level, calls, ms = line.split()
+        out[(name, int(level))] = (int(calls), float(ms))
+    return out
 
 
 def _check(rc):

@@ -20,7 +20,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _header_symbols():
     src = open(os.path.join(ROOT, "include", "pss.h")).read()
-    decl = r"^(?:int|size_t|const char \*)\s*(pss_[a-z_]+)\s*\("
+    decl = r"^(?:int|int64_t|size_t|const char \*)\s*(pss_[a-z_]+)\s*\("
     return sorted(set(re.findall(decl, src, flags=re.M)))
 
 
@@ -123,3 +123,10 @@ def test_compute_calls_refuse_without_gpu():
     with pytest.raises(RuntimeError):
         pss.ipls_iterate(b, torch.zeros(2, 25, dtype=torch.float64), 1,
                          gamma=b.new_gamma(0))
+
+
+def test_kernel_timing_switch_without_launches(L):
+    # no launch was timed: the report is empty and the switch round-trips
+    pss.kernel_timing(True)
+    pss.kernel_timing(False)
+    assert pss.kernel_times() == {}
