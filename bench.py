@@ -3,7 +3,8 @@
 Main workload: coordinated-turn bearings-only tracking, one long sequence of
 n = 10^6 steps (the long-sequence configuration), 10 cubature IPLS passes
 (SLR, filter elements, filter scan, smoother scan), then the
-pseudo-log-likelihood and its gradient at the final nominal, FP64.  One
+pseudo-log-likelihood and its gradient at the final nominal (one gradient
+pass returns both), FP64.  One
 "step" is that whole hot path over the sequence, captured in a HIP graph and
 replayed; inputs are synthetic (seeded simulation) and already in HBM.
 
@@ -164,11 +165,11 @@ def copy_probe(stream, dev, reps=5):
     return gbps
 
 
-def shapes(dtype, T_req, E_req):
-    T0 = T_req or (128 if dtype == "f64" else 256)
-    E0 = E_req or 4
-    Tup = min(T0, 128 if dtype == "f64" else 256)
-    return T0, E0, Tup, 2
+def shapes(dtype, T_req, E_req, smoother=False):
+    """Mirror of the library's default launch shapes (T0, E0, Tup, Eup)."""
+    T0 = T_req or 64
+    E0 = E_req or (2 if smoother else 4)
+    return T0, E0, min(T0, 64), 2
 
 
 class Runner:
@@ -184,7 +185,6 @@ class Runner:
         self.m, self.N = self.m0.clone(), self.N0.clone()
         self.ws_ipls, _ = self.b.workspace("ipls")
         self.ws_grad, _ = self.b.workspace("loglik_grad")
-        self.ws_ll, _ = self.b.workspace("loglik")
         self.stream = stream
         self.graph = None
         self.want_graph = graph
@@ -193,7 +193,7 @@ class Runner:
         self.m.copy_(self.m0)
         self.N.copy_(self.N0)
         pss.ipls_iterate(self.b, self.yd, self.w.M, self.m, self.N, ws=self.ws_ipls)
-        pss.loglik(self.b, self.yd, self.m, self.N, ws=self.ws_ll)
+        # the gradient pass also returns the log-likelihood
         return pss.loglik_grad(self.b, self.m, self.N, self.yd, ws=self.ws_grad)
 
     def prepare(self, warmup):
@@ -401,7 +401,9 @@ def main():
         log("stages (ms): " + ", ".join("%s %.3f" % kv for kv in stage.items()))
         T0, E0, Tup, Eup = shapes(args.dtype, args.scan_threads, args.scan_elems)
         kflops = scan_kernel_flops("filter", [n], T0, E0, Tup, Eup)
-        kflops.update(scan_kernel_flops("smoother", [n + 1], T0, E0, Tup, Eup))
+        kflops.update(scan_kernel_flops(
+            "smoother", [n + 1], *shapes(args.dtype, args.scan_threads, args.scan_elems, True)))
+        E0s = shapes(args.dtype, args.scan_threads, args.scan_elems, True)[1]
         kernels = {}
         for key, (calls, tot) in sorted(ktimes.items()):
             avg = tot / calls
@@ -469,9 +471,7 @@ def main():
                 yy = pss.to_soa(wb.y, tdt, dev)
                 mm, NN = pss.ipls_iterate(bb, yy, M)
                 wg, _ = bb.workspace("loglik_grad")
-                wl_, _ = bb.workspace("loglik")
-                t_g = timed(stream, lambda: (pss.loglik(bb, yy, mm, NN, ws=wl_),
-                                             pss.loglik_grad(bb, mm, NN, yy, ws=wg)), 10)
+                t_g = timed(stream, lambda: pss.loglik_grad(bb, mm, NN, yy, ws=wg), 10)
                 wi, _ = bb.workspace("ipls")
                 m0, N0 = bb.prior_nominal()
                 t_i = timed(stream, lambda: (mm.copy_(m0), NN.copy_(N0),
@@ -522,7 +522,7 @@ def main():
         "data": "synthetic (seeded CT bearings-only simulation)",
         "config": {"workload": "ct_bearings_long_n%d_M%d_cubature" % (n, M), "B": 1, "n": n,
                    "passes": M, "nx": 5, "ny": 2, "graph": not args.no_graph,
-                   "scan_threads": T0, "scan_elems": E0},
+                   "scan_threads": T0, "filter_elems": E0, "smoother_elems": E0s},
         "loglik_grad_ms": extras.get("param_estimation_64x1e4", {}).get(args.dtype, {}).get(
             "loglik_plus_grad_ms"),
         "nan_loglik": nan,

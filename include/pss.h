@@ -101,8 +101,9 @@ typedef struct pss_problem {
     double theta[3];            /* log q1, log q2, log sigma                   */
     double sensors[4];          /* s1x, s1y, s2x, s2y                          */
     /* launch shape overrides (0 = library default / autotuned):
-       block threads per scan tile (64, 128 or 256) and elements folded
-       sequentially per thread (>= 1) at the finest scan level */
+       block threads per scan tile (64, 128 or 256; default 64) and elements
+       folded sequentially per thread (>= 1) at the finest level of both
+       scans (default 4 for the filter scan, 2 for the smoother scan) */
     int32_t scan_threads;
     int32_t scan_elems;
 } pss_problem;

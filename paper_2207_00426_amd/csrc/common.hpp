@@ -31,6 +31,20 @@ struct KTime {
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// LDS of a scan tile of T threads folding E elements each: the tree holds NE
+// values per thread; staged outputs (see apply_phase) NP values per element.
+// Outputs are staged when that fits in the tree's space or in 48 KiB.
+inline bool scan_stage(int NE, int NP, int T, int E, size_t esz)
+{
+    const size_t tree = (size_t)NE * T * esz, st = (size_t)NP * T * E * esz;
+    return st <= tree || st <= 48 * 1024;
+}
+inline size_t scan_lds(int NE, int NP, int T, int E, size_t esz, bool stage)
+{
+    const size_t tree = (size_t)NE * T * esz, st = stage ? (size_t)NP * T * E * esz : 0;
+    return tree > st ? tree : st;
+}
+
 // bump allocator over the caller's workspace
 struct Carver {
     char *base;

@@ -277,30 +277,139 @@ PSS_INL void xi_matrix(const T (&Ui)[NX][NX], const T (&Zj)[NX][NX], T (&M)[2 * 
     }
 }
 
+// ---- element views ---------------------------------------------------------
+// The operators below read their operands through views, one field at a time
+// and only when it is needed, so an operand may stay in LDS or memory instead
+// of occupying registers for the whole operator.  FRegV views an element in
+// registers; FSlotV views one stored flat, component c at p[c * ld] in the
+// component order of visit() (an LDS slot: p = lds + slot, ld = threads).
+// Setters write through the view.
 template <typename T, int NX>
-PSS_INL void filter_combine(const FElem<T, NX> &ei, const FElem<T, NX> &ej, FElem<T, NX> &o)
+struct FRegV {
+    FElem<T, NX> *e;
+    PSS_INL T A(int i, int j) const { return e->A[i][j]; }
+    PSS_INL T b(int i) const { return e->b[i]; }
+    PSS_INL T U(int i, int j) const { return e->U[i][j]; }
+    PSS_INL T eta(int i) const { return e->eta[i]; }
+    PSS_INL T Z(int i, int j) const { return e->Z[i][j]; }
+    PSS_INL void sA(int i, int j, T v) const { e->A[i][j] = v; }
+    PSS_INL void sb(int i, T v) const { e->b[i] = v; }
+    PSS_INL void sU(int i, int j, T v) const { e->U[i][j] = v; }
+    PSS_INL void seta(int i, T v) const { e->eta[i] = v; }
+    PSS_INL void sZ(int i, int j, T v) const { e->Z[i][j] = v; }
+};
+
+template <typename T, int NX, typename I>
+struct FSlotV {
+    T *p;
+    I ld;
+    static constexpr int oA = 0, ob = NX * NX, oU = ob + NX, oe = oU + tri_size(NX),
+                         oZ = oe + NX;
+    PSS_INL T A(int i, int j) const { return p[(I)(oA + i * NX + j) * ld]; }
+    PSS_INL T b(int i) const { return p[(I)(ob + i) * ld]; }
+    PSS_INL T U(int i, int j) const { return p[(I)(oU + tri_idx(i, j)) * ld]; }
+    PSS_INL T eta(int i) const { return p[(I)(oe + i) * ld]; }
+    PSS_INL T Z(int i, int j) const { return p[(I)(oZ + tri_idx(i, j)) * ld]; }
+    PSS_INL void sA(int i, int j, T v) const { p[(I)(oA + i * NX + j) * ld] = v; }
+    PSS_INL void sb(int i, T v) const { p[(I)(ob + i) * ld] = v; }
+    PSS_INL void sU(int i, int j, T v) const { p[(I)(oU + tri_idx(i, j)) * ld] = v; }
+    PSS_INL void seta(int i, T v) const { p[(I)(oe + i) * ld] = v; }
+    PSS_INL void sZ(int i, int j, T v) const { p[(I)(oZ + tri_idx(i, j)) * ld] = v; }
+};
+
+template <typename T, int NX, class VS, class VD>
+PSS_INL void felem_copy(const VS &s, const VD &d)
 {
-    T M[2 * NX][2 * NX];
-    xi_matrix(ei.U, ej.Z, M);
-    lq_rows<2 * NX, NX>(M);
-    T X11[NX][NX], X21[NX][NX], X22[NX][NX];
 #pragma unroll
-    for (int i = 0; i < NX; ++i)
+    for (int i = 0; i < NX; ++i) {
 #pragma unroll
-        for (int j = 0; j < NX; ++j) {
-            X11[i][j] = M[i][j];
-            X21[i][j] = M[NX + i][j];
-            X22[i][j] = M[NX + i][NX + j];
+        for (int j = 0; j < NX; ++j)
+            d.sA(i, j, s.A(i, j));
+        d.sb(i, s.b(i));
+        d.seta(i, s.eta(i));
+#pragma unroll
+        for (int j = 0; j <= i; ++j) {
+            d.sU(i, j, s.U(i, j));
+            d.sZ(i, j, s.Z(i, j));
         }
-    T Ui_full[NX][NX];
+    }
+}
+
+template <typename T, int NX, class V>
+PSS_INL void load_lower_U(const V &v, T (&L)[NX][NX])
+{
 #pragma unroll
     for (int i = 0; i < NX; ++i)
 #pragma unroll
         for (int j = 0; j < NX; ++j)
-            Ui_full[i][j] = (j <= i) ? ei.U[i][j] : T(0);
-    T Tm[NX][NX];
-    rsolve_lower_t(Ui_full, X11, Tm);
-    T G[NX][NX];
+            L[i][j] = (j <= i) ? v.U(i, j) : T(0);
+}
+
+template <typename T, int NX, class V>
+PSS_INL void load_lower_Z(const V &v, T (&L)[NX][NX])
+{
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+#pragma unroll
+        for (int j = 0; j < NX; ++j)
+            L[i][j] = (j <= i) ? v.Z(i, j) : T(0);
+}
+
+template <typename T, int NX, class V>
+PSS_INL void load_A(const V &v, T (&A)[NX][NX])
+{
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+#pragma unroll
+        for (int j = 0; j < NX; ++j)
+            A[i][j] = v.A(i, j);
+}
+
+// Table 3 through views.  The output is written field by field, b, U, eta,
+// Z, A, each after the last read of the input fields it may overwrite, so
+// `o` may view the same storage as `ei` or as `ej`.
+template <typename T, int NX, class VI, class VJ, class VO>
+PSS_INL void filter_combine_v(const VI &ei, const VJ &ej, const VO &o)
+{
+    // v = b_i + U_i U_i^T eta_j and q = eta_j - Z_j Z_j^T b_i need the
+    // inputs only; computing them first keeps U_i, Z_j out of the Tria below
+    T v[NX], q[NX];
+    T M[2 * NX][2 * NX];
+    {
+        T Ui[NX][NX], Zj[NX][NX], etj[NX], bi[NX];
+        load_lower_U(ei, Ui);
+        load_lower_Z(ej, Zj);
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+            etj[i] = ej.eta(i);
+            bi[i] = ei.b(i);
+        }
+        T ut[NX], uu[NX], zt[NX], zz[NX];
+        lowerT_mv(Ui, etj, ut);
+        lower_mv(Ui, ut, uu);
+        lowerT_mv(Zj, bi, zt);
+        lower_mv(Zj, zt, zz);
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+            v[i] = bi[i] + uu[i];
+            q[i] = etj[i] - zz[i];
+        }
+        // Xi = Tria([[U_i^T Z_j, I], [Z_j, 0]])
+        xi_matrix(Ui, Zj, M);
+    }
+    lq_rows<2 * NX, NX>(M);
+    // Tm = U_i Xi11^{-T}, G = I - Tm Xi21^T
+    T Tm[NX][NX], G[NX][NX];
+    {
+        T Ui[NX][NX], X11[NX][NX];
+        load_lower_U(ei, Ui);
+#pragma unroll
+        for (int i = 0; i < NX; ++i)
+#pragma unroll
+            for (int j = 0; j < NX; ++j)
+                X11[i][j] = M[i][j];
+        rsolve_lower_t(Ui, X11, Tm);
+    }
 #pragma unroll
     for (int i = 0; i < NX; ++i)
 #pragma unroll
@@ -308,87 +417,129 @@ PSS_INL void filter_combine(const FElem<T, NX> &ei, const FElem<T, NX> &ej, FEle
             T s = (i == j) ? T(1) : T(0);
 #pragma unroll
             for (int t = 0; t < NX; ++t)
-                s = pfma(-Tm[i][t], X21[j][t], s);
+                s = pfma(-Tm[i][t], M[NX + j][t], s);
             G[i][j] = s;
         }
-    T AG[NX][NX];
-    mm(ej.A, G, AG);
-    // b
-    T ut[NX], uu[NX], v[NX], w[NX];
-    lowerT_mv(ei.U, ej.eta, ut);
-    lower_mv(ei.U, ut, uu);
-#pragma unroll
-    for (int i = 0; i < NX; ++i)
-        v[i] = ei.b[i] + uu[i];
-    mv(AG, v, w);
-    // eta
-    T zt[NX], zz[NX], q[NX], gq[NX], aq[NX];
-    lowerT_mv(ej.Z, ei.b, zt);
-    lower_mv(ej.Z, zt, zz);
-#pragma unroll
-    for (int i = 0; i < NX; ++i)
-        q[i] = ej.eta[i] - zz[i];
+    T gq[NX];
     mtv(G, q, gq);
-    mtv(ei.A, gq, aq);
-    // U = Tria([A_j Tm, U_j])
-    T AT[NX][NX];
-    mm(ej.A, Tm, AT);
-    // Z = Tria([A_i^T Xi22, Z_i])
-    T AX[NX][NX];
-#pragma unroll
-    for (int a = 0; a < NX; ++a)
-#pragma unroll
-        for (int c = 0; c < NX; ++c) {
-            T s = ei.A[c][a] * X22[c][c];
-#pragma unroll
-            for (int t = c + 1; t < NX; ++t)
-                s = pfma(ei.A[t][a], X22[t][c], s);
-            AX[a][c] = s;
-        }
-    T An[NX][NX];
-    mm(AG, ei.A, An);
-#pragma unroll
-    for (int i = 0; i < NX; ++i) {
-        o.b[i] = w[i] + ej.b[i];
-        o.eta[i] = aq[i] + ei.eta[i];
+    // A_j G and A_j Tm; then b = A_j G v + b_j
+    T AG[NX][NX], AT[NX][NX];
+    {
+        T Aj[NX][NX];
+        load_A(ej, Aj);
+        mm(Aj, G, AG);
+        mm(Aj, Tm, AT);
     }
-    tria_dense_lower(AT, ej.U, o.U);
-    tria_dense_lower(AX, ei.Z, o.Z);
+    {
+        T w[NX];
+        mv(AG, v, w);
 #pragma unroll
-    for (int i = 0; i < NX; ++i)
+        for (int i = 0; i < NX; ++i)
+            o.sb(i, w[i] + ej.b(i));
+    }
+    // U = Tria([A_j Tm, U_j])
+    {
+        T Uj[NX][NX], Un[NX][NX];
+        load_lower_U(ej, Uj);
+        tria_dense_lower(AT, Uj, Un);
 #pragma unroll
-        for (int j = 0; j < NX; ++j)
-            o.A[i][j] = An[i][j];
+        for (int i = 0; i < NX; ++i)
+#pragma unroll
+            for (int j = 0; j <= i; ++j)
+                o.sU(i, j, Un[i][j]);
+    }
+    T Ai[NX][NX];
+    load_A(ei, Ai);
+    // eta = A_i^T G^T (eta_j - Z_j Z_j^T b_i) + eta_i
+    {
+        T aq[NX];
+        mtv(Ai, gq, aq);
+#pragma unroll
+        for (int i = 0; i < NX; ++i)
+            o.seta(i, aq[i] + ei.eta(i));
+    }
+    // Z = Tria([A_i^T Xi22, Z_i])
+    {
+        T AX[NX][NX];
+#pragma unroll
+        for (int a = 0; a < NX; ++a)
+#pragma unroll
+            for (int c = 0; c < NX; ++c) {
+                T s = Ai[c][a] * M[NX + c][NX + c];
+#pragma unroll
+                for (int t = c + 1; t < NX; ++t)
+                    s = pfma(Ai[t][a], M[NX + t][NX + c], s);
+                AX[a][c] = s;
+            }
+        T Zi[NX][NX], Zn[NX][NX];
+        load_lower_Z(ei, Zi);
+        tria_dense_lower(AX, Zi, Zn);
+#pragma unroll
+        for (int i = 0; i < NX; ++i)
+#pragma unroll
+            for (int j = 0; j <= i; ++j)
+                o.sZ(i, j, Zn[i][j]);
+    }
+    // A = A_j G A_i
+    {
+        T An[NX][NX];
+        mm(AG, Ai, An);
+#pragma unroll
+        for (int i = 0; i < NX; ++i)
+#pragma unroll
+            for (int j = 0; j < NX; ++j)
+                o.sA(i, j, An[i][j]);
+    }
+}
+
+template <typename T, int NX>
+PSS_INL void filter_combine(const FElem<T, NX> &ei, const FElem<T, NX> &ej, FElem<T, NX> &o)
+{
+    filter_combine_v<T, NX>(FRegV<T, NX>{const_cast<FElem<T, NX> *>(&ei)},
+                            FRegV<T, NX>{const_cast<FElem<T, NX> *>(&ej)}, FRegV<T, NX>{&o});
 }
 
 // The operator with a true prefix on the left: every prefix a_1 (x) ... (x)
 // a_k has A = 0 (A_1 = 0 in Table 1), so only its b and U, i.e. the
 // filtering marginal (m, N), matter, and the result is again such a prefix.
 // This is Table 3 with A_i = 0, b_i = m, U_i = N: the Xi22 block and the
-// eta/Z outputs drop out.
-template <typename T, int NX>
-PSS_INL void filter_apply(const Marg<T, NX> &p, const FElem<T, NX> &ej, Marg<T, NX> &o)
+// eta/Z outputs drop out.  `o` must not be `p`.
+template <typename T, int NX, class VJ>
+PSS_INL void filter_apply_v(const Marg<T, NX> &p, const VJ &ej, Marg<T, NX> &o)
 {
-    T M[2 * NX][2 * NX];
-    xi_matrix(p.N, ej.Z, M);
-    lq_rows<NX, NX>(M);
-    T X11[NX][NX], X21[NX][NX];
-#pragma unroll
-    for (int i = 0; i < NX; ++i)
-#pragma unroll
-        for (int j = 0; j < NX; ++j) {
-            X11[i][j] = M[i][j];
-            X21[i][j] = M[NX + i][j];
-        }
     T Nf[NX][NX];
 #pragma unroll
     for (int i = 0; i < NX; ++i)
 #pragma unroll
         for (int j = 0; j < NX; ++j)
             Nf[i][j] = (j <= i) ? p.N[i][j] : T(0);
-    T Tm[NX][NX];
-    rsolve_lower_t(Nf, X11, Tm);
-    T G[NX][NX];
+    T v[NX];
+    T M[2 * NX][2 * NX];
+    {
+        T Zj[NX][NX], etj[NX];
+        load_lower_Z(ej, Zj);
+#pragma unroll
+        for (int i = 0; i < NX; ++i)
+            etj[i] = ej.eta(i);
+        T ut[NX], uu[NX];
+        lowerT_mv(Nf, etj, ut);
+        lower_mv(Nf, ut, uu);
+#pragma unroll
+        for (int i = 0; i < NX; ++i)
+            v[i] = p.m[i] + uu[i];
+        xi_matrix(Nf, Zj, M);
+    }
+    lq_rows<NX, NX>(M);
+    T Tm[NX][NX], G[NX][NX];
+    {
+        T X11[NX][NX];
+#pragma unroll
+        for (int i = 0; i < NX; ++i)
+#pragma unroll
+            for (int j = 0; j < NX; ++j)
+                X11[i][j] = M[i][j];
+        rsolve_lower_t(Nf, X11, Tm);
+    }
 #pragma unroll
     for (int i = 0; i < NX; ++i)
 #pragma unroll
@@ -396,24 +547,30 @@ PSS_INL void filter_apply(const Marg<T, NX> &p, const FElem<T, NX> &ej, Marg<T, 
             T s = (i == j) ? T(1) : T(0);
 #pragma unroll
             for (int t = 0; t < NX; ++t)
-                s = pfma(-Tm[i][t], X21[j][t], s);
+                s = pfma(-Tm[i][t], M[NX + j][t], s);
             G[i][j] = s;
         }
-    T AG[NX][NX];
-    mm(ej.A, G, AG);
-    T ut[NX], uu[NX], v[NX], w[NX];
-    lowerT_mv(p.N, ej.eta, ut);
-    lower_mv(p.N, ut, uu);
-#pragma unroll
-    for (int i = 0; i < NX; ++i)
-        v[i] = p.m[i] + uu[i];
+    T AG[NX][NX], AT[NX][NX];
+    {
+        T Aj[NX][NX];
+        load_A(ej, Aj);
+        mm(Aj, G, AG);
+        mm(Aj, Tm, AT);
+    }
+    T w[NX];
     mv(AG, v, w);
 #pragma unroll
     for (int i = 0; i < NX; ++i)
-        o.m[i] = w[i] + ej.b[i];
-    T AT[NX][NX];
-    mm(ej.A, Tm, AT);
-    tria_dense_lower(AT, ej.U, o.N);
+        o.m[i] = w[i] + ej.b(i);
+    T Uj[NX][NX];
+    load_lower_U(ej, Uj);
+    tria_dense_lower(AT, Uj, o.N);
+}
+
+template <typename T, int NX>
+PSS_INL void filter_apply(const Marg<T, NX> &p, const FElem<T, NX> &ej, Marg<T, NX> &o)
+{
+    filter_apply_v<T, NX>(p, FRegV<T, NX>{const_cast<FElem<T, NX> *>(&ej)}, o);
 }
 
 // --------------------------------------------------------------------------
@@ -478,36 +635,132 @@ PSS_INL void smoother_element_last(const Marg<T, NX> &f, SElem<T, NX> &e)
     }
 }
 
+// Smoother element views (as for the filter element): registers, or a flat
+// slot with component c at p[c * ld].
+template <typename T, int NX>
+struct SRegV {
+    SElem<T, NX> *e;
+    PSS_INL T E(int i, int j) const { return e->E[i][j]; }
+    PSS_INL T g(int i) const { return e->g[i]; }
+    PSS_INL T D(int i, int j) const { return e->D[i][j]; }
+    PSS_INL void sE(int i, int j, T v) const { e->E[i][j] = v; }
+    PSS_INL void sg(int i, T v) const { e->g[i] = v; }
+    PSS_INL void sD(int i, int j, T v) const { e->D[i][j] = v; }
+};
+
+template <typename T, int NX, typename I>
+struct SSlotV {
+    T *p;
+    I ld;
+    static constexpr int oE = 0, og = NX * NX, oD = og + NX;
+    PSS_INL T E(int i, int j) const { return p[(I)(oE + i * NX + j) * ld]; }
+    PSS_INL T g(int i) const { return p[(I)(og + i) * ld]; }
+    PSS_INL T D(int i, int j) const { return p[(I)(oD + tri_idx(i, j)) * ld]; }
+    PSS_INL void sE(int i, int j, T v) const { p[(I)(oE + i * NX + j) * ld] = v; }
+    PSS_INL void sg(int i, T v) const { p[(I)(og + i) * ld] = v; }
+    PSS_INL void sD(int i, int j, T v) const { p[(I)(oD + tri_idx(i, j)) * ld] = v; }
+};
+
+template <typename T, int NX, class VS, class VD>
+PSS_INL void selem_copy(const VS &s, const VD &d)
+{
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+#pragma unroll
+        for (int j = 0; j < NX; ++j)
+            d.sE(i, j, s.E(i, j));
+        d.sg(i, s.g(i));
+#pragma unroll
+        for (int j = 0; j <= i; ++j)
+            d.sD(i, j, s.D(i, j));
+    }
+}
+
 // Lemma 4 / Table 5:  (i) (x) (j) = {E_i E_j, E_i g_j + g_i, Tria([E_i D_j, D_i])}
+// Every field of `ej` is read before the first write and each field of `ei`
+// before the write of the same field, so `o` may view `ei` or `ej`.
+template <typename T, int NX, class VI, class VJ, class VO>
+PSS_INL void smoother_combine_v(const VI &ei, const VJ &ej, const VO &o)
+{
+    T Ei[NX][NX], ED[NX][NX], Eg[NX], EE[NX][NX];
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+#pragma unroll
+        for (int j = 0; j < NX; ++j)
+            Ei[i][j] = ei.E(i, j);
+    {
+        T Dj[NX][NX], gj[NX], Ej[NX][NX];
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+            gj[i] = ej.g(i);
+#pragma unroll
+            for (int j = 0; j < NX; ++j) {
+                Dj[i][j] = (j <= i) ? ej.D(i, j) : T(0);
+                Ej[i][j] = ej.E(i, j);
+            }
+        }
+        mm_lower(Ei, Dj, ED);
+        mv(Ei, gj, Eg);
+        mm(Ei, Ej, EE);
+    }
+    {
+        T Di[NX][NX], Dn[NX][NX];
+#pragma unroll
+        for (int i = 0; i < NX; ++i)
+#pragma unroll
+            for (int j = 0; j < NX; ++j)
+                Di[i][j] = (j <= i) ? ei.D(i, j) : T(0);
+        tria_dense_lower(ED, Di, Dn);
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+            o.sg(i, Eg[i] + ei.g(i));
+#pragma unroll
+            for (int j = 0; j <= i; ++j)
+                o.sD(i, j, Dn[i][j]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+#pragma unroll
+        for (int j = 0; j < NX; ++j)
+            o.sE(i, j, EE[i][j]);
+}
+
 template <typename T, int NX>
 PSS_INL void smoother_combine(const SElem<T, NX> &ei, const SElem<T, NX> &ej, SElem<T, NX> &o)
 {
-    T ED[NX][NX], Eg[NX], EE[NX][NX];
-    mm_lower(ei.E, ej.D, ED);
-    mv(ei.E, ej.g, Eg);
-    mm(ei.E, ej.E, EE);
-    tria_dense_lower(ED, ei.D, o.D);
-#pragma unroll
-    for (int i = 0; i < NX; ++i) {
-        o.g[i] = Eg[i] + ei.g[i];
-#pragma unroll
-        for (int j = 0; j < NX; ++j)
-            o.E[i][j] = EE[i][j];
-    }
+    smoother_combine_v<T, NX>(SRegV<T, NX>{const_cast<SElem<T, NX> *>(&ei)},
+                              SRegV<T, NX>{const_cast<SElem<T, NX> *>(&ej)}, SRegV<T, NX>{&o});
 }
 
 // element (x) true suffix: a suffix a_k (x) ... (x) a_n has E = 0, so it is a
 // smoothing marginal (g, D) = (m^s, N^s); Table 5 with E_j = 0.
+template <typename T, int NX, class VI>
+PSS_INL void smoother_apply_v(const VI &ei, const Marg<T, NX> &s, Marg<T, NX> &o)
+{
+    T Ei[NX][NX], ED[NX][NX], Eg[NX], Di[NX][NX];
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+#pragma unroll
+        for (int j = 0; j < NX; ++j)
+            Ei[i][j] = ei.E(i, j);
+    mm_lower(Ei, s.N, ED);
+    mv(Ei, s.m, Eg);
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+#pragma unroll
+        for (int j = 0; j < NX; ++j)
+            Di[i][j] = (j <= i) ? ei.D(i, j) : T(0);
+    tria_dense_lower(ED, Di, o.N);
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+        o.m[i] = Eg[i] + ei.g(i);
+}
+
 template <typename T, int NX>
 PSS_INL void smoother_apply(const SElem<T, NX> &ei, const Marg<T, NX> &s, Marg<T, NX> &o)
 {
-    T ED[NX][NX], Eg[NX];
-    mm_lower(ei.E, s.N, ED);
-    mv(ei.E, s.m, Eg);
-    tria_dense_lower(ED, ei.D, o.N);
-#pragma unroll
-    for (int i = 0; i < NX; ++i)
-        o.m[i] = Eg[i] + ei.g[i];
+    smoother_apply_v<T, NX>(SRegV<T, NX>{const_cast<SElem<T, NX> *>(&ei)}, s, o);
 }
 
 // --------------------------------------------------------------------------

@@ -14,12 +14,16 @@ inline const T *cptr(const void *p) { return static_cast<const T *>(p); }
 template <typename T>
 inline T *mptr(void *p) { return static_cast<T *>(p); }
 
-// default launch shapes (overridable through pss_problem)
+// default launch shapes (overridable through pss_problem).  One 64-lane
+// wave per tile; the filter folds 4 elements per thread, the smoother 2 (its
+// operator is cheaper, and with 2 its level-0 reads and stash writes stay
+// closer to whole cache lines); the upper levels fold 2.
 template <typename T, int NX>
 struct Defaults {
-    static constexpr int T0 = (sizeof(T) == 8 && NX >= 5) ? 128 : 256;
-    static constexpr int E0 = 4;
-    static constexpr int Tup = (sizeof(T) == 8 && NX >= 5) ? 128 : 256;
+    static constexpr int T0 = 64;
+    static constexpr int E0_filter = 4;
+    static constexpr int E0_smoother = 2;
+    static constexpr int Tup = 64;
     static constexpr int Eup = 2;
 };
 
@@ -31,10 +35,12 @@ struct Core {
     static constexpr int PY = tri_size(NY);
 
     // ------------------------------------------------------------------
-    static void shapes(const Ctx &c, int &T0, int &E0, int &Tup, int &Eup)
+    static void shapes(const Ctx &c, bool smoother, int &T0, int &E0, int &Tup, int &Eup)
     {
         T0 = c.p->scan_threads > 0 ? c.p->scan_threads : Defaults<T, NX>::T0;
-        E0 = c.p->scan_elems > 0 ? c.p->scan_elems : Defaults<T, NX>::E0;
+        E0 = c.p->scan_elems > 0 ? c.p->scan_elems
+                                 : (smoother ? Defaults<T, NX>::E0_smoother
+                                             : Defaults<T, NX>::E0_filter);
         Tup = Defaults<T, NX>::Tup;
         Eup = Defaults<T, NX>::Eup;
         if (Tup > T0)
@@ -129,7 +135,10 @@ struct Core {
     }
 
     template <class Op>
-    static size_t lds_bytes(int Tb) { return (size_t)Tb * Op::NE * sizeof(T); }
+    static size_t lds_bytes(int Tb, int E, bool stage)
+    {
+        return scan_lds(Op::NE, Op::NP, Tb, E, sizeof(T), stage);
+    }
 
     template <class K>
     static int prep_lds(K kernel, size_t bytes)
@@ -160,6 +169,7 @@ struct Core {
             g.extra = extra;
             g.B = c.B;
             g.E = sh.E[l];
+            g.stage = l == 0 && scan_stage(Op::NE, Op::NP, sh.T[l], sh.E[l], sizeof(T));
             return g;
         };
         // up-sweeps of the lower levels
@@ -167,7 +177,7 @@ struct Core {
             const LevelGeom g = geom(l);
             const int64_t tree_ld = sh.ntiles[l] * sh.T[l];
             AggRef agg = agg_ref(w.agg[l + 1], sh.nelem[l + 1]);
-            const size_t lb = lds_bytes<Op>(sh.T[l]);
+            const size_t lb = lds_bytes<Op>(sh.T[l], sh.E[l], g.stage);
             KTime kt(c.s, Op::name, "up", l);
             if (l == 0) {
                 auto k = k_scan_up<Op, Src0, AggRef>;
@@ -190,7 +200,7 @@ struct Core {
         {
             const int l = sh.L - 1;
             const LevelGeom g = geom(l);
-            const size_t lb = lds_bytes<Op>(sh.T[l]);
+            const size_t lb = lds_bytes<Op>(sh.T[l], sh.E[l], g.stage);
             KTime kt(c.s, Op::name, "top", l);
             if (l == 0) {
                 auto k = k_scan_top<Op, Src0, Dst0, Start>;
@@ -214,7 +224,7 @@ struct Core {
         for (int l = sh.L - 2; l >= 0; --l) {
             const LevelGeom g = geom(l);
             const int64_t tree_ld = sh.ntiles[l] * sh.T[l];
-            const size_t lb = lds_bytes<Op>(sh.T[l]);
+            const size_t lb = lds_bytes<Op>(sh.T[l], sh.E[l], g.stage);
             MargRef<T, NX> pin = marg_ref(w.pre[l + 1], sh.nelem[l + 1]);
             KTime kt(c.s, Op::name, "down", l);
             if (l == 0) {
@@ -243,13 +253,13 @@ struct Core {
     static ScanShape filter_shape(const Ctx &c)
     {
         int T0, E0, Tup, Eup;
-        shapes(c, T0, E0, Tup, Eup);
+        shapes(c, false, T0, E0, Tup, Eup);
         return plan_scan(c, 0, T0, E0, Tup, Eup);
     }
     static ScanShape smoother_shape(const Ctx &c)
     {
         int T0, E0, Tup, Eup;
-        shapes(c, T0, E0, Tup, Eup);
+        shapes(c, true, T0, E0, Tup, Eup);
         return plan_scan(c, 1, T0, E0, Tup, Eup);
     }
 

@@ -126,6 +126,47 @@ struct SElemRef {
     }
 };
 
+// views of element t of an SoA reference (fields read and written in place)
+template <typename T, int NX>
+struct FRefV {
+    FElemRef<T, NX> r;
+    int64_t t;
+    PSS_INL T A(int i, int j) const { return r.A[(i * NX + j) * r.ld + t]; }
+    PSS_INL T b(int i) const { return r.b[i * r.ld + t]; }
+    PSS_INL T U(int i, int j) const { return r.U[tri_idx(i, j) * r.ld + t]; }
+    PSS_INL T eta(int i) const { return r.eta[i * r.ld + t]; }
+    PSS_INL T Z(int i, int j) const { return r.Z[tri_idx(i, j) * r.ld + t]; }
+    PSS_INL void sA(int i, int j, T v) const { r.A[(i * NX + j) * r.ld + t] = v; }
+    PSS_INL void sb(int i, T v) const { r.b[i * r.ld + t] = v; }
+    PSS_INL void sU(int i, int j, T v) const { r.U[tri_idx(i, j) * r.ld + t] = v; }
+    PSS_INL void seta(int i, T v) const { r.eta[i * r.ld + t] = v; }
+    PSS_INL void sZ(int i, int j, T v) const { r.Z[tri_idx(i, j) * r.ld + t] = v; }
+};
+
+template <typename T, int NX>
+struct SRefV {
+    SElemRef<T, NX> r;
+    int64_t t;
+    PSS_INL T E(int i, int j) const { return r.E[(i * NX + j) * r.ld + t]; }
+    PSS_INL T g(int i) const { return r.g[i * r.ld + t]; }
+    PSS_INL T D(int i, int j) const { return r.D[tri_idx(i, j) * r.ld + t]; }
+    PSS_INL void sE(int i, int j, T v) const { r.E[(i * NX + j) * r.ld + t] = v; }
+    PSS_INL void sg(int i, T v) const { r.g[i * r.ld + t] = v; }
+    PSS_INL void sD(int i, int j, T v) const { r.D[tri_idx(i, j) * r.ld + t] = v; }
+};
+
+template <typename T, int NX>
+PSS_INL FRefV<T, NX> view_of(const FElemRef<T, NX> &r, int64_t t)
+{
+    return FRefV<T, NX>{r, t};
+}
+
+template <typename T, int NX>
+PSS_INL SRefV<T, NX> view_of(const SElemRef<T, NX> &r, int64_t t)
+{
+    return SRefV<T, NX>{r, t};
+}
+
 // linearisation parameters (stride 0: one shared set)
 template <typename T, int NX, int NY>
 struct GammaRef {
@@ -221,6 +262,27 @@ struct FilterScan {
     static constexpr const char *name = "filter";
     PSS_INL static void combine(const Elem &a, const Elem &b, Elem &o) { filter_combine(a, b, o); }
     PSS_INL static void apply(const Pre &p, const Elem &a, Pre &o) { filter_apply(p, a, o); }
+    // view forms: `o` may view the storage of `a` or `b`
+    PSS_INL static FSlotV<T, NX, int> slot(T *lds, int Tb, int s)
+    {
+        return FSlotV<T, NX, int>{lds + s, Tb};
+    }
+    PSS_INL static FRegV<T, NX> reg(Elem &e) { return FRegV<T, NX>{&e}; }
+    template <class VA, class VB, class VO>
+    PSS_INL static void combine_v(const VA &a, const VB &b, const VO &o)
+    {
+        filter_combine_v<T, NX>(a, b, o);
+    }
+    template <class VA>
+    PSS_INL static void apply_v(const Pre &p, const VA &a, Pre &o)
+    {
+        filter_apply_v<T, NX>(p, a, o);
+    }
+    template <class VS, class VD>
+    PSS_INL static void copy_v(const VS &src, const VD &dst)
+    {
+        felem_copy<T, NX>(src, dst);
+    }
 };
 
 // Reverse associative scan of the smoother, run as a forward scan over the
@@ -236,6 +298,26 @@ struct SmootherScan {
     static constexpr const char *name = "smoother";
     PSS_INL static void combine(const Elem &a, const Elem &b, Elem &o) { smoother_combine(b, a, o); }
     PSS_INL static void apply(const Pre &p, const Elem &a, Pre &o) { smoother_apply(a, p, o); }
+    PSS_INL static SSlotV<T, NX, int> slot(T *lds, int Tb, int s)
+    {
+        return SSlotV<T, NX, int>{lds + s, Tb};
+    }
+    PSS_INL static SRegV<T, NX> reg(Elem &e) { return SRegV<T, NX>{&e}; }
+    template <class VA, class VB, class VO>
+    PSS_INL static void combine_v(const VA &a, const VB &b, const VO &o)
+    {
+        smoother_combine_v<T, NX>(b, a, o);
+    }
+    template <class VA>
+    PSS_INL static void apply_v(const Pre &p, const VA &a, Pre &o)
+    {
+        smoother_apply_v<T, NX>(a, p, o);
+    }
+    template <class VS, class VD>
+    PSS_INL static void copy_v(const VS &src, const VD &dst)
+    {
+        selem_copy<T, NX>(src, dst);
+    }
 };
 
 // LDS object access, component-major
@@ -268,11 +350,8 @@ PSS_INL void tree_up(typename Op::T *lds, int Tb, int nvalid)
             const int r = (j + 1) * 2 * d - 1, l = r - d;
             if (r - 2 * d + 1 < nvalid) {
                 if (r - d + 1 < nvalid) {
-                    typename Op::Elem a, b, c;
-                    lds_get(a, lds, Tb, l);
-                    lds_get(b, lds, Tb, r);
-                    Op::combine(a, b, c);
-                    lds_put(c, lds, Tb, r);
+                    // slot r <- slot l (x) slot r, operands read in place
+                    Op::combine_v(Op::slot(lds, Tb, l), Op::slot(lds, Tb, r), Op::slot(lds, Tb, r));
                 } else {
                     for (int c = 0; c < Op::NE; ++c)
                         lds[c * Tb + r] = lds[c * Tb + l];
@@ -301,15 +380,14 @@ PSS_INL void tree_down(typename Op::T *lds, int Tb, int nvalid, const typename O
             const int r = (j + 1) * 2 * d - 1, l = r - d;
             if (r - 2 * d + 1 < nvalid) {
                 typename Op::Pre P;
-                typename Op::Elem a;
                 lds_get(P, lds, Tb, r);
-                lds_get(a, lds, Tb, l);
-                lds_put(P, lds, Tb, l);
                 if (r - d + 1 < nvalid) {
+                    // the element in slot l is read before P overwrites it
                     typename Op::Pre Q;
-                    Op::apply(P, a, Q);
+                    Op::apply_v(P, Op::slot(lds, Tb, l), Q);
                     lds_put(Q, lds, Tb, r);
                 }
+                lds_put(P, lds, Tb, l);
             }
         }
     }
@@ -325,6 +403,8 @@ struct LevelGeom {
     int extra; // level 0: elements per sequence = n_b + extra, element offset y_off[b] + extra*b
     int B;
     int E;
+    int stage; // outputs staged in LDS and written by the whole block (needs
+               // NP * T * E values of LDS)
 };
 
 PSS_INL void seq_range(const LevelGeom &g, int b, int64_t &off, int64_t &cnt)
@@ -342,8 +422,25 @@ PSS_INL void seq_range(const LevelGeom &g, int b, int64_t &off, int64_t &cnt)
 struct TileInfo {
     int b;
     int64_t off, cnt, start;
-    int tcnt, nvalid;
+    int tcnt, nvalid, E;
 };
+
+// Tile-interleaved position of the tile's element q (thread q / E, its j-th
+// element, j = q % E): the j-th elements of all threads are contiguous, so a
+// wave's j-th accesses touch consecutive words.  A bijection of [0, tcnt)
+// also for a ragged last tile, whose last thread holds r <= E elements.
+PSS_INL int ilv(int q, int tcnt, int E)
+{
+    const int nv = (tcnt + E - 1) / E, r = tcnt - (nv - 1) * E;
+    const int t = q / E, j = q - t * E;
+    return j < r ? j * nv + t : r * nv + (j - r) * (nv - 1) + t;
+}
+
+// slot of element p of the tile's sequence in storage private to the scan
+PSS_INL int64_t ilv_slot(const TileInfo &ti, int64_t p)
+{
+    return ti.off + ti.start + ilv((int)(p - ti.start), ti.tcnt, ti.E);
+}
 
 PSS_INL TileInfo tile_info(const LevelGeom &g)
 {
@@ -357,62 +454,68 @@ PSS_INL TileInfo tile_info(const LevelGeom &g)
     const int64_t rem = ti.cnt - ti.start;
     ti.tcnt = (int)(rem < TS ? rem : TS);
     ti.nvalid = (ti.tcnt + g.E - 1) / g.E;
+    ti.E = g.E;
     return ti;
 }
 
 // --- element sources --------------------------------------------------------
 // plain SoA source (filter elements, or aggregates of a level below)
+// A source either builds element p in registers (up / down) or, when
+// lazy_up / lazy_down is set, hands out a view of it (uview / dview) that the
+// operators read field by field.
 template <class Op, class Ref>
 struct RefSrc {
+    static constexpr bool lazy_up = true, lazy_down = true;
     Ref ref;
-    PSS_INL void up(int b, int64_t off, int64_t cnt, int64_t p, typename Op::Elem &e) const
-    {
-        ref.load(off + p, e);
-    }
-    PSS_INL void down(int b, int64_t off, int64_t cnt, int64_t p, typename Op::Elem &e) const
-    {
-        ref.load(off + p, e);
-    }
+    PSS_INL auto uview(const TileInfo &ti, int64_t p) const { return view_of(ref, ti.off + p); }
+    PSS_INL auto dview(const TileInfo &ti, int64_t p) const { return view_of(ref, ti.off + p); }
 };
 
 // smoother level 0: element of state k = n - p built from the transition
 // linearisation of slot (b, k) and the filtering marginal at k (Table 4),
-// stashed at its state slot during the up phase and re-read afterwards.
+// stashed (tile-interleaved) during the up phase and re-read afterwards.
 template <typename T, int NX, int NY>
 struct SmootherSrc {
+    static constexpr bool lazy_up = false, lazy_down = true;
     GammaRef<T, NX, NY> gam;
     MargRef<T, NX> filt; // ld = T_x
     SElemRef<T, NX> stash; // ld = T_x
     const int64_t *y_off;
-    PSS_INL void up(int b, int64_t off, int64_t cnt, int64_t p, SElem<T, NX> &e) const
+    PSS_INL void up(const TileInfo &ti, int64_t p, SElem<T, NX> &e) const
     {
-        const int64_t n = cnt - 1, k = n - p;
+        const int64_t n = ti.cnt - 1, k = n - p;
         Marg<T, NX> f;
-        filt.load(off + k, f);
+        filt.load(ti.off + k, f);
         if (k == n) {
             smoother_element_last(f, e);
         } else {
             T F[NX][NX], c[NX], S[NX][NX];
-            gam.load_trans(y_off[b] + k, F, c, S);
+            gam.load_trans(y_off[ti.b] + k, F, c, S);
             smoother_element(F, c, S, f, e);
         }
-        stash.store(off + k, e);
+        stash.store(ilv_slot(ti, p), e);
     }
-    PSS_INL void down(int b, int64_t off, int64_t cnt, int64_t p, SElem<T, NX> &e) const
+    PSS_INL SRefV<T, NX> dview(const TileInfo &ti, int64_t p) const
     {
-        stash.load(off + (cnt - 1 - p), e);
+        return view_of(stash, ilv_slot(ti, p));
     }
 };
 
 // --- output sinks -------------------------------------------------------------
+// put(ti, p, excl, incl) receives the exclusive and inclusive prefix of
+// element p.  A sink with `stageable` also has first(ti, excl), called with
+// the exclusive prefix of a sequence's first element, and store(ti, p, incl):
+// apply_phase may then collect a tile's inclusive prefixes in LDS and store
+// them with consecutive lanes on consecutive elements.
 // levels >= 1: exclusive prefix of each element
 template <class Op, class Ref>
 struct PreDst {
+    static constexpr bool stageable = false;
     Ref ref;
-    PSS_INL void put(int b, int64_t off, int64_t cnt, int64_t p, const typename Op::Pre &excl,
+    PSS_INL void put(const TileInfo &ti, int64_t p, const typename Op::Pre &excl,
                      const typename Op::Pre &incl) const
     {
-        ref.store(off + p, excl);
+        ref.store(ti.off + p, excl);
     }
 };
 
@@ -421,15 +524,23 @@ struct PreDst {
 // prior)
 template <typename T, int NX>
 struct FiltDst {
+    static constexpr bool stageable = true;
     MargRef<T, NX> out; // ld = T_x
     const int64_t *y_off;
-    PSS_INL void put(int b, int64_t off, int64_t cnt, int64_t p, const Marg<T, NX> &excl,
+    PSS_INL void first(const TileInfo &ti, const Marg<T, NX> &excl) const
+    {
+        out.store(y_off[ti.b] + ti.b, excl);
+    }
+    PSS_INL void store(const TileInfo &ti, int64_t p, const Marg<T, NX> &incl) const
+    {
+        out.store(y_off[ti.b] + ti.b + p + 1, incl);
+    }
+    PSS_INL void put(const TileInfo &ti, int64_t p, const Marg<T, NX> &excl,
                      const Marg<T, NX> &incl) const
     {
-        const int64_t x0 = y_off[b] + b;
         if (p == 0)
-            out.store(x0, excl);
-        out.store(x0 + p + 1, incl);
+            first(ti, excl);
+        store(ti, p, incl);
     }
 };
 
@@ -437,11 +548,17 @@ struct FiltDst {
 // of state n - p
 template <typename T, int NX>
 struct SmoothDst {
+    static constexpr bool stageable = true;
     MargRef<T, NX> out;
-    PSS_INL void put(int b, int64_t off, int64_t cnt, int64_t p, const Marg<T, NX> &excl,
+    PSS_INL void first(const TileInfo &ti, const Marg<T, NX> &excl) const {}
+    PSS_INL void store(const TileInfo &ti, int64_t p, const Marg<T, NX> &incl) const
+    {
+        out.store(ti.off + (ti.cnt - 1 - p), incl);
+    }
+    PSS_INL void put(const TileInfo &ti, int64_t p, const Marg<T, NX> &excl,
                      const Marg<T, NX> &incl) const
     {
-        out.store(off + (cnt - 1 - p), incl);
+        store(ti, p, incl);
     }
 };
 
@@ -466,6 +583,45 @@ struct StartPre {
 // ---------------------------------------------------------------------------
 // scan kernels
 // ---------------------------------------------------------------------------
+template <class Op, class Src, class V>
+PSS_INL void src_first(const Src &src, const TileInfo &ti, int64_t p, const V &acc)
+{
+    if constexpr (Src::lazy_up) {
+        Op::copy_v(src.uview(ti, p), acc);
+    } else {
+        typename Op::Elem e;
+        src.up(ti, p, e);
+        Op::copy_v(Op::reg(e), acc);
+    }
+}
+
+template <class Op, class Src, class V>
+PSS_INL void src_fold(const Src &src, const TileInfo &ti, int64_t p, const V &acc)
+{
+    if constexpr (Src::lazy_up) {
+        Op::combine_v(acc, src.uview(ti, p), acc);
+    } else {
+        typename Op::Elem e;
+        src.up(ti, p, e);
+        Op::combine_v(acc, Op::reg(e), acc);
+    }
+}
+
+template <class Op, class Src>
+PSS_INL void src_apply(const Src &src, const TileInfo &ti, int64_t p, const typename Op::Pre &P,
+                       typename Op::Pre &Q)
+{
+    if constexpr (Src::lazy_down) {
+        Op::apply_v(P, src.dview(ti, p), Q);
+    } else {
+        typename Op::Elem e;
+        src.down(ti, p, e);
+        Op::apply_v(P, Op::reg(e), Q);
+    }
+}
+
+// thread t folds its elements left to right into its own LDS slot (the slot
+// doubles as the accumulator, so it never occupies registers)
 template <class Op, class Src>
 PSS_INL void fold_phase(const LevelGeom &g, const TileInfo &ti, const Src &src,
                         typename Op::T *lds, int Tb)
@@ -476,36 +632,59 @@ PSS_INL void fold_phase(const LevelGeom &g, const TileInfo &ti, const Src &src,
         int64_t pe = p0 + g.E;
         if (pe > ti.start + ti.tcnt)
             pe = ti.start + ti.tcnt;
-        typename Op::Elem acc;
-        src.up(ti.b, ti.off, ti.cnt, p0, acc);
-        for (int64_t p = p0 + 1; p < pe; ++p) {
-            typename Op::Elem e, o;
-            src.up(ti.b, ti.off, ti.cnt, p, e);
-            Op::combine(acc, e, o);
-            acc = o;
-        }
-        lds_put(acc, lds, Tb, tid);
+        const auto acc = Op::slot(lds, Tb, tid);
+        src_first<Op>(src, ti, p0, acc);
+        for (int64_t p = p0 + 1; p < pe; ++p)
+            src_fold<Op>(src, ti, p, acc);
     }
 }
 
+// Thread t walks its elements again from its exclusive prefix (left in its
+// LDS slot by the down-sweep).  With g.stage (stageable sinks only) the
+// inclusive prefixes are first collected in LDS, component-major over the
+// tile's elements, and then stored by the whole block, consecutive lanes on
+// consecutive elements; the block must call this uniformly.
 template <class Op, class Src, class Dst>
 PSS_INL void apply_phase(const LevelGeom &g, const TileInfo &ti, const Src &src, const Dst &dst,
                          typename Op::T *lds, int Tb)
 {
     const int tid = threadIdx.x;
-    if (tid < ti.nvalid) {
-        typename Op::Pre P;
+    const bool act = tid < ti.nvalid;
+    const int64_t p0 = ti.start + (int64_t)tid * g.E;
+    int64_t pe = p0 + g.E;
+    if (pe > ti.start + ti.tcnt)
+        pe = ti.start + ti.tcnt;
+    typename Op::Pre P;
+    if (act)
         lds_get(P, lds, Tb, tid);
-        const int64_t p0 = ti.start + (int64_t)tid * g.E;
-        int64_t pe = p0 + g.E;
-        if (pe > ti.start + ti.tcnt)
-            pe = ti.start + ti.tcnt;
+    if constexpr (Dst::stageable) {
+        if (g.stage) {
+            const int ld = Tb * g.E;
+            __syncthreads(); // every prefix is in registers: LDS is free
+            if (act) {
+                for (int64_t p = p0; p < pe; ++p) {
+                    typename Op::Pre Q;
+                    src_apply<Op>(src, ti, p, P, Q);
+                    if (p == 0)
+                        dst.first(ti, P);
+                    lds_put(Q, lds, ld, (int)(p - ti.start));
+                    P = Q;
+                }
+            }
+            __syncthreads();
+            for (int q = tid; q < ti.tcnt; q += Tb) {
+                typename Op::Pre x;
+                lds_get(x, lds, ld, q);
+                dst.store(ti, ti.start + q, x);
+            }
+            return;
+        }
+    }
+    if (act) {
         for (int64_t p = p0; p < pe; ++p) {
-            typename Op::Elem e;
             typename Op::Pre Q;
-            src.down(ti.b, ti.off, ti.cnt, p, e);
-            Op::apply(P, e, Q);
-            dst.put(ti.b, ti.off, ti.cnt, p, P, Q);
+            src_apply<Op>(src, ti, p, P, Q);
+            dst.put(ti, p, P, Q);
             P = Q;
         }
     }
@@ -527,11 +706,8 @@ __global__ __launch_bounds__(256) void k_scan_up(LevelGeom g, Src src, AggRef ag
     const int64_t base = (int64_t)blockIdx.x * Tb + threadIdx.x;
     for (int c = 0; c < Op::NE; ++c)
         tree[c * tree_ld + base] = lds[c * Tb + threadIdx.x];
-    if (threadIdx.x == 0) {
-        typename Op::Elem a;
-        lds_get(a, lds, Tb, Tb - 1);
-        agg.store(blockIdx.x, a);
-    }
+    if (threadIdx.x == 0)
+        Op::copy_v(Op::slot(lds, Tb, Tb - 1), view_of(agg, (int64_t)blockIdx.x));
 }
 
 // lower levels, second half: restore the tree, down-sweep from the tile's

@@ -250,6 +250,8 @@ int run(const pss_group *gs, int ng, int n_iter, int32_t *status, void *ws, size
         G.B = p->B;
         G.E_f = sh.E_f;
         G.E_s = sh.E_s;
+        G.stage_f = scan_stage(65, 20, sh.T, sh.E_f, sizeof(T));
+        G.stage_s = scan_stage(45, 20, sh.T, sh.E_s, sizeof(T));
         G.y_off = p->y_off;
         G.T_y = c.T_y;
         G.T_x = c.T_x;
@@ -302,7 +304,10 @@ int run(const pss_group *gs, int ng, int n_iter, int32_t *status, void *ws, size
     a.total_items = item;
 
     auto kern = k_ipls_persistent<T>;
-    const size_t lds = (size_t)sh.T * 65 * sizeof(T);
+    // sized for the largest objects (coordinated-turn filter / smoother)
+    size_t lds = scan_lds(65, 20, sh.T, sh.E_f, sizeof(T), scan_stage(65, 20, sh.T, sh.E_f, sizeof(T)));
+    lds = std::max(lds, scan_lds(45, 20, sh.T, sh.E_s, sizeof(T),
+                                 scan_stage(45, 20, sh.T, sh.E_s, sizeof(T))));
     int rc = hip_check(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
                        "hipFuncSetAttribute");

@@ -31,6 +31,7 @@ struct PGroup {
     int kind;
     int B;
     int E_f, E_s;
+    int stage_f, stage_s; // outputs staged through LDS (see apply_phase)
     const int64_t *y_off;
     int64_t T_y, T_x;
     const T *y;
@@ -171,9 +172,9 @@ template <typename T, int NX, int NY, bool CT>
 struct FusedFiltSrc {
     const PGroup<T> *G;
     int64_t x0; // first state slot of the sequence
-    PSS_INL void up(int b, int64_t off, int64_t cnt, int64_t p, FElem<T, NX> &e) const
+    PSS_INL void up(const TileInfo &ti, int64_t p, FElem<T, NX> &e) const
     {
-        const int64_t s = off + p;
+        const int64_t s = ti.off + p;
         T F[NX][NX], c[NX], SL[NX][NX], H[NY][NX], d[NY], SO[NY][NY], yy[NY];
 #pragma unroll
         for (int a = 0; a < NY; ++a)
@@ -215,11 +216,12 @@ struct FusedFiltSrc {
         } else {
             filter_element(F, c, SL, H, d, SO, yy, e);
         }
-        felem_ref_dev<T, NX>(G->fstash, G->T_y).store(s, e);
+        felem_ref_dev<T, NX>(G->fstash, G->T_y).store(ilv_slot(ti, p), e);
     }
-    PSS_INL void down(int b, int64_t off, int64_t cnt, int64_t p, FElem<T, NX> &e) const
+    static constexpr bool lazy_up = false, lazy_down = true;
+    PSS_INL FRefV<T, NX> dview(const TileInfo &ti, int64_t p) const
     {
-        felem_ref_dev<T, NX>(G->fstash, G->T_y).load(off + p, e);
+        return view_of(felem_ref_dev<T, NX>(G->fstash, G->T_y), ilv_slot(ti, p));
     }
 };
 
@@ -229,11 +231,11 @@ template <typename T, int NX, int NY, bool CT>
 struct FusedSmoothSrc {
     const PGroup<T> *G;
     int64_t ybase; // y_off[b]
-    PSS_INL void up(int b, int64_t off, int64_t cnt, int64_t p, SElem<T, NX> &e) const
+    PSS_INL void up(const TileInfo &ti, int64_t p, SElem<T, NX> &e) const
     {
-        const int64_t n = cnt - 1, k = n - p;
+        const int64_t n = ti.cnt - 1, k = n - p;
         Marg<T, NX> f;
-        pre_ref<T, NX>(G->mf, G->T_x).load(off + k, f);
+        pre_ref<T, NX>(G->mf, G->T_x).load(ti.off + k, f);
         if (k == n) {
             smoother_element_last(f, e);
         } else {
@@ -254,11 +256,12 @@ struct FusedSmoothSrc {
             }
             smoother_element(F, c, SL, f, e);
         }
-        selem_ref_dev<T, NX>(G->sstash, G->T_x).store(off + k, e);
+        selem_ref_dev<T, NX>(G->sstash, G->T_x).store(ilv_slot(ti, p), e);
     }
-    PSS_INL void down(int b, int64_t off, int64_t cnt, int64_t p, SElem<T, NX> &e) const
+    static constexpr bool lazy_up = false, lazy_down = true;
+    PSS_INL SRefV<T, NX> dview(const TileInfo &ti, int64_t p) const
     {
-        selem_ref_dev<T, NX>(G->sstash, G->T_x).load(off + (cnt - 1 - p), e);
+        return view_of(selem_ref_dev<T, NX>(G->sstash, G->T_x), ilv_slot(ti, p));
     }
 };
 
@@ -277,6 +280,7 @@ PSS_INL void filter_tile(const PArgs<T> &a, const PGroup<T> &G, int64_t gt, T *l
     g.extra = 0;
     g.B = G.B;
     g.E = G.E_f;
+    g.stage = G.stage_f;
     TileInfo ti;
     ti.b = b;
     seq_range(g, b, ti.off, ti.cnt);
@@ -285,6 +289,7 @@ PSS_INL void filter_tile(const PArgs<T> &a, const PGroup<T> &G, int64_t gt, T *l
     const int64_t rem = ti.cnt - ti.start;
     ti.tcnt = (int)(rem < TS ? rem : TS);
     ti.nvalid = (ti.tcnt + g.E - 1) / g.E;
+    ti.E = g.E;
     const int Tb = blockDim.x;
     FusedFiltSrc<T, NX, NY, CT> src{&G, G.y_off[b] + b};
     fold_phase<Op>(g, ti, src, lds, Tb);
@@ -299,10 +304,8 @@ PSS_INL void filter_tile(const PArgs<T> &a, const PGroup<T> &G, int64_t gt, T *l
                 atomicOr(a.error, 1);
             pub.load(gt - 1, excl);
         }
-        typename Op::Elem agg;
-        lds_get(agg, lds, Tb, Tb - 1);
         typename Op::Pre incl;
-        Op::apply(excl, agg, incl);
+        Op::apply_v(excl, Op::slot(lds, Tb, Tb - 1), incl);
         pub.store(gt, incl);
         flag_store(G.flag_f + gt, 1);
     }
@@ -329,6 +332,7 @@ PSS_INL void smoother_tile(const PArgs<T> &a, const PGroup<T> &G, int64_t gu, T 
     g.extra = 1;
     g.B = G.B;
     g.E = G.E_s;
+    g.stage = G.stage_s;
     TileInfo ti;
     ti.b = b;
     seq_range(g, b, ti.off, ti.cnt);
@@ -337,6 +341,7 @@ PSS_INL void smoother_tile(const PArgs<T> &a, const PGroup<T> &G, int64_t gu, T 
     const int64_t rem = ti.cnt - ti.start;
     ti.tcnt = (int)(rem < TS ? rem : TS);
     ti.nvalid = (ti.tcnt + g.E - 1) / g.E;
+    ti.E = g.E;
     const int Tb = blockDim.x;
     const int64_t n = ti.cnt - 1;
     // states [klo, khi] of this tile; wait for the filter tiles that wrote
@@ -366,10 +371,8 @@ PSS_INL void smoother_tile(const PArgs<T> &a, const PGroup<T> &G, int64_t gu, T 
                 atomicOr(a.error, 4);
             pub.load(gu - 1, excl);
         }
-        typename Op::Elem agg;
-        lds_get(agg, lds, Tb, Tb - 1);
         typename Op::Pre incl;
-        Op::apply(excl, agg, incl);
+        Op::apply_v(excl, Op::slot(lds, Tb, Tb - 1), incl);
         pub.store(gu, incl);
         flag_store(G.flag_s + gu, 1);
     }
