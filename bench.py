@@ -382,11 +382,11 @@ def main():
             assert rc == 0, pss.last_error()
 
         reps = 5 if n >= 10 ** 5 else 20
-        # per-kernel durations, HIP events on the launch stream
+        # per-kernel durations inside the step itself (eager, same launches as
+        # the captured graph), HIP events on the launch stream
         pss.kernel_timing(True)
-        for _ in range(reps):
-            fscan()
-            sscan()
+        for _ in range(2):
+            R.step()
         torch.cuda.synchronize()
         ktimes = pss.kernel_times()
         pss.kernel_timing(False)
@@ -404,6 +404,8 @@ def main():
         kflops.update(scan_kernel_flops(
             "smoother", [n + 1], *shapes(args.dtype, args.scan_threads, args.scan_elems, True)))
         E0s = shapes(args.dtype, args.scan_threads, args.scan_elems, True)[1]
+        kflops[("slr", 0)] = n * (FLOPS["slr_transition"] + FLOPS["slr_bearings"])
+        kflops[("filter_elements", 0)] = n * FLOPS["filter_element"]
         kernels = {}
         for key, (calls, tot) in sorted(ktimes.items()):
             avg = tot / calls
@@ -412,7 +414,7 @@ def main():
                 "launches": calls, "avg_ms": round(avg, 5),
                 "flops_per_launch": fl_k,
                 "tflops": None if fl_k is None else round(fl_k / (avg * 1e-3) / 1e12, 4)}
-        dom = max(ktimes, key=lambda k: ktimes[k][1])
+        dom = max((k for k in ktimes if k in kflops), key=lambda k: ktimes[k][1])
         dom_ms = ktimes[dom][1] / ktimes[dom][0]
         fl = kflops[dom]
         achieved = fl / (dom_ms * 1e-3) / 1e12

@@ -277,7 +277,10 @@ struct Core {
         return cv.used;
     }
 
-    static int fscan(const Ctx &c, const pss_felem *el, void *mf, void *Nf, void *ws)
+    // ilv: the elements are stored tile-interleaved for this scan's level 0
+    // (as written by felem(..., true)); the library's own passes use that
+    static int fscan(const Ctx &c, const pss_felem *el, void *mf, void *Nf, void *ws,
+                     bool ilv = false)
     {
         const ScanShape sh = filter_shape(c);
         Carver cv{static_cast<char *>(ws)};
@@ -289,9 +292,13 @@ struct Core {
         er.eta = mptr<T>(el->eta);
         er.Z = mptr<T>(el->Z);
         er.ld = c.T_y;
-        RefSrc<FS, FElemRef<T, NX>> src{er};
         FiltDst<T, NX> dst{marg_ref2(mf, Nf, c.T_x), c.p->y_off};
         StartPre<T, NX> st{cptr<T>(c.p->m0), cptr<T>(c.p->N0)};
+        if (ilv) {
+            RefSrc<FS, FElemRef<T, NX>, true> src{er};
+            return run_scan<FS>(c, sh, w, 0, src, dst, st, &felem_ref);
+        }
+        RefSrc<FS, FElemRef<T, NX>> src{er};
         return run_scan<FS>(c, sh, w, 0, src, dst, st, &felem_ref);
     }
 
@@ -309,8 +316,15 @@ struct Core {
         return run_scan<SS>(c, sh, w, 1, src, dst, st, &selem_ref);
     }
 
-    static int felem(const Ctx &c, const pss_gamma *g, const void *y, const pss_felem *out)
+    static int felem(const Ctx &c, const pss_gamma *g, const void *y, const pss_felem *out,
+                     bool ilv = false)
     {
+        int ilv_T = 0, ilv_E = 0;
+        if (ilv) {
+            const ScanShape sh = filter_shape(c);
+            ilv_T = sh.T[0];
+            ilv_E = sh.E[0];
+        }
         FElemRef<T, NX> er;
         er.A = mptr<T>(out->A);
         er.b = mptr<T>(out->b);
@@ -322,7 +336,7 @@ struct Core {
         KTime kt(c.s, "filter_elements", "", 0);
         hipLaunchKernelGGL((k_filter_elements<T, NX, NY>), dim3((unsigned)((c.T_y + tb - 1) / tb)),
                            dim3(tb), 0, c.s, c.p->y_off, c.B, c.T_y, gamma_ref(g, c.T_y),
-                           cptr<T>(y), cptr<T>(c.p->m0), cptr<T>(c.p->N0), er);
+                           cptr<T>(y), cptr<T>(c.p->m0), cptr<T>(c.p->N0), er, ilv_T, ilv_E);
         return hip_check(hipGetLastError(), "filter elements launch");
     }
 
@@ -397,9 +411,9 @@ struct Core {
         for (int it = 0; it < n_iter && rc == PSS_OK; ++it) {
             if (is_ct(c) && (rc = slr(c, m_nom, N_nom, y, &gw)))
                 break;
-            if ((rc = felem(c, g, y, &el)))
+            if ((rc = felem(c, g, y, &el, true)))
                 break;
-            if ((rc = fscan(c, &el, mf, Nf, scan_ws)))
+            if ((rc = fscan(c, &el, mf, Nf, scan_ws, true)))
                 break;
             rc = sscan(c, g, mf, Nf, m_nom, N_nom, scan_ws);
         }
@@ -424,9 +438,9 @@ struct Core {
         int rc;
         if (is_ct(c) && (rc = slr(c, m_nom, N_nom, y, &gw)))
             return rc;
-        if ((rc = felem(c, g, y, &el)))
+        if ((rc = felem(c, g, y, &el, true)))
             return rc;
-        if ((rc = fscan(c, &el, mfb, mfb + (size_t)NX * c.T_x, scan_ws)))
+        if ((rc = fscan(c, &el, mfb, mfb + (size_t)NX * c.T_x, scan_ws, true)))
             return rc;
         const int tb = 128;
         KTime kt(c.s, "loglik_terms", "", 0);

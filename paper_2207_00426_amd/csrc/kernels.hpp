@@ -436,6 +436,22 @@ PSS_INL int ilv(int q, int tcnt, int E)
     return j < r ? j * nv + t : r * nv + (j - r) * (nv - 1) + t;
 }
 
+// inverse of ilv: the tile element stored at interleaved position r
+PSS_INL int ilv_inv(int r, int tcnt, int E)
+{
+    const int nv = (tcnt + E - 1) / E, rr = tcnt - (nv - 1) * E;
+    int t, j;
+    if (r < rr * nv) {
+        j = r / nv;
+        t = r - j * nv;
+    } else {
+        const int r2 = r - rr * nv;
+        j = rr + r2 / (nv - 1);
+        t = r2 - (j - rr) * (nv - 1);
+    }
+    return t * E + j;
+}
+
 // slot of element p of the tile's sequence in storage private to the scan
 PSS_INL int64_t ilv_slot(const TileInfo &ti, int64_t p)
 {
@@ -463,12 +479,17 @@ PSS_INL TileInfo tile_info(const LevelGeom &g)
 // A source either builds element p in registers (up / down) or, when
 // lazy_up / lazy_down is set, hands out a view of it (uview / dview) that the
 // operators read field by field.
-template <class Op, class Ref>
+// (ILV: the level's elements are stored tile-interleaved, see ilv)
+template <class Op, class Ref, bool ILV = false>
 struct RefSrc {
     static constexpr bool lazy_up = true, lazy_down = true;
     Ref ref;
-    PSS_INL auto uview(const TileInfo &ti, int64_t p) const { return view_of(ref, ti.off + p); }
-    PSS_INL auto dview(const TileInfo &ti, int64_t p) const { return view_of(ref, ti.off + p); }
+    PSS_INL int64_t slot(const TileInfo &ti, int64_t p) const
+    {
+        return ILV ? ilv_slot(ti, p) : ti.off + p;
+    }
+    PSS_INL auto uview(const TileInfo &ti, int64_t p) const { return view_of(ref, slot(ti, p)); }
+    PSS_INL auto dview(const TileInfo &ti, int64_t p) const { return view_of(ref, slot(ti, p)); }
 };
 
 // smoother level 0: element of state k = n - p built from the transition
@@ -620,8 +641,16 @@ PSS_INL void src_apply(const Src &src, const TileInfo &ti, int64_t p, const type
     }
 }
 
-// thread t folds its elements left to right into its own LDS slot (the slot
-// doubles as the accumulator, so it never occupies registers)
+// Thread t folds its elements left to right.  The accumulator stays in
+// registers when the element is small (FP32); an FP64 filter element would
+// not fit beside the operator's work space, so there the thread's LDS slot
+// doubles as the accumulator.  Either way the fold ends in that slot.
+template <class Op>
+constexpr bool reg_accumulator()
+{
+    return sizeof(typename Op::T) * Op::NE <= 260;
+}
+
 template <class Op, class Src>
 PSS_INL void fold_phase(const LevelGeom &g, const TileInfo &ti, const Src &src,
                         typename Op::T *lds, int Tb)
@@ -632,10 +661,19 @@ PSS_INL void fold_phase(const LevelGeom &g, const TileInfo &ti, const Src &src,
         int64_t pe = p0 + g.E;
         if (pe > ti.start + ti.tcnt)
             pe = ti.start + ti.tcnt;
-        const auto acc = Op::slot(lds, Tb, tid);
-        src_first<Op>(src, ti, p0, acc);
-        for (int64_t p = p0 + 1; p < pe; ++p)
-            src_fold<Op>(src, ti, p, acc);
+        if constexpr (reg_accumulator<Op>()) {
+            typename Op::Elem a;
+            const auto acc = Op::reg(a);
+            src_first<Op>(src, ti, p0, acc);
+            for (int64_t p = p0 + 1; p < pe; ++p)
+                src_fold<Op>(src, ti, p, acc);
+            lds_put(a, lds, Tb, tid);
+        } else {
+            const auto acc = Op::slot(lds, Tb, tid);
+            src_first<Op>(src, ti, p0, acc);
+            for (int64_t p = p0 + 1; p < pe; ++p)
+                src_fold<Op>(src, ti, p, acc);
+        }
     }
 }
 
@@ -767,13 +805,23 @@ template <typename T, int NX, int NY>
 __global__ __launch_bounds__(128) void k_filter_elements(const int64_t *y_off, int B, int64_t T_y,
                                                          GammaRef<T, NX, NY> gam, const T *y,
                                                          const T *m0, const T *N0,
-                                                         FElemRef<T, NX> out)
+                                                         FElemRef<T, NX> out, int ilv_T,
+                                                         int ilv_E)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= T_y)
+    // thread i fills stored slot i; with ilv_E > 0 the elements are stored
+    // tile-interleaved for a level-0 filter scan of ilv_T threads x ilv_E
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= T_y)
         return;
-    const int b = find_seq(y_off, B, t, 0);
-    const int64_t k = t - y_off[b];
+    const int b = find_seq(y_off, B, i, 0);
+    int64_t k = i - y_off[b];
+    if (ilv_E > 0) {
+        const int64_t TS = (int64_t)ilv_T * ilv_E, cnt = y_off[b + 1] - y_off[b];
+        const int64_t start = (k / TS) * TS;
+        const int tcnt = (int)((cnt - start) < TS ? (cnt - start) : TS);
+        k = start + ilv_inv((int)(k - start), tcnt, ilv_E);
+    }
+    const int64_t t = y_off[b] + k; // logical step slot
     T F[NX][NX], c[NX], SL[NX][NX], H[NY][NX], d[NY], SO[NY][NY], yy[NY];
     gam.load_trans(t, F, c, SL);
     gam.load_obs(t, H, d, SO);
@@ -794,7 +842,7 @@ __global__ __launch_bounds__(128) void k_filter_elements(const int64_t *y_off, i
     } else {
         filter_element(F, c, SL, H, d, SO, yy, e);
     }
-    out.store(t, e);
+    out.store(i, e);
 }
 
 // pseudo-log-likelihood terms (Section 5.1) from the filtering marginal of the
