@@ -232,6 +232,7 @@ int run(const pss_group *gs, int ng, int n_iter, int32_t *status, void *ws, size
     a.error = status ? status : L.error;
     a.spin_limit = 1 << 24;
     int64_t item = 0, flag_pos = 0;
+    int b_all = 0;
     for (int i = 0; i < ng; ++i) {
         const pss_problem *p = gs[i].p;
         Ctx c{p, p->B, p->y_off_host[p->B], p->y_off_host[p->B] + p->B, s};
@@ -248,6 +249,8 @@ int run(const pss_group *gs, int ng, int n_iter, int32_t *status, void *ws, size
         PGroup<T> &G = a.g[i];
         G.kind = kind_of(p);
         G.B = p->B;
+        G.seq0 = b_all;
+        b_all += p->B;
         G.E_f = sh.E_f;
         G.E_s = sh.E_s;
         G.stage_f = scan_stage(65, 20, sh.T, sh.E_f, sizeof(T));
@@ -302,6 +305,27 @@ int run(const pss_group *gs, int ng, int n_iter, int32_t *status, void *ws, size
         item += L.nts[i];
     }
     a.total_items = item;
+    // time-major order when at least a quarter of its (sequence, tile) slots
+    // hold a tile
+    {
+        int64_t maxt_f = 0, maxt_s = 0, nt = 0;
+        const int64_t TSf = (int64_t)sh.T * sh.E_f, TSs = (int64_t)sh.T * sh.E_s;
+        for (int i = 0; i < ng; ++i) {
+            const pss_problem *p = gs[i].p;
+            for (int b = 0; b < p->B; ++b) {
+                const int64_t n = p->y_off_host[b + 1] - p->y_off_host[b];
+                maxt_f = std::max(maxt_f, (n + TSf - 1) / TSf);
+                maxt_s = std::max(maxt_s, (n + 1 + TSs - 1) / TSs);
+            }
+        }
+        nt = item;
+        const int64_t slots = (maxt_f + maxt_s) * (int64_t)b_all;
+        a.rr = b_all > 1 && slots <= 4 * nt;
+        a.B_all = b_all;
+        a.n_f_items = maxt_f * (int64_t)b_all;
+        if (a.rr)
+            a.total_items = slots;
+    }
 
     auto kern = k_ipls_persistent<T>;
     // sized for the largest objects (coordinated-turn filter / smoother)

@@ -2,9 +2,12 @@
 // model groups in ONE launch (gfx950).
 //
 // Work items are (group, sequence, tile) triples handed out in a fixed order
-// by one atomic counter: first every filter tile of every group, sequences in
-// order, tiles in time order; then every smoother tile, tiles in reverse time
-// order.  A filter tile builds its elements on the fly (SLR at the previous
+// by one atomic counter: first every filter tile of every group, then every
+// smoother tile (smoother tiles in reverse time order).  For batches of many
+// sequences the order is time-major (tile 0 of every sequence, then tile 1,
+// ...), so the blocks running at the same time work on different sequences
+// and a tile's predecessor has long finished; otherwise it is sequence by
+// sequence, tiles in order.  A filter tile builds its elements on the fly (SLR at the previous
 // nominal for the CT model, then Lemma 1), folds them, runs the in-LDS
 // up-sweep, then chains with its predecessor: it waits for tile t-1's
 // published inclusive prefix (a filtering marginal), publishes its own
@@ -49,6 +52,7 @@ struct PGroup {
     int *flag_s;           // per smoother tile: suffix published
     const int64_t *tile_f, *tile_s; // per-sequence tile offsets [B+1]
     int64_t item_f0, item_s0;       // first global item of this group's phases
+    int seq0;                       // first global sequence index of this group
     int64_t ntiles_f, ntiles_s;
     // linear model parameters (kind == kGroupLinear4)
     const T *gF, *gc, *gSL, *gH, *gd, *gSO;
@@ -62,6 +66,13 @@ struct PArgs {
     PGroup<T> g[kMaxGroups];
     int n_groups;
     int64_t total_items;
+    // time-major order (rr != 0): filter item r = t * B_all + s is tile t of
+    // global sequence s (skipped if that sequence has fewer tiles), for t <
+    // maxt_f; then the smoother items likewise; otherwise items run group by
+    // group, sequence by sequence, tile by tile
+    int rr;
+    int B_all;
+    int64_t n_f_items;
     int *counter;   // work counter (reset before each pass)
     int *error;     // set if a wait exceeded its bound
     int spin_limit; // bounded waits
@@ -398,6 +409,33 @@ __global__ __launch_bounds__(256) void k_ipls_persistent(PArgs<T> a)
         if (item >= a.total_items)
             break;
         // filter items of all groups first, then smoother items
+        if (a.rr) {
+            const bool smooth = item >= a.n_f_items;
+            const int64_t r = smooth ? item - a.n_f_items : item;
+            const int64_t t = r / a.B_all;
+            const int sg = (int)(r - t * a.B_all);
+            int gi = 0;
+            while (gi + 1 < a.n_groups && sg >= a.g[gi + 1].seq0)
+                ++gi;
+            const PGroup<T> &G = a.g[gi];
+            const int sq = sg - G.seq0;
+            const int64_t *toff = smooth ? G.tile_s : G.tile_f;
+            const int64_t t0 = toff[sq];
+            if (t < toff[sq + 1] - t0) {
+                if (!smooth) {
+                    if (G.kind == kGroupCT)
+                        filter_tile<T, 5, 2, true>(a, G, t0 + t, lds);
+                    else
+                        filter_tile<T, 4, 2, false>(a, G, t0 + t, lds);
+                } else {
+                    if (G.kind == kGroupCT)
+                        smoother_tile<T, 5, 2, true>(a, G, t0 + t, lds);
+                    else
+                        smoother_tile<T, 4, 2, false>(a, G, t0 + t, lds);
+                }
+            }
+            continue;
+        }
         for (int gi = 0; gi < a.n_groups; ++gi) {
             const PGroup<T> &G = a.g[gi];
             if (item >= G.item_f0 && item < G.item_f0 + G.ntiles_f) {
