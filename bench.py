@@ -16,7 +16,9 @@ Also in the line (same run):
                   square-root kernel (one thread walks the sequence) at
                   n = 10^4 and 10^5 (prefixes of the same sequence)
   loglik_grad_ms  one loglik + gradient evaluation on 64 CT sequences of
-                  10^4 steps (the parameter-estimation configuration)
+                  10^4 steps (the parameter-estimation configuration), and 50
+                  L-BFGS steps on theta from theta* + 0.5 on that batch (IPLS
+                  re-run at every evaluation)
   kernels         every scan kernel of one filter and one smoother scan,
                   timed per launch with HIP events on its stream, with the
                   counted flops it executes
@@ -43,6 +45,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+from paper_2207_00426_amd import estimate  # noqa: E402
 from paper_2207_00426_amd import pss  # noqa: E402
 from paper_2207_00426_amd import workloads as wl  # noqa: E402
 
@@ -480,6 +483,27 @@ def main():
                                              pss.ipls_iterate(bb, yy, M, mm, NN, ws=wi)), 3)
                 lg[dt] = {"loglik_plus_grad_ms": round(t_g, 4), "ipls_ms": round(t_i, 4)}
                 log("64x1e4 %s: loglik+grad %.3f ms, IPLS %.3f ms" % (dt, t_g, t_i))
+                # 50 L-BFGS steps from theta* + 0.5 (IPLS re-run at every
+                # evaluation, frozen-nominal gradient)
+                th_star = [float(v) for v in wb.model.theta]
+                t0 = time.perf_counter()
+                fit = estimate.fit_theta_lbfgs(bb, yy, [v + 0.5 for v in th_star], n_steps=50,
+                                               passes=M)
+                t_fit = time.perf_counter() - t0
+                lg[dt]["lbfgs"] = {
+                    "iterations": fit["iterations"], "evaluations": fit["evaluations"],
+                    "theta_true": [round(v, 5) for v in th_star],
+                    "theta_start": [round(v + 0.5, 5) for v in th_star],
+                    "theta_final": [round(v, 5) for v in fit["theta"]],
+                    "loss_start": fit["loss_start"], "loss_final": fit["loss_final"],
+                    "ms_per_loglik_grad_evaluation": round(fit["ms_per_evaluation"], 3),
+                    "ms_ipls_per_evaluation": round(fit["ms_ipls_per_evaluation"], 3),
+                    "total_s": round(t_fit, 3)}
+                log("64x1e4 %s: L-BFGS %d steps, %d evaluations, theta %s -> %s (true %s), "
+                    "%.2f s" % (dt, fit["iterations"], fit["evaluations"],
+                                [round(v + 0.5, 3) for v in th_star],
+                                [round(v, 3) for v in fit["theta"]],
+                                [round(v, 3) for v in th_star], t_fit))
             extras["param_estimation_64x1e4"] = lg
 
         if not args.no_extras:
