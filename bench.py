@@ -50,10 +50,13 @@ from paper_2207_00426_amd import pss  # noqa: E402
 from paper_2207_00426_amd import workloads as wl  # noqa: E402
 
 # Counted floating-point operations of the nx = 5, ny = 2 operators (add,
-# multiply, divide, square root = 1; fused multiply-add = 2), obtained by
-# instantiating the register code on a counting number type.
-FLOPS = dict(filter_combine=3328, filter_apply=2280, smoother_combine=730, smoother_apply=505,
-             filter_element=1251, smoother_element=1502, slr_transition=937, slr_bearings=487)
+# multiply, reciprocal, square root = 1; fused multiply-add = 2), obtained by
+# instantiating the register code on a counting number type.  "_leaf": the
+# filter operator with a finest-level element on the right, whose Z has only
+# ny non-zero columns.
+FLOPS = dict(filter_combine=3363, filter_apply=2300, filter_combine_leaf=2492,
+             filter_apply_leaf=1805, smoother_combine=740, smoother_apply=515,
+             filter_element=1261, smoother_element=1514, slr_transition=938, slr_bearings=488)
 PEAK = {"f64": 78.6, "f32": 78.6}  # TFLOP/s vector ALU (FP32 without packed instructions)
 
 
@@ -105,13 +108,21 @@ def scan_kernel_flops(op, lengths, T0, E0, Tup, Eup):
     element is applied once.  The smoother's level-0 up-sweep also builds its
     elements (one per state)."""
     comb, app = FLOPS[op + "_combine"], FLOPS[op + "_apply"]
+    # the filter's finest level folds and applies leaf elements (elements -
+    # threads fold combines, elements applies); its trees use the general form
+    lcomb = FLOPS.get(op + "_combine_leaf", comb)
+    lapp = FLOPS.get(op + "_apply_leaf", app)
     plan = scan_plan(lengths, T0, E0, Tup, Eup)
     out = {}
     for l, (T, E, elems, tiles, threads) in enumerate(plan):
-        up = (elems - tiles) * comb
+        if l == 0:
+            up = (elems - threads) * lcomb + (threads - tiles) * comb
+            down = elems * lapp + (threads - tiles) * app
+        else:
+            up = (elems - tiles) * comb
+            down = (elems + threads - tiles) * app
         if op == "smoother" and l == 0:
             up += elems * FLOPS["smoother_element"]
-        down = (elems + threads - tiles) * app
         if l == len(plan) - 1:
             out[(op + "_top", l)] = up + down
         else:

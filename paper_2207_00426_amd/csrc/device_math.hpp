@@ -27,6 +27,32 @@ PSS_INL double pfma(double a, double b, double c) { return fma(a, b, c); }
 PSS_INL float pfma(float a, float b, float c) { return fmaf(a, b, c); }
 
 // --------------------------------------------------------------------------
+// Reciprocal: the hardware estimate refined by Newton-Raphson steps
+// r <- r + r (1 - x r), each roughly doubling the correct bits (two steps in
+// FP64, one in FP32, from the estimate's ~2^-23 relative error); ~1 ulp, not
+// correctly rounded.  Zero gives an infinity or NaN; callers select such
+// results away.
+// --------------------------------------------------------------------------
+PSS_INL double prcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+PSS_INL float prcp(float x)
+{
+    float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
+// exact power-of-two scaling of a row: 2^-e with sc = m 2^e, m in [0.5, 1)
+PSS_INL int pexp(double x) { return __builtin_amdgcn_frexp_exp(x); }
+PSS_INL int pexp(float x) { return __builtin_amdgcn_frexp_expf(x); }
+PSS_INL double pldexp(double x, int e) { return __builtin_amdgcn_ldexp(x, e); }
+PSS_INL float pldexp(float x, int e) { return __builtin_amdgcn_ldexpf(x, e); }
+
+// --------------------------------------------------------------------------
 // Tria by Householder reflections applied from the right (an LQ sweep).
 //
 // On entry A is R x C; rows 0..K-1 are reduced in turn: reflection i maps row
@@ -41,14 +67,17 @@ PSS_INL float pfma(float a, float b, float c) { return fmaf(a, b, c); }
 // of Lemmas 1-3), the sweep never touches those columns.  Z0 = C disables
 // the shortcut.
 //
-// The reflector uses the cancellation-free form of the pivot update
-// (v0 = -sigma / (alpha + |x|) when alpha > 0), so the new diagonal is
-// +|x| without a sign fix-up.  Each row is first scaled by its largest
-// magnitude, so squares neither overflow nor fall into the subnormal range
-// (in FP32 a tail of norm^2 ~ 1e-39 would otherwise give tau = 2/vv = inf);
-// a tail below machine epsilon relative to a positive pivot is left alone
-// (its reflection is the identity to working precision), and an all-zero row
-// is untouched.
+// Reflector of row x = (a, t) (pivot a, tail t, s = |t|^2, r = |x|):
+// v = (a - r, t), with the pivot entry taken as -s / (a + r) when a > 0 so
+// nothing cancels; since |v|^2 = -2 r v0, the reflection is
+// I - tau v v^T with tau = -1 / (r v0) for either sign of a, and maps x to
+// (+r, 0, ...) without a sign fix-up.  Two reciprocals per row.  In FP32 each
+// row is first scaled by a power of two near its largest magnitude, so
+// squares neither overflow nor fall into the subnormal range (a tail with
+// s ~ 1e-39 would otherwise give an infinite tau); FP64's exponent range makes
+// that unnecessary for these models.  A tail below machine epsilon relative
+// to a positive pivot is left alone (its reflection is the identity to
+// working precision), and an all-zero row is untouched.
 // --------------------------------------------------------------------------
 template <typename T> struct Eps;
 template <> struct Eps<double> { static constexpr double v = 2.220446049250313e-16; };
@@ -62,27 +91,32 @@ PSS_INL float pmax(float a, float b) { return fmaxf(a, b); }
 template <int K, int Z0, typename T, int R, int C>
 PSS_INL void lq_rows(T (&A)[R][C])
 {
-    static_assert(K <= R && R <= C, "lq_rows: need K <= R <= C");
+    static_assert(K <= R && K <= C, "lq_rows: need K <= R and K <= C");
+    constexpr bool kScale = sizeof(T) == 4;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         const int jend = cmin(C, Z0 + i + 1);
-        T sc = pabs(A[i][i]);
+        int ex = 0;
+        if constexpr (kScale) {
+            T sc = pabs(A[i][i]);
 #pragma unroll
-        for (int j = i + 1; j < jend; ++j)
-            sc = pmax(sc, pabs(A[i][j]));
-        const T inv = (sc > T(0)) ? T(1) / sc : T(0);
+            for (int j = i + 1; j < jend; ++j)
+                sc = pmax(sc, pabs(A[i][j]));
+            ex = pexp(sc);
+#pragma unroll
+            for (int j = i; j < jend; ++j)
+                A[i][j] = pldexp(A[i][j], -ex);
+        }
         T sig = T(0);
 #pragma unroll
-        for (int j = i + 1; j < jend; ++j) {
-            A[i][j] *= inv; // row i now holds the scaled reflector tail
+        for (int j = i + 1; j < jend; ++j)
             sig = pfma(A[i][j], A[i][j], sig);
-        }
-        const T al = A[i][i] * inv;
+        const T al = A[i][i];
         const T nr = psqrt(pfma(al, al, sig));
-        const T v0 = (al > T(0)) ? -sig / (al + nr) : (al - nr);
-        const T vv = pfma(v0, v0, sig);
-        const bool skip = !(vv > T(0)) || (al > T(0) && sig <= Eps<T>::v * Eps<T>::v);
-        const T tau = skip ? T(0) : T(2) / vv;
+        const T v0 = (al > T(0)) ? -sig * prcp(al + nr) : (al - nr);
+        const T p = nr * v0;
+        const bool skip = !(p < T(0)) || (al > T(0) && sig <= Eps<T>::v * Eps<T>::v * al * al);
+        const T tau = skip ? T(0) : -prcp(p);
 #pragma unroll
         for (int r = i + 1; r < R; ++r) {
             T w = A[r][i] * v0;
@@ -95,7 +129,8 @@ PSS_INL void lq_rows(T (&A)[R][C])
             for (int j = i + 1; j < jend; ++j)
                 A[r][j] = pfma(-tw, A[i][j], A[r][j]);
         }
-        A[i][i] = (skip && al > T(0)) ? sc * al : nr * sc;
+        const T d = (skip && al > T(0)) ? al : nr;
+        A[i][i] = kScale ? pldexp(d, ex) : d;
     }
 }
 
@@ -141,6 +176,28 @@ PSS_INL void tria_dense_lower(const T (&X)[R][R], const T (&L2)[R][R], T (&L)[R]
             L[i][j] = A[i][j];
 }
 
+// Tria([X, L2]) with X dense R x NC and L2 lower R x R, into lower L.
+template <typename T, int R, int NC>
+PSS_INL void tria_cols_lower(const T (&X)[R][NC], const T (&L2)[R][R], T (&L)[R][R])
+{
+    T A[R][NC + R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+#pragma unroll
+        for (int j = 0; j < NC; ++j)
+            A[i][j] = X[i][j];
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+            A[i][NC + j] = (j <= i) ? L2[i][j] : T(0);
+    }
+    lq_rows<R, NC>(A);
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int j = 0; j <= i; ++j)
+            L[i][j] = A[i][j];
+}
+
 // --------------------------------------------------------------------------
 // triangular solves (L lower with non-zero diagonal)
 // --------------------------------------------------------------------------
@@ -151,7 +208,7 @@ PSS_INL void rsolve_lower(const T (&B)[R][N], const T (&L)[N][N], T (&X)[R][N])
     T inv[N];
 #pragma unroll
     for (int j = 0; j < N; ++j)
-        inv[j] = T(1) / L[j][j];
+        inv[j] = prcp(L[j][j]);
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
@@ -171,7 +228,7 @@ PSS_INL void rsolve_lower_t(const T (&B)[R][N], const T (&L)[N][N], T (&X)[R][N]
     T inv[N];
 #pragma unroll
     for (int j = 0; j < N; ++j)
-        inv[j] = T(1) / L[j][j];
+        inv[j] = prcp(L[j][j]);
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
@@ -194,7 +251,7 @@ PSS_INL void lsolve_lower(const T (&L)[N][N], const T (&b)[N], T (&x)[N])
 #pragma unroll
         for (int t = 0; t < i; ++t)
             s = pfma(-L[i][t], x[t], s);
-        x[i] = s / L[i][i];
+        x[i] = s * prcp(L[i][i]);
     }
 }
 

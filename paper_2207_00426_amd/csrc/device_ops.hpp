@@ -260,19 +260,31 @@ PSS_INL void filter_element_first(const T (&m0)[NX], const T (&N0)[NX][NX], cons
 //   eta = A_i^T G^T (eta_j - Z_j Z_j^T b_i) + eta_i
 //   Z  = Tria([A_i^T Xi22, Z_i])
 // --------------------------------------------------------------------------
-template <typename T, int NX>
-PSS_INL void xi_matrix(const T (&Ui)[NX][NX], const T (&Zj)[NX][NX], T (&M)[2 * NX][2 * NX])
+// Xi input block [[U_i^T Z_j, I], [Z_j, 0]] of Table 3 with Z_j given as its
+// first NZ columns (lower trapezoidal NX x NZ).  NZ = NX is the general
+// case; a finest-level element stores Z_j = Tria([Z_k, 0]) with Z_k of ny
+// columns (Lemma 1), whose columns from ny on are exactly zero, so NZ = ny
+// drops them and the block has NZ + NX columns instead of 2 NX.  Columns can
+// be dropped or reordered freely: Tria only depends on the Gram matrix.
+template <typename T, int NX, int NZ>
+PSS_INL void xi_block(const T (&Ui)[NX][NX], const T (&Zj)[NX][NZ], T (&M)[2 * NX][NZ + NX])
 {
-    T W[NX][NX];
-    mm_lowerT_lower(Ui, Zj, W);
 #pragma unroll
-    for (int i = 0; i < NX; ++i) {
+    for (int r = 0; r < NX; ++r) {
+#pragma unroll
+        for (int a = 0; a < NZ; ++a) {
+            const int t0 = r > a ? r : a;
+            T s = Ui[t0][r] * Zj[t0][a];
+#pragma unroll
+            for (int t = t0 + 1; t < NX; ++t)
+                s = pfma(Ui[t][r], Zj[t][a], s);
+            M[r][a] = s;
+            M[NX + r][a] = Zj[r][a];
+        }
 #pragma unroll
         for (int j = 0; j < NX; ++j) {
-            M[i][j] = W[i][j];
-            M[i][NX + j] = (i == j) ? T(1) : T(0);
-            M[NX + i][j] = (j <= i) ? Zj[i][j] : T(0);
-            M[NX + i][NX + j] = T(0);
+            M[r][NZ + j] = (r == j) ? T(1) : T(0);
+            M[NX + r][NZ + j] = T(0);
         }
     }
 }
@@ -355,6 +367,16 @@ PSS_INL void load_lower_Z(const V &v, T (&L)[NX][NX])
             L[i][j] = (j <= i) ? v.Z(i, j) : T(0);
 }
 
+template <typename T, int NX, int NZ, class V>
+PSS_INL void load_Z_cols(const V &v, T (&Z)[NX][NZ])
+{
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+#pragma unroll
+        for (int a = 0; a < NZ; ++a)
+            Z[i][a] = (a <= i) ? v.Z(i, a) : T(0);
+}
+
 template <typename T, int NX, class V>
 PSS_INL void load_A(const V &v, T (&A)[NX][NX])
 {
@@ -367,37 +389,50 @@ PSS_INL void load_A(const V &v, T (&A)[NX][NX])
 
 // Table 3 through views.  The output is written field by field, b, U, eta,
 // Z, A, each after the last read of the input fields it may overwrite, so
-// `o` may view the same storage as `ei` or as `ej`.
-template <typename T, int NX, class VI, class VJ, class VO>
+// `o` may view the same storage as `ei` or as `ej`.  Only the first NZ
+// columns of Z_j are read (see xi_block).
+template <typename T, int NX, int NZ, class VI, class VJ, class VO>
 PSS_INL void filter_combine_v(const VI &ei, const VJ &ej, const VO &o)
 {
+    constexpr int C = NZ + NX;
+    constexpr int K = cmin(2 * NX, C);
     // v = b_i + U_i U_i^T eta_j and q = eta_j - Z_j Z_j^T b_i need the
     // inputs only; computing them first keeps U_i, Z_j out of the Tria below
     T v[NX], q[NX];
-    T M[2 * NX][2 * NX];
+    T M[2 * NX][C];
     {
-        T Ui[NX][NX], Zj[NX][NX], etj[NX], bi[NX];
+        T Ui[NX][NX], Zj[NX][NZ], etj[NX], bi[NX];
         load_lower_U(ei, Ui);
-        load_lower_Z(ej, Zj);
+        load_Z_cols(ej, Zj);
 #pragma unroll
         for (int i = 0; i < NX; ++i) {
             etj[i] = ej.eta(i);
             bi[i] = ei.b(i);
         }
-        T ut[NX], uu[NX], zt[NX], zz[NX];
+        T ut[NX], uu[NX], zt[NZ];
         lowerT_mv(Ui, etj, ut);
         lower_mv(Ui, ut, uu);
-        lowerT_mv(Zj, bi, zt);
-        lower_mv(Zj, zt, zz);
+#pragma unroll
+        for (int a = 0; a < NZ; ++a) {
+            T s = Zj[a][a] * bi[a];
+#pragma unroll
+            for (int i = a + 1; i < NX; ++i)
+                s = pfma(Zj[i][a], bi[i], s);
+            zt[a] = s;
+        }
 #pragma unroll
         for (int i = 0; i < NX; ++i) {
+            T s = Zj[i][0] * zt[0];
+#pragma unroll
+            for (int a = 1; a < NZ && a <= i; ++a)
+                s = pfma(Zj[i][a], zt[a], s);
             v[i] = bi[i] + uu[i];
-            q[i] = etj[i] - zz[i];
+            q[i] = etj[i] - s;
         }
         // Xi = Tria([[U_i^T Z_j, I], [Z_j, 0]])
-        xi_matrix(Ui, Zj, M);
+        xi_block(Ui, Zj, M);
     }
-    lq_rows<2 * NX, NX>(M);
+    lq_rows<K, NZ>(M);
     // Tm = U_i Xi11^{-T}, G = I - Tm Xi21^T
     T Tm[NX][NX], G[NX][NX];
     {
@@ -458,13 +493,13 @@ PSS_INL void filter_combine_v(const VI &ei, const VJ &ej, const VO &o)
         for (int i = 0; i < NX; ++i)
             o.seta(i, aq[i] + ei.eta(i));
     }
-    // Z = Tria([A_i^T Xi22, Z_i])
+    // Z = Tria([A_i^T Xi22, Z_i]); Xi22 is NX x NZ lower trapezoidal
     {
-        T AX[NX][NX];
+        T AX[NX][NZ];
 #pragma unroll
         for (int a = 0; a < NX; ++a)
 #pragma unroll
-            for (int c = 0; c < NX; ++c) {
+            for (int c = 0; c < NZ; ++c) {
                 T s = Ai[c][a] * M[NX + c][NX + c];
 #pragma unroll
                 for (int t = c + 1; t < NX; ++t)
@@ -473,7 +508,7 @@ PSS_INL void filter_combine_v(const VI &ei, const VJ &ej, const VO &o)
             }
         T Zi[NX][NX], Zn[NX][NX];
         load_lower_Z(ei, Zi);
-        tria_dense_lower(AX, Zi, Zn);
+        tria_cols_lower(AX, Zi, Zn);
 #pragma unroll
         for (int i = 0; i < NX; ++i)
 #pragma unroll
@@ -495,7 +530,7 @@ PSS_INL void filter_combine_v(const VI &ei, const VJ &ej, const VO &o)
 template <typename T, int NX>
 PSS_INL void filter_combine(const FElem<T, NX> &ei, const FElem<T, NX> &ej, FElem<T, NX> &o)
 {
-    filter_combine_v<T, NX>(FRegV<T, NX>{const_cast<FElem<T, NX> *>(&ei)},
+    filter_combine_v<T, NX, NX>(FRegV<T, NX>{const_cast<FElem<T, NX> *>(&ei)},
                             FRegV<T, NX>{const_cast<FElem<T, NX> *>(&ej)}, FRegV<T, NX>{&o});
 }
 
@@ -504,7 +539,7 @@ PSS_INL void filter_combine(const FElem<T, NX> &ei, const FElem<T, NX> &ej, FEle
 // filtering marginal (m, N), matter, and the result is again such a prefix.
 // This is Table 3 with A_i = 0, b_i = m, U_i = N: the Xi22 block and the
 // eta/Z outputs drop out.  `o` must not be `p`.
-template <typename T, int NX, class VJ>
+template <typename T, int NX, int NZ, class VJ>
 PSS_INL void filter_apply_v(const Marg<T, NX> &p, const VJ &ej, Marg<T, NX> &o)
 {
     T Nf[NX][NX];
@@ -514,10 +549,10 @@ PSS_INL void filter_apply_v(const Marg<T, NX> &p, const VJ &ej, Marg<T, NX> &o)
         for (int j = 0; j < NX; ++j)
             Nf[i][j] = (j <= i) ? p.N[i][j] : T(0);
     T v[NX];
-    T M[2 * NX][2 * NX];
+    T M[2 * NX][NZ + NX];
     {
-        T Zj[NX][NX], etj[NX];
-        load_lower_Z(ej, Zj);
+        T Zj[NX][NZ], etj[NX];
+        load_Z_cols(ej, Zj);
 #pragma unroll
         for (int i = 0; i < NX; ++i)
             etj[i] = ej.eta(i);
@@ -527,9 +562,9 @@ PSS_INL void filter_apply_v(const Marg<T, NX> &p, const VJ &ej, Marg<T, NX> &o)
 #pragma unroll
         for (int i = 0; i < NX; ++i)
             v[i] = p.m[i] + uu[i];
-        xi_matrix(Nf, Zj, M);
+        xi_block(Nf, Zj, M);
     }
-    lq_rows<NX, NX>(M);
+    lq_rows<NX, NZ>(M);
     T Tm[NX][NX], G[NX][NX];
     {
         T X11[NX][NX];
@@ -570,7 +605,7 @@ PSS_INL void filter_apply_v(const Marg<T, NX> &p, const VJ &ej, Marg<T, NX> &o)
 template <typename T, int NX>
 PSS_INL void filter_apply(const Marg<T, NX> &p, const FElem<T, NX> &ej, Marg<T, NX> &o)
 {
-    filter_apply_v<T, NX>(p, FRegV<T, NX>{const_cast<FElem<T, NX> *>(&ej)}, o);
+    filter_apply_v<T, NX, NX>(p, FRegV<T, NX>{const_cast<FElem<T, NX> *>(&ej)}, o);
 }
 
 // --------------------------------------------------------------------------

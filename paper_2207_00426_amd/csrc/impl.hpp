@@ -294,11 +294,13 @@ struct Core {
         er.ld = c.T_y;
         FiltDst<T, NX> dst{marg_ref2(mf, Nf, c.T_x), c.p->y_off};
         StartPre<T, NX> st{cptr<T>(c.p->m0), cptr<T>(c.p->N0)};
+        // finest-level elements: Z = Tria([Z_k, 0]) with Z_k of ny columns
+        constexpr int LZ = NY < NX ? NY : NX;
         if (ilv) {
-            RefSrc<FS, FElemRef<T, NX>, true> src{er};
+            RefSrc<FS, FElemRef<T, NX>, true, LZ> src{er};
             return run_scan<FS>(c, sh, w, 0, src, dst, st, &felem_ref);
         }
-        RefSrc<FS, FElemRef<T, NX>> src{er};
+        RefSrc<FS, FElemRef<T, NX>, false, LZ> src{er};
         return run_scan<FS>(c, sh, w, 0, src, dst, st, &felem_ref);
     }
 

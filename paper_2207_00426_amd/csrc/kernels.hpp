@@ -268,15 +268,16 @@ struct FilterScan {
         return FSlotV<T, NX, int>{lds + s, Tb};
     }
     PSS_INL static FRegV<T, NX> reg(Elem &e) { return FRegV<T, NX>{&e}; }
-    template <class VA, class VB, class VO>
+    // NZ: columns of the right element's Z that can be non-zero (xi_block)
+    template <int NZ = NX, class VA, class VB, class VO>
     PSS_INL static void combine_v(const VA &a, const VB &b, const VO &o)
     {
-        filter_combine_v<T, NX>(a, b, o);
+        filter_combine_v<T, NX, NZ>(a, b, o);
     }
-    template <class VA>
+    template <int NZ = NX, class VA>
     PSS_INL static void apply_v(const Pre &p, const VA &a, Pre &o)
     {
-        filter_apply_v<T, NX>(p, a, o);
+        filter_apply_v<T, NX, NZ>(p, a, o);
     }
     template <class VS, class VD>
     PSS_INL static void copy_v(const VS &src, const VD &dst)
@@ -303,12 +304,12 @@ struct SmootherScan {
         return SSlotV<T, NX, int>{lds + s, Tb};
     }
     PSS_INL static SRegV<T, NX> reg(Elem &e) { return SRegV<T, NX>{&e}; }
-    template <class VA, class VB, class VO>
+    template <int NZ = NX, class VA, class VB, class VO>
     PSS_INL static void combine_v(const VA &a, const VB &b, const VO &o)
     {
         smoother_combine_v<T, NX>(b, a, o);
     }
-    template <class VA>
+    template <int NZ = NX, class VA>
     PSS_INL static void apply_v(const Pre &p, const VA &a, Pre &o)
     {
         smoother_apply_v<T, NX>(a, p, o);
@@ -479,10 +480,13 @@ PSS_INL TileInfo tile_info(const LevelGeom &g)
 // A source either builds element p in registers (up / down) or, when
 // lazy_up / lazy_down is set, hands out a view of it (uview / dview) that the
 // operators read field by field.
-// (ILV: the level's elements are stored tile-interleaved, see ilv)
-template <class Op, class Ref, bool ILV = false>
+// (ILV: the level's elements are stored tile-interleaved, see ilv.  LEAF_NZ
+// > 0: finest-level filter elements, whose Z has only LEAF_NZ columns that
+// can be non-zero; leaf_nz = 0 for everything else.)
+template <class Op, class Ref, bool ILV = false, int LEAF_NZ = 0>
 struct RefSrc {
     static constexpr bool lazy_up = true, lazy_down = true;
+    static constexpr int leaf_nz = LEAF_NZ;
     Ref ref;
     PSS_INL int64_t slot(const TileInfo &ti, int64_t p) const
     {
@@ -498,6 +502,7 @@ struct RefSrc {
 template <typename T, int NX, int NY>
 struct SmootherSrc {
     static constexpr bool lazy_up = false, lazy_down = true;
+    static constexpr int leaf_nz = 0;
     GammaRef<T, NX, NY> gam;
     MargRef<T, NX> filt; // ld = T_x
     SElemRef<T, NX> stash; // ld = T_x
@@ -616,15 +621,22 @@ PSS_INL void src_first(const Src &src, const TileInfo &ti, int64_t p, const V &a
     }
 }
 
+template <class Src, int NX>
+constexpr int leaf_cols()
+{
+    return Src::leaf_nz > 0 ? Src::leaf_nz : NX;
+}
+
 template <class Op, class Src, class V>
 PSS_INL void src_fold(const Src &src, const TileInfo &ti, int64_t p, const V &acc)
 {
+    constexpr int nz = leaf_cols<Src, Op::NX>();
     if constexpr (Src::lazy_up) {
-        Op::combine_v(acc, src.uview(ti, p), acc);
+        Op::template combine_v<nz>(acc, src.uview(ti, p), acc);
     } else {
         typename Op::Elem e;
         src.up(ti, p, e);
-        Op::combine_v(acc, Op::reg(e), acc);
+        Op::template combine_v<nz>(acc, Op::reg(e), acc);
     }
 }
 
@@ -632,12 +644,13 @@ template <class Op, class Src>
 PSS_INL void src_apply(const Src &src, const TileInfo &ti, int64_t p, const typename Op::Pre &P,
                        typename Op::Pre &Q)
 {
+    constexpr int nz = leaf_cols<Src, Op::NX>();
     if constexpr (Src::lazy_down) {
-        Op::apply_v(P, src.dview(ti, p), Q);
+        Op::template apply_v<nz>(P, src.dview(ti, p), Q);
     } else {
         typename Op::Elem e;
         src.down(ti, p, e);
-        Op::apply_v(P, Op::reg(e), Q);
+        Op::template apply_v<nz>(P, Op::reg(e), Q);
     }
 }
 

@@ -230,6 +230,7 @@ struct FusedFiltSrc {
         felem_ref_dev<T, NX>(G->fstash, G->T_y).store(ilv_slot(ti, p), e);
     }
     static constexpr bool lazy_up = false, lazy_down = true;
+    static constexpr int leaf_nz = NY < NX ? NY : NX; // Z = Tria([Z_k, 0])
     PSS_INL FRefV<T, NX> dview(const TileInfo &ti, int64_t p) const
     {
         return view_of(felem_ref_dev<T, NX>(G->fstash, G->T_y), ilv_slot(ti, p));
@@ -270,6 +271,7 @@ struct FusedSmoothSrc {
         selem_ref_dev<T, NX>(G->sstash, G->T_x).store(ilv_slot(ti, p), e);
     }
     static constexpr bool lazy_up = false, lazy_down = true;
+    static constexpr int leaf_nz = 0;
     PSS_INL SRefV<T, NX> dview(const TileInfo &ti, int64_t p) const
     {
         return view_of(selem_ref_dev<T, NX>(G->sstash, G->T_x), ilv_slot(ti, p));

@@ -115,6 +115,9 @@ def test_filter_elements_match_tables_1_2(nx, ny):
             np.testing.assert_allclose(par.gram(U[t]), par.gram(rU), rtol=1e-9, atol=1e-11)
             np.testing.assert_allclose(par.gram(Z[t]), par.gram(rZ), rtol=1e-9, atol=1e-11)
             assert np.all(np.diag(U[t]) >= 0) and np.all(np.diag(Z[t]) >= 0)
+            # Z = Tria([Z_k, 0]) with Z_k of ny columns: the columns from ny
+            # on are exactly zero (the scan reads only the first ny)
+            assert np.all(Z[t][:, ny:] == 0.0)
 
 
 def test_scalar_random_walk_steady_state():
