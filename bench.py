@@ -136,7 +136,8 @@ def kernel_source_hash():
     other kernels than the ones built here is not used."""
     import hashlib
     from paper_2207_00426_amd import build as hipbuild
-    h = hashlib.sha256(" ".join(hipbuild.FLAGS).encode())
+    # build flags without include paths (those differ between machines)
+    h = hashlib.sha256(" ".join(f for f in hipbuild.FLAGS if not f.startswith("-I")).encode())
     csrc = os.path.join(ROOT, "paper_2207_00426_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
         if f.endswith((".hip", ".hpp", ".h")):

@@ -34,7 +34,9 @@ def lbfgs(fg, x0, n_steps=50, history=10, max_step=1.0, c1=1e-4, max_backtracks=
 
     Two-loop recursion for the direction (initial inverse Hessian scaled by
     s.y / y.y of the latest pair), Armijo backtracking from step 1 with the
-    step length capped at max_step, curvature pairs with s.y <= 0 skipped.
+    step length capped at max_step, curvature pairs with s.y <= 0 skipped; a
+    direction whose search fails is replaced once by the scaled negative
+    gradient (memory cleared) before the run stops.
     Returns (x, f, trace) with trace a list of (f, |g|_inf, evaluations)."""
     x = np.asarray(x0, dtype=np.float64).copy()
     f, g = fg(x)
@@ -64,17 +66,26 @@ def lbfgs(fg, x0, n_steps=50, history=10, max_step=1.0, c1=1e-4, max_backtracks=
             S, Y = [], []
             d = -g / max(np.max(np.abs(g)), 1e-300)
             slope = g.dot(d)
-        nd = np.linalg.norm(d)
-        t = min(1.0, max_step / nd) if nd > 0 else 1.0
         accepted = False
-        for _ in range(max_backtracks):
-            xn = x + t * d
-            fn, gn = fg(xn)
-            evals += 1
-            if np.isfinite(fn) and fn <= f + c1 * t * slope:
-                accepted = True
+        for attempt in range(2):
+            nd = np.linalg.norm(d)
+            t = min(1.0, max_step / nd) if nd > 0 else 1.0
+            for _ in range(max_backtracks):
+                xn = x + t * d
+                fn, gn = fg(xn)
+                evals += 1
+                if np.isfinite(fn) and fn <= f + c1 * t * slope:
+                    accepted = True
+                    break
+                t *= 0.5
+            if accepted or attempt == 1:
                 break
-            t *= 0.5
+            # the quasi-Newton direction failed (with an approximate gradient
+            # it need not descend): forget the curvature pairs and retry along
+            # the scaled negative gradient
+            S, Y = [], []
+            d = -g / max(np.max(np.abs(g)), 1e-300)
+            slope = g.dot(d)
         if not accepted:
             break
         s, y = xn - x, gn - g
