@@ -167,7 +167,15 @@ def ct_Q(prm):
     return Q
 
 
-def ct_linearize(prm, ms, Ns, y, literal=False):
+METHODS = {"cubature": 0, "cubature_literal": 1, "taylor": 2}
+
+
+def ct_linearize(prm, ms, Ns, y, literal=False, method=None):
+    """Per-step linearisation of the CT model at the nominal (ms, Ns):
+    method "cubature" (residual SLR, Section 4.3), "cubature_literal" (the
+    printed Tria + DownDate form) or "taylor" (first-order, Section 4.2)."""
+    if method is None:
+        method = "cubature_literal" if literal else "cubature"
     prm = _f64(prm)
     ms = _f64(ms)
     Ns = _f64(Ns)
@@ -175,13 +183,14 @@ def ct_linearize(prm, ms, Ns, y, literal=False):
     n = y.shape[0]
     F = np.zeros((n, 5, 5)); c = np.zeros((n, 5)); SL = np.zeros((n, 5, 5))
     H = np.zeros((n, 2, 5)); d = np.zeros((n, 2)); SO = np.zeros((n, 2, 2))
-    bad = _load().or_ct_linearize(I(n), _p(prm), _p(ms), _p(Ns), _p(y), I(int(literal)), _p(F),
+    bad = _load().or_ct_linearize(I(n), _p(prm), _p(ms), _p(Ns), _p(y), I(METHODS[method]), _p(F),
                                   _p(c), _p(SL), _p(H), _p(d), _p(SO))
     return dict(F=F, c=c, SL=SL, H=H, d=d, SO=SO, bad=int(bad))
 
 
-def ct_ipls(prm, m0, N0, y, M, ms_init=None, Ns_init=None, history=False):
-    """Algorithm 3 (sequential reference).  Initial nominal: the prior at every k."""
+def ct_ipls(prm, m0, N0, y, M, ms_init=None, Ns_init=None, history=False, method="cubature"):
+    """Algorithm 3 (sequential reference).  Initial nominal: the prior at every k.
+    method "taylor": the iterated extended smoother (Section 4.2)."""
     prm = _f64(prm); m0 = _f64(m0); N0 = _f64(N0); y = _f64(y)
     n = y.shape[0]
     ms = np.repeat(m0[None], n + 1, axis=0) if ms_init is None else _f64(ms_init).copy()
@@ -191,7 +200,7 @@ def ct_ipls(prm, m0, N0, y, M, ms_init=None, Ns_init=None, history=False):
     mf = np.zeros((n + 1, 5)); Nf = np.zeros((n + 1, 5, 5))
     rc = _load().or_ct_ipls(I(n), _p(prm), _p(m0), _p(N0), _p(y), I(M), _p(ms), _p(Ns),
                             _p(hm) if history else None, _p(hN) if history else None,
-                            _p(mf), _p(Nf))
+                            _p(mf), _p(Nf), I(METHODS[method]))
     if rc != 0:
         raise RuntimeError("oracle IPLS failed")
     out = dict(ms=ms, Ns=Ns, mf=mf, Nf=Nf)
@@ -201,21 +210,35 @@ def ct_ipls(prm, m0, N0, y, M, ms_init=None, Ns_init=None, history=False):
     return out
 
 
-def ct_loglik(prm, m0, N0, y, ms, Ns, per_step=False):
+def ct_loglik(prm, m0, N0, y, ms, Ns, per_step=False, method="cubature"):
     prm = _f64(prm); m0 = _f64(m0); N0 = _f64(N0); y = _f64(y); ms = _f64(ms); Ns = _f64(Ns)
     n = y.shape[0]
     ell = np.zeros(n)
-    tot = _load().or_ct_loglik(I(n), _p(prm), _p(m0), _p(N0), _p(y), _p(ms), _p(Ns), _p(ell))
+    tot = _load().or_ct_loglik(I(n), _p(prm), _p(m0), _p(N0), _p(y), _p(ms), _p(Ns), _p(ell),
+                               I(METHODS[method]))
     return (tot, ell) if per_step else tot
 
 
-def ct_score(prm, m0, N0, y, ms, Ns):
+def ct_score(prm, m0, N0, y, ms, Ns, method="cubature"):
     """(loglik, d loglik / d (log q1, log q2, log sigma)) at a frozen nominal."""
     prm = _f64(prm); m0 = _f64(m0); N0 = _f64(N0); y = _f64(y); ms = _f64(ms); Ns = _f64(Ns)
     n = y.shape[0]
     g = np.zeros(3)
-    tot = _load().or_ct_score(I(n), _p(prm), _p(m0), _p(N0), _p(y), _p(ms), _p(Ns), _p(g))
+    tot = _load().or_ct_score(I(n), _p(prm), _p(m0), _p(N0), _p(y), _p(ms), _p(Ns), _p(g),
+                              I(METHODS[method]))
     return tot, g
+
+
+def ct_jac_f(prm, x):
+    J = np.zeros((5, 5))
+    _load().or_ct_jac_f(_p(_f64(prm)), _p(_f64(x)), _p(J))
+    return J
+
+
+def ct_jac_h(prm, x):
+    J = np.zeros((2, 5))
+    _load().or_ct_jac_h(_p(_f64(prm)), _p(_f64(x)), _p(J))
+    return J
 
 
 def ct_theta_params(theta, base=None):

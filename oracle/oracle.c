@@ -24,6 +24,9 @@
  *   - tria, downdate, cubature SLR, filters, smoothers, log-likelihood and
  *     score are pinned by the CPU tests (closed forms, brute force, finite
  *     differences, library routines);
+ *   - the first-order Taylor linearisation (iterated extended smoother) is
+ *     pinned by finite differences of the model functions and by the
+ *     cubature SLR's small-covariance limit;
  *   - the CT iterated smoother's output values have no printed reference in
  *     the paper: beyond the invariants tested, parity unpinned.
  */
@@ -1051,6 +1054,66 @@ void or_filter_combine_cov(int nx, const double *Ai, const double *bi, const dou
 }
 
 /* ------------------------------------------------------------------------ */
+/* First-order Taylor linearisation (Section 4.2: the iterated extended     */
+/* smoother): F = Jacobian of f at the nominal mean, c = f(m) - F m,        */
+/* Lambda = Q; H = Jacobian of h at the nominal mean, d = h(m) - H m,       */
+/* Omega = R.  The nominal covariance is not used.                          */
+/* ------------------------------------------------------------------------ */
+/* d/dw of s1 = sin(w dt)/w and s2 = (1 - cos(w dt))/w, a = w dt:          */
+/*   ds1 = dt^2 (a cos a - sin a)/a^2,  ds2 = dt^2 (a sin a - 1 + cos a)/a^2 */
+/* with their Taylor series in a near 0 (-a/3 + a^3/30, 1/2 - a^2/8 + a^4/144)*/
+static void ct_ds(double dt, double w, double *ds1, double *ds2)
+{
+    double a = w * dt;
+    if (fabs(a) < 1e-3) {
+        *ds1 = dt * dt * (-a / 3.0 + a * a * a / 30.0);
+        *ds2 = dt * dt * (0.5 - a * a / 8.0 + a * a * a * a / 144.0);
+    } else {
+        *ds1 = dt * dt * (a * cos(a) - sin(a)) / (a * a);
+        *ds2 = dt * dt * (a * sin(a) - 1.0 + cos(a)) / (a * a);
+    }
+}
+
+/* Jacobian of the CT transition mean (5 x 5, row-major) */
+void or_ct_jac_f(const double *prm, const double *x, double *J)
+{
+    double dt = prm[0], w = x[4], a = w * dt;
+    double s1 = dt * sinc_(a), s2 = dt * 0.5 * a * sinc_(0.5 * a) * sinc_(0.5 * a);
+    double ca = cos(a), sa = sin(a), ds1, ds2, vx = x[2], vy = x[3];
+    ct_ds(dt, w, &ds1, &ds2);
+    for (int i = 0; i < 25; ++i)
+        J[i] = 0.0;
+    J[0 * 5 + 0] = 1.0;
+    J[0 * 5 + 2] = s1;
+    J[0 * 5 + 3] = -s2;
+    J[0 * 5 + 4] = ds1 * vx - ds2 * vy;
+    J[1 * 5 + 1] = 1.0;
+    J[1 * 5 + 2] = s2;
+    J[1 * 5 + 3] = s1;
+    J[1 * 5 + 4] = ds2 * vx + ds1 * vy;
+    J[2 * 5 + 2] = ca;
+    J[2 * 5 + 3] = -sa;
+    J[2 * 5 + 4] = dt * (-sa * vx - ca * vy);
+    J[3 * 5 + 2] = sa;
+    J[3 * 5 + 3] = ca;
+    J[3 * 5 + 4] = dt * (ca * vx - sa * vy);
+    J[4 * 5 + 4] = 1.0;
+}
+
+/* Jacobian of the two bearings (2 x 5, row-major) */
+void or_ct_jac_h(const double *prm, const double *x, double *J)
+{
+    for (int i = 0; i < 10; ++i)
+        J[i] = 0.0;
+    for (int s = 0; s < 2; ++s) {
+        double dx = x[0] - prm[4 + 2 * s], dy = x[1] - prm[5 + 2 * s];
+        double r2 = dx * dx + dy * dy;
+        J[s * 5 + 0] = -dy / r2;
+        J[s * 5 + 1] = dx / r2;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* CT model: per-step cubature linearisation (Section 4.1 / 4.3) at a       */
 /* nominal trajectory (ms, Ns), k = 0..n.  Transition parameters of slot j  */
 /* come from the marginal at j, measurement parameters of slot j (for       */
@@ -1066,6 +1129,32 @@ int or_ct_linearize(int n, const double *prm, const double *ms, const double *Ns
     if (or_cholesky(nx, Q, LQ) != 0)
         return -1;
     int bad = 0;
+    if (literal == 2) { /* first-order Taylor (extended) */
+        for (int j = 0; j < n; ++j) {
+            const double *m = ms + (long)j * nx, *m1 = ms + (long)(j + 1) * nx;
+            double fm[5], hm[2];
+            double *Fj = F + (long)j * 25, *Hj = H + (long)j * 10;
+            or_ct_f(prm, m, fm);
+            or_ct_jac_f(prm, m, Fj);
+            for (int r = 0; r < nx; ++r) {
+                double s = fm[r];
+                for (int q = 0; q < nx; ++q)
+                    s -= Fj[r * nx + q] * m[q];
+                c[(long)j * nx + r] = s;
+            }
+            memcpy(SL + (long)j * 25, LQ, sizeof(LQ));
+            or_ct_h(prm, m1, y + (long)j * ny, hm);
+            or_ct_jac_h(prm, m1, Hj);
+            for (int r = 0; r < ny; ++r) {
+                double s = hm[r];
+                for (int q = 0; q < nx; ++q)
+                    s -= Hj[r * nx + q] * m1[q];
+                d[(long)j * ny + r] = s;
+            }
+            memcpy(SO + (long)j * 4, SOn, sizeof(SOn));
+        }
+        return 0;
+    }
     for (int j = 0; j < n; ++j) {
         double Xp[25], Xm[25], Zp[25], Zm[25], Yp[10], Ym[10];
         const double *m = ms + (long)j * nx, *N = Ns + (long)j * nx * nx;
@@ -1103,7 +1192,7 @@ int or_ct_linearize(int n, const double *prm, const double *ms, const double *Ns
 /* ([M][n+1][...]) and last_mf/last_Nf the filter output of the last pass.  */
 int or_ct_ipls(int n, const double *prm, const double *m0, const double *N0, const double *y,
                int M, double *ms, double *Ns, double *hist_ms, double *hist_Ns, double *last_mf,
-               double *last_Nf)
+               double *last_Nf, int method)
 {
     const int nx = 5, ny = 2;
     size_t nst = (size_t)(n + 1);
@@ -1113,7 +1202,7 @@ int or_ct_ipls(int n, const double *prm, const double *m0, const double *N0, con
     double *mf = malloc(sizeof(double) * nst * 5), *Nf = malloc(sizeof(double) * nst * 25);
     int rc = 0;
     for (int it = 0; it < M && rc == 0; ++it) {
-        if (or_ct_linearize(n, prm, ms, Ns, y, 0, F, c, SL, H, d, SO) != 0) {
+        if (or_ct_linearize(n, prm, ms, Ns, y, method, F, c, SL, H, d, SO) != 0) {
             rc = -1;
             break;
         }
@@ -1136,7 +1225,7 @@ int or_ct_ipls(int n, const double *prm, const double *m0, const double *N0, con
 /* given nominal: sum over k of log N(y_k; predicted mean, covariance).     */
 /* ell (optional, [n]) receives the per-step terms.                          */
 double or_ct_loglik(int n, const double *prm, const double *m0, const double *N0,
-                    const double *y, const double *ms, const double *Ns, double *ell)
+                    const double *y, const double *ms, const double *Ns, double *ell, int method)
 {
     const int nx = 5, ny = 2;
     size_t nst = (size_t)(n + 1);
@@ -1146,7 +1235,7 @@ double or_ct_loglik(int n, const double *prm, const double *m0, const double *N0
     double *mf = malloc(sizeof(double) * nst * 5), *Nf = malloc(sizeof(double) * nst * 25);
     double *l = malloc(sizeof(double) * (size_t)n);
     double total = NAN;
-    if (or_ct_linearize(n, prm, ms, Ns, y, 0, F, c, SL, H, d, SO) == 0) {
+    if (or_ct_linearize(n, prm, ms, Ns, y, method, F, c, SL, H, d, SO) == 0) {
         or_sqrt_filter(n, nx, ny, m0, N0, F, c, SL, H, d, SO, 1, y, mf, Nf, l);
         total = 0.0;
         for (int j = 0; j < n; ++j)
@@ -1256,7 +1345,7 @@ double or_lgssm_score_terms(int n, int nx, int ny, const double *m0, const doubl
 /* Lam_j = Q(theta) + R_j R_j^T and Om_j = sigma^2 I + R'_j R'_j^T, so       */
 /* dLam/dlog q1 = q1 Qv, dLam/dlog q2 = q2 Qw and dOm/dlog sigma = 2 s^2 I.  */
 double or_ct_score(int n, const double *prm, const double *m0, const double *N0,
-                   const double *y, const double *ms, const double *Ns, double *grad3)
+                   const double *y, const double *ms, const double *Ns, double *grad3, int method)
 {
     const int nx = 5, ny = 2;
     double *F = malloc(sizeof(double) * (size_t)n * 25), *c = malloc(sizeof(double) * (size_t)n * 5);
@@ -1266,7 +1355,7 @@ double or_ct_score(int n, const double *prm, const double *m0, const double *N0,
     double *Lbar = malloc(sizeof(double) * (size_t)n * 25), *Obar = malloc(sizeof(double) * (size_t)n * 4);
     double total = NAN;
     grad3[0] = grad3[1] = grad3[2] = NAN;
-    if (or_ct_linearize(n, prm, ms, Ns, y, 0, F, c, SL, H, d, SO) == 0) {
+    if (or_ct_linearize(n, prm, ms, Ns, y, method, F, c, SL, H, d, SO) == 0) {
         for (int j = 0; j < n; ++j) {
             mat_mult(nx, nx, nx, SL + (size_t)j * 25, SL + (size_t)j * 25, Lam + (size_t)j * 25);
             mat_mult(ny, ny, ny, SO + (size_t)j * 4, SO + (size_t)j * 4, Om + (size_t)j * 4);
@@ -1313,7 +1402,7 @@ int or_ct_ipls_batch(int B, const long *y_off, const double *prm, const double *
         long n = y_off[b + 1] - y_off[b];
         long xo = y_off[b] + b;
         rc |= or_ct_ipls((int)n, prm, m0, N0, y + y_off[b] * 2, M, ms + xo * 5, Ns + xo * 25,
-                         NULL, NULL, NULL, NULL);
+                         NULL, NULL, NULL, NULL, 0);
     }
     return rc;
 }
@@ -1350,7 +1439,7 @@ int or_ct_loglik_batch(int B, const long *y_off, const double *prm, const double
         long n = y_off[b + 1] - y_off[b];
         long xo = y_off[b] + b;
         ll[b] = or_ct_loglik((int)n, prm, m0, N0, y + y_off[b] * 2, ms + xo * 5, Ns + xo * 25,
-                             NULL);
+                             NULL, 0);
     }
     return 0;
 }
@@ -1364,7 +1453,7 @@ int or_ct_score_batch(int B, const long *y_off, const double *prm, const double 
         long n = y_off[b + 1] - y_off[b];
         long xo = y_off[b] + b;
         ll[b] = or_ct_score((int)n, prm, m0, N0, y + y_off[b] * 2, ms + xo * 5, Ns + xo * 25,
-                            grad3 + 3 * b);
+                            grad3 + 3 * b, 0);
     }
     return 0;
 }
