@@ -12,6 +12,8 @@ value = smoothed time steps per second = n * passes / seconds per step.
 
 Also in the line (same run):
   fp32            the same step in FP32
+  ieks_taylor     the same step with the first-order Taylor linearisation
+                  (the iterated extended smoother) instead of cubature SLR
   sequential      time per IPLS pass of the parallel scans vs the sequential
                   square-root kernel (one thread walks the sequence) at
                   n = 10^4 and 10^5 (prefixes of the same sequence)
@@ -190,11 +192,11 @@ def shapes(dtype, T_req, E_req, smoother=False):
 class Runner:
     """Device-resident buffers and a captured step for one batch."""
 
-    def __init__(self, w, dtype, dev, stream, T=0, E=0, graph=True):
+    def __init__(self, w, dtype, dev, stream, T=0, E=0, graph=True, linearization="cubature"):
         self.tdt = torch.float64 if dtype == "f64" else torch.float32
         self.w = w
         self.b = pss.Batch.ct(w.y_off, w.model, dtype=self.tdt, device=dev, scan_threads=T,
-                              scan_elems=E)
+                              scan_elems=E, linearization=linearization)
         self.yd = pss.to_soa(w.y, self.tdt, dev)
         self.m0, self.N0 = self.b.prior_nominal()
         self.m, self.N = self.m0.clone(), self.N0.clone()
@@ -451,6 +453,20 @@ def main():
             log("%s: %.3f ms/step" % (other, ms2))
             del R2
             torch.cuda.empty_cache()
+            # the iterated extended smoother (first-order Taylor linearisation,
+            # Section 4.2) on the same step, both precisions
+            ieks = {}
+            for dt in ("f64", "f32"):
+                R3 = Runner(full, dt, dev, stream, graph=not args.no_graph,
+                            linearization="taylor")
+                out3 = R3.prepare(1)
+                ms3, _ = R3.time_steps(max(2, args.steps // 2))
+                ieks[dt] = {"ms_per_step": round(ms3, 4), "value": round(n * M / (ms3 * 1e-3), 1),
+                            "nan_loglik": int(torch.isnan(out3[0]).sum().item())}
+                log("IEKS %s: %.3f ms/step" % (dt, ms3))
+                del R3
+                torch.cuda.empty_cache()
+            extras["ieks_taylor"] = ieks
             # parallel vs sequential square-root kernel, per IPLS pass
             seq = {}
             for nn in (10 ** 4, 10 ** 5):

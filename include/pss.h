@@ -74,6 +74,16 @@ typedef enum {
     PSS_MODEL_CT_BEARINGS = 1
 } pss_model_kind;
 
+/* linearisation of a nonlinear model (PSS_MODEL_CT_BEARINGS) */
+typedef enum {
+    /* statistical linear regression with the third-degree cubature rule
+       (Section 4.3): the iterated posterior-linearisation smoother */
+    PSS_LIN_CUBATURE = 0,
+    /* first-order Taylor expansion at the nominal mean (Section 4.2): the
+       iterated extended smoother; Lambda = Q, Omega = R */
+    PSS_LIN_TAYLOR = 1
+} pss_linearization;
+
 /* operations for pss_workspace_size */
 typedef enum {
     PSS_OP_SLR = 0,
@@ -106,6 +116,10 @@ typedef struct pss_problem {
        scans (default 4 for the filter scan, 2 for the smoother scan) */
     int32_t scan_threads;
     int32_t scan_elems;
+    /* pss_linearization used by every call that linearises the model
+       (slr_linearize, ipls_iterate, loglik, loglik_grad, ipls_batched,
+       sequential_smoother); 0 = cubature */
+    int32_t linearization;
 } pss_problem;
 
 /* Square-root linearisation parameters Gamma^sqrt (eq. Gamma-s), SoA over

@@ -370,6 +370,10 @@ static int validate(const pss_problem *p)
         set_error("scan_threads must be 0, 64, 128 or 256");
         return PSS_EINVAL;
     }
+    if (p->linearization != PSS_LIN_CUBATURE && p->linearization != PSS_LIN_TAYLOR) {
+        set_error("linearization must be PSS_LIN_CUBATURE or PSS_LIN_TAYLOR");
+        return PSS_EINVAL;
+    }
     if (p->scan_elems < 0 || p->scan_elems > 256) {
         set_error("scan_elems must be in 0..256");
         return PSS_EINVAL;

@@ -860,6 +860,99 @@ PSS_INL void ct_h(const CTParams<T> &P, const T (&x)[5], const T (&y)[2], T (&o)
 }
 
 // --------------------------------------------------------------------------
+// First-order Taylor linearisation (Section 4.2, the iterated extended
+// smoother): F = Jacobian of f at the nominal mean m, c = f(m) - F m,
+// S_Lambda = chol Q; H = Jacobian of the bearings at m, d = h~(m) - H m
+// (h~ on the branch nearest to y), S_Omega = sigma I.  The nominal factor is
+// not used.
+// --------------------------------------------------------------------------
+// g1 = d/dw [sin(w dt)/w] / dt^2 = (a cos a - sin a) / a^2 and
+// g2 = d/dw [(1 - cos(w dt))/w] / dt^2 = (a sin a - 1 + cos a) / a^2, a = w dt.
+// Both closed forms cancel as a -> 0 (relative error ~ eps / a^2), so below
+// a type-dependent switch point their power series are used.
+template <typename T> struct TaylorSwitch;
+template <> struct TaylorSwitch<double> { static constexpr double a = 1e-2; };
+template <> struct TaylorSwitch<float> { static constexpr float a = 0.3f; };
+
+template <typename T>
+PSS_INL void ct_dsw(T a, T &g1, T &g2)
+{
+    if (fabs(a) < TaylorSwitch<T>::a) {
+        const T a2 = a * a;
+        g1 = a * (T(-1) / T(3) + a2 * (T(1) / T(30) + a2 * (T(-1) / T(840) + a2 / T(45360))));
+        g2 = T(0.5) + a2 * (T(-1) / T(8) + a2 * (T(1) / T(144) - a2 / T(5760)));
+    } else {
+        const T ca = pcos(a), sa = psin(a), r = T(1) / (a * a);
+        g1 = (a * ca - sa) * r;
+        g2 = (a * sa - T(1) + ca) * r;
+    }
+}
+
+template <typename T>
+PSS_INL void ct_taylor_transition(const CTParams<T> &P, const Marg<T, 5> &mg, T (&F)[5][5],
+                                  T (&c)[5], T (&S)[5][5])
+{
+    const T dt = P.dt, a = mg.m[4] * dt, h = T(0.5) * a;
+    const T sh = sinc_(h);
+    const T s1 = dt * sinc_(a), s2 = dt * h * sh * sh;
+    const T ca = pcos(a), sa = psin(a), vx = mg.m[2], vy = mg.m[3];
+    T g1, g2;
+    ct_dsw(a, g1, g2);
+    const T d1 = dt * dt * g1, d2 = dt * dt * g2;
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+#pragma unroll
+        for (int j = 0; j < 5; ++j)
+            F[i][j] = T(0);
+    F[0][0] = T(1);
+    F[0][2] = s1;
+    F[0][3] = -s2;
+    F[0][4] = d1 * vx - d2 * vy;
+    F[1][1] = T(1);
+    F[1][2] = s2;
+    F[1][3] = s1;
+    F[1][4] = d2 * vx + d1 * vy;
+    F[2][2] = ca;
+    F[2][3] = -sa;
+    F[2][4] = -dt * (sa * vx + ca * vy);
+    F[3][2] = sa;
+    F[3][3] = ca;
+    F[3][4] = dt * (ca * vx - sa * vy);
+    F[4][4] = T(1);
+    T fx[5];
+    ct_f(P, mg.m, fx);
+    T Fm[5];
+    mv(F, mg.m, Fm);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        c[i] = fx[i] - Fm[i];
+#pragma unroll
+        for (int j = 0; j < 5; ++j)
+            S[i][j] = P.LQ[i][j];
+    }
+}
+
+template <typename T>
+PSS_INL void ct_taylor_bearings(const CTParams<T> &P, const Marg<T, 5> &mg, const T (&y)[2],
+                                T (&H)[2][5], T (&d)[2], T (&S)[2][2])
+{
+    const T sx[2] = {P.s1x, P.s2x}, sy[2] = {P.s1y, P.s2y};
+    T hx[2];
+    ct_h(P, mg.m, y, hx);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const T dx = mg.m[0] - sx[s], dy = mg.m[1] - sy[s];
+        const T r = T(1) / (dx * dx + dy * dy);
+        H[s][0] = -dy * r;
+        H[s][1] = dx * r;
+        H[s][2] = H[s][3] = H[s][4] = T(0);
+        d[s] = hx[s] - (H[s][0] * mg.m[0] + H[s][1] * mg.m[1]);
+        S[s][0] = s == 0 ? P.sigma : T(0);
+        S[s][1] = s == 1 ? P.sigma : T(0);
+    }
+}
+
+// --------------------------------------------------------------------------
 // Cubature SLR (Section 4.3) in the residual form.  With the sigma points
 // X+-_i = m +- sqrt(nx) N e_i (equal weights 1/(2 nx)) and their images
 // written as z+-_i = r + e+-_i (a common reference r plus deviations),

@@ -545,7 +545,8 @@ int Core<T, NX, NY>::slr(const Ctx &c, const void *m, const void *N, const void 
         KTime kt(c.s, "slr", "", 0);
         hipLaunchKernelGGL((k_slr_ct<T>), dim3((unsigned)((c.T_x + tb - 1) / tb)), dim3(tb), 0,
                            c.s, c.p->y_off, c.B, c.T_x, c.T_y, P, marg_ref2(m, N, c.T_x),
-                           cptr<T>(y), gamma_ref(out, c.T_y));
+                           cptr<T>(y), gamma_ref(out, c.T_y),
+                           c.p->linearization == PSS_LIN_TAYLOR ? 1 : 0);
         return hip_check(hipGetLastError(), "slr launch");
     } else {
         set_error("the coordinated-turn model needs nx = 5, ny = 2");

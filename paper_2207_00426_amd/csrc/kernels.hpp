@@ -1046,7 +1046,7 @@ __global__ __launch_bounds__(64) void k_sequential(const int64_t *y_off, int B, 
 template <typename T>
 __global__ __launch_bounds__(128) void k_slr_ct(const int64_t *y_off, int B, int64_t T_x,
                                                 int64_t T_y, CTParams<T> P, MargRef<T, 5> nom,
-                                                const T *y, GammaRef<T, 5, 2> out)
+                                                const T *y, GammaRef<T, 5, 2> out, int taylor)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= T_x)
@@ -1057,14 +1057,20 @@ __global__ __launch_bounds__(128) void k_slr_ct(const int64_t *y_off, int B, int
     nom.load(s, mg);
     if (k < n) {
         T G[5][5], off[5], S[5][5];
-        ct_slr_transition(P, mg, G, off, S);
+        if (taylor)
+            ct_taylor_transition(P, mg, G, off, S);
+        else
+            ct_slr_transition(P, mg, G, off, S);
         out.store_trans(y_off[b] + k, G, off, S);
     }
     if (k >= 1) {
         const int64_t t = y_off[b] + k - 1;
         T yy[2] = {y[t], y[T_y + t]};
         T G[2][5], off[2], S[2][2];
-        ct_slr_bearings(P, mg, yy, G, off, S);
+        if (taylor)
+            ct_taylor_bearings(P, mg, yy, G, off, S);
+        else
+            ct_slr_bearings(P, mg, yy, G, off, S);
         out.store_obs(t, G, off, S);
     }
 }

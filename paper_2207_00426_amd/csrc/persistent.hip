@@ -253,6 +253,7 @@ int run(const pss_group *gs, int ng, int n_iter, int32_t *status, void *ws, size
         b_all += p->B;
         G.E_f = sh.E_f;
         G.E_s = sh.E_s;
+        G.taylor = p->linearization == PSS_LIN_TAYLOR ? 1 : 0;
         G.stage_f = scan_stage(65, 20, sh.T, sh.E_f, sizeof(T));
         G.stage_s = scan_stage(45, 20, sh.T, sh.E_s, sizeof(T));
         G.y_off = p->y_off;

@@ -35,6 +35,7 @@ struct PGroup {
     int B;
     int E_f, E_s;
     int stage_f, stage_s; // outputs staged through LDS (see apply_phase)
+    int taylor;           // CT: first-order Taylor instead of cubature SLR
     const int64_t *y_off;
     int64_t T_y, T_x;
     const T *y;
@@ -198,8 +199,13 @@ struct FusedFiltSrc {
             Marg<T, NX> prev, cur;
             nom.load(x0 + p, prev);
             nom.load(x0 + p + 1, cur);
-            ct_slr_transition(G->ct, prev, F, c, SL);
-            ct_slr_bearings(G->ct, cur, yy, H, d, SO);
+            if (G->taylor) {
+                ct_taylor_transition(G->ct, prev, F, c, SL);
+                ct_taylor_bearings(G->ct, cur, yy, H, d, SO);
+            } else {
+                ct_slr_transition(G->ct, prev, F, c, SL);
+                ct_slr_bearings(G->ct, cur, yy, H, d, SO);
+            }
             trans_ref_dev<T, NX>(G->gstash, G->T_y).store(s, F, c, SL);
         } else {
             GammaRef<T, NX, NY> gr;

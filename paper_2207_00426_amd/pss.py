@@ -25,6 +25,8 @@ LIB_PATH = os.path.join(_HERE, "libpss.so")
 
 PSS_F32, PSS_F64 = 0, 1
 MODEL_LINEAR, MODEL_CT = 0, 1
+LIN_CUBATURE, LIN_TAYLOR = 0, 1
+LINEARIZATIONS = {"cubature": LIN_CUBATURE, "taylor": LIN_TAYLOR}
 OPS = dict(slr=0, filter_elements=1, filter_scan=2, smoother_scan=3, ipls=4, loglik=5,
            loglik_grad=6, sequential=7)
 STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported", -3: "workspace too small",
@@ -50,7 +52,8 @@ class Problem(ctypes.Structure):
                 ("m0", ctypes.c_void_p), ("N0", ctypes.c_void_p),
                 ("dt", ctypes.c_double), ("theta", ctypes.c_double * 3),
                 ("sensors", ctypes.c_double * 4),
-                ("scan_threads", ctypes.c_int32), ("scan_elems", ctypes.c_int32)]
+                ("scan_threads", ctypes.c_int32), ("scan_elems", ctypes.c_int32),
+                ("linearization", ctypes.c_int32)]
 
 
 class GroupC(ctypes.Structure):
@@ -218,7 +221,7 @@ class Batch:
 
     def __init__(self, model, dtype, nx, ny, y_off, m0, N0, device="cuda", dt=0.0,
                  theta=(0.0, 0.0, 0.0), sensors=(0.0, 0.0, 0.0, 0.0), scan_threads=0,
-                 scan_elems=0):
+                 scan_elems=0, linearization="cubature"):
         self.model = model
         self.torch_dtype = dtype
         self.nx, self.ny = nx, ny
@@ -236,6 +239,7 @@ class Batch:
         self.sensors = tuple(float(v) for v in sensors)
         self.scan_threads = int(scan_threads)
         self.scan_elems = int(scan_elems)
+        self.linearization = LINEARIZATIONS[linearization]
 
     @classmethod
     def ct(cls, y_off, model, dtype=torch.float64, device="cuda", theta=None, **kw):
@@ -264,6 +268,7 @@ class Batch:
         p.sensors = (ctypes.c_double * 4)(*self.sensors)
         p.scan_threads = self.scan_threads
         p.scan_elems = self.scan_elems
+        p.linearization = getattr(self, "linearization", LIN_CUBATURE)
         return p
 
     # buffers -------------------------------------------------------------
