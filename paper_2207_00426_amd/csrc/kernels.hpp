@@ -664,7 +664,7 @@ constexpr bool reg_accumulator()
     return sizeof(typename Op::T) * Op::NE <= 260;
 }
 
-template <class Op, class Src>
+template <class Op, class Src, bool RegAcc = reg_accumulator<Op>()>
 PSS_INL void fold_phase(const LevelGeom &g, const TileInfo &ti, const Src &src,
                         typename Op::T *lds, int Tb)
 {
@@ -674,7 +674,7 @@ PSS_INL void fold_phase(const LevelGeom &g, const TileInfo &ti, const Src &src,
         int64_t pe = p0 + g.E;
         if (pe > ti.start + ti.tcnt)
             pe = ti.start + ti.tcnt;
-        if constexpr (reg_accumulator<Op>()) {
+        if constexpr (RegAcc) {
             typename Op::Elem a;
             const auto acc = Op::reg(a);
             src_first<Op>(src, ti, p0, acc);

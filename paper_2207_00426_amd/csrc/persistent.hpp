@@ -284,7 +284,37 @@ struct FusedSmoothSrc {
     }
 };
 
-// ---- one tile of a phase ----------------------------------------------------
+// A tile first builds all its elements (each thread its own chunk, written to
+// the tile-interleaved stash), then folds them back lazily: the model
+// linearisation and element construction never share registers with the
+// fold's operator, so the kernel's register peak is the larger of the two
+// phases rather than their sum.
+template <class Src>
+struct Stashed {
+    static constexpr bool lazy_up = true, lazy_down = true;
+    static constexpr int leaf_nz = Src::leaf_nz;
+    Src src;
+    PSS_INL auto uview(const TileInfo &ti, int64_t p) const { return src.dview(ti, p); }
+    PSS_INL auto dview(const TileInfo &ti, int64_t p) const { return src.dview(ti, p); }
+};
+
+template <class Op, class Src>
+PSS_INL void build_phase(const LevelGeom &g, const TileInfo &ti, const Src &src)
+{
+    const int tid = threadIdx.x;
+    if (tid < ti.nvalid) {
+        const int64_t p0 = ti.start + (int64_t)tid * g.E;
+        int64_t pe = p0 + g.E;
+        if (pe > ti.start + ti.tcnt)
+            pe = ti.start + ti.tcnt;
+        for (int64_t p = p0; p < pe; ++p) {
+            typename Op::Elem e;
+            src.up(ti, p, e); // builds and stashes
+        }
+    }
+}
+
+// ---- one tile of a phase ----------------------------------------------------// ---- one tile of a phase ----------------------------------------------------
 template <typename T, int NX, int NY, bool CT>
 PSS_INL void filter_tile(const PArgs<T> &a, const PGroup<T> &G, int64_t gt, T *lds)
 {
@@ -310,7 +340,9 @@ PSS_INL void filter_tile(const PArgs<T> &a, const PGroup<T> &G, int64_t gt, T *l
     ti.nvalid = (ti.tcnt + g.E - 1) / g.E;
     ti.E = g.E;
     const int Tb = blockDim.x;
-    FusedFiltSrc<T, NX, NY, CT> src{&G, G.y_off[b] + b};
+    FusedFiltSrc<T, NX, NY, CT> build{&G, G.y_off[b] + b};
+    build_phase<Op>(g, ti, build);
+    Stashed<FusedFiltSrc<T, NX, NY, CT>> src{build};
     fold_phase<Op>(g, ti, src, lds, Tb);
     tree_up<Op>(lds, Tb, ti.nvalid);
     typename Op::Pre excl;
@@ -377,7 +409,9 @@ PSS_INL void smoother_tile(const PArgs<T> &a, const PGroup<T> &G, int64_t gu, T 
     }
     __syncthreads();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    FusedSmoothSrc<T, NX, NY, CT> src{&G, G.y_off[b]};
+    FusedSmoothSrc<T, NX, NY, CT> build{&G, G.y_off[b]};
+    build_phase<Op>(g, ti, build);
+    Stashed<FusedSmoothSrc<T, NX, NY, CT>> src{build};
     fold_phase<Op>(g, ti, src, lds, Tb);
     tree_up<Op>(lds, Tb, ti.nvalid);
     typename Op::Pre excl;
