@@ -84,6 +84,20 @@ typedef enum {
     PSS_LIN_TAYLOR = 1
 } pss_linearization;
 
+/* form of the parallel filter and smoother */
+typedef enum {
+    /* square-root form (Lemmas 1-4, right columns of Tables 1-5): the
+       library's method */
+    PSS_FORM_SQRT = 0,
+    /* standard covariance form (left columns of Tables 1-5), for comparison;
+       honoured by pss_slr_linearize, pss_ipls_iterate and pss_loglik only.
+       The "N" buffers of marginals, the nominal's included (on input and on
+       output), then hold the packed lower triangle of the covariance P, not a
+       factor; the cubature SLR factors P itself (Cholesky).  The prior is
+       still given as a factor N0. */
+    PSS_FORM_COV = 1
+} pss_form;
+
 /* operations for pss_workspace_size */
 typedef enum {
     PSS_OP_SLR = 0,
@@ -120,6 +134,8 @@ typedef struct pss_problem {
        (slr_linearize, ipls_iterate, loglik, loglik_grad, ipls_batched,
        sequential_smoother); 0 = cubature */
     int32_t linearization;
+    /* pss_form; 0 = square root */
+    int32_t form;
 } pss_problem;
 
 /* Square-root linearisation parameters Gamma^sqrt (eq. Gamma-s), SoA over

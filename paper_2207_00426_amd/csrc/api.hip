@@ -370,6 +370,10 @@ static int validate(const pss_problem *p)
         set_error("scan_threads must be 0, 64, 128 or 256");
         return PSS_EINVAL;
     }
+    if (p->form != PSS_FORM_SQRT && p->form != PSS_FORM_COV) {
+        set_error("form must be PSS_FORM_SQRT or PSS_FORM_COV");
+        return PSS_EINVAL;
+    }
     if (p->linearization != PSS_LIN_CUBATURE && p->linearization != PSS_LIN_TAYLOR) {
         set_error("linearization must be PSS_LIN_CUBATURE or PSS_LIN_TAYLOR");
         return PSS_EINVAL;
@@ -423,6 +427,16 @@ static int check_ws(const Ctx &c, int op, const void *ws, size_t ws_bytes)
 } // namespace pss
 
 using namespace pss;
+
+// entry points of the square-root form only
+static int need_sqrt(const pss_problem *p, const char *what)
+{
+    if (p->form != PSS_FORM_SQRT) {
+        set_error(std::string(what) + " is defined for the square-root form only");
+        return PSS_EUNSUPPORTED;
+    }
+    return PSS_OK;
+}
 
 #define PSS_GUARD(expr)                                                                          \
     do {                                                                                         \
@@ -552,6 +566,8 @@ int pss_sqrt_filter_elements(const pss_problem *p, const pss_gamma *g, const voi
         int rc = validate(p);
         if (rc)
             return rc;
+        if ((rc = need_sqrt(p, "sqrt_filter_elements")))
+            return rc;
         if (!gamma_ok(g) || !y || !out || !out->A || !out->b || !out->U || !out->eta ||
             !out->Z) {
             set_error("sqrt_filter_elements: null buffer");
@@ -571,6 +587,8 @@ int pss_sqrt_filter_scan(const pss_problem *p, const pss_felem *el, void *m_f, v
     PSS_GUARD(([&]() -> int {
         int rc = validate(p);
         if (rc)
+            return rc;
+        if ((rc = need_sqrt(p, "sqrt_filter_scan")))
             return rc;
         if (!el || !el->A || !el->b || !el->U || !el->eta || !el->Z || !m_f || !N_f) {
             set_error("sqrt_filter_scan: null buffer");
@@ -593,6 +611,8 @@ int pss_sqrt_smoother_scan(const pss_problem *p, const pss_gamma *g, const void 
     PSS_GUARD(([&]() -> int {
         int rc = validate(p);
         if (rc)
+            return rc;
+        if ((rc = need_sqrt(p, "sqrt_smoother_scan")))
             return rc;
         if (!gamma_ok(g) || !m_f || !N_f || !m_s || !N_s) {
             set_error("sqrt_smoother_scan: null buffer");
@@ -667,6 +687,8 @@ int pss_loglik_grad(const pss_problem *p, const void *m_nom, const void *N_nom, 
         int rc = validate(p);
         if (rc)
             return rc;
+        if ((rc = need_sqrt(p, "loglik_grad")))
+            return rc;
         if (p->model != PSS_MODEL_CT_BEARINGS) {
             set_error("loglik_grad: theta is defined for the coordinated-turn model");
             return PSS_EUNSUPPORTED;
@@ -692,6 +714,8 @@ int pss_sequential_smoother(const pss_problem *p, const pss_gamma *g, const void
     PSS_GUARD(([&]() -> int {
         int rc = validate(p);
         if (rc)
+            return rc;
+        if ((rc = need_sqrt(p, "sequential_smoother")))
             return rc;
         if (!y || !m_nom || !N_nom || n_iter < 0 || ((m_f == nullptr) != (N_f == nullptr))) {
             set_error("sequential_smoother: null buffer or negative n_iter");

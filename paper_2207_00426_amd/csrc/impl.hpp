@@ -279,8 +279,9 @@ struct Core {
 
     // ilv: the elements are stored tile-interleaved for this scan's level 0
     // (as written by felem(..., true)); the library's own passes use that
+    // cov: the standard (covariance-form) scan of the same storage layout
     static int fscan(const Ctx &c, const pss_felem *el, void *mf, void *Nf, void *ws,
-                     bool ilv = false)
+                     bool ilv = false, bool cov = false)
     {
         const ScanShape sh = filter_shape(c);
         Carver cv{static_cast<char *>(ws)};
@@ -296,6 +297,18 @@ struct Core {
         StartPre<T, NX> st{cptr<T>(c.p->m0), cptr<T>(c.p->N0)};
         // finest-level elements: Z = Tria([Z_k, 0]) with Z_k of ny columns
         constexpr int LZ = NY < NX ? NY : NX;
+        if (cov) {
+            using FSC = FilterScanCov<T, NX>;
+            StartPreCov<T, NX> stc{cptr<T>(c.p->m0), cptr<T>(c.p->N0)};
+            Carver cc{static_cast<char *>(ws)};
+            auto wc = carve_scan<FSC>(cc, c, sh);
+            if (ilv) {
+                RefSrc<FSC, FElemRef<T, NX>, true> src{er};
+                return run_scan<FSC>(c, sh, wc, 0, src, dst, stc, &felem_ref);
+            }
+            RefSrc<FSC, FElemRef<T, NX>> src{er};
+            return run_scan<FSC>(c, sh, wc, 0, src, dst, stc, &felem_ref);
+        }
         if (ilv) {
             RefSrc<FS, FElemRef<T, NX>, true, LZ> src{er};
             return run_scan<FS>(c, sh, w, 0, src, dst, st, &felem_ref);
@@ -305,21 +318,29 @@ struct Core {
     }
 
     static int sscan(const Ctx &c, const pss_gamma *g, const void *mf, const void *Nf, void *ms,
-                     void *Ns, void *ws)
+                     void *Ns, void *ws, bool cov = false)
     {
         const ScanShape sh = smoother_shape(c);
         Carver cv{static_cast<char *>(ws)};
         auto w = carve_scan<SS>(cv, c, sh);
         T *stash = cv.template take<T>((size_t)Sizes<NX>::selem * c.T_x);
-        SmootherSrc<T, NX, NY> src{gamma_ref(g, c.T_y), marg_ref2(mf, Nf, c.T_x),
-                                   selem_ref(stash, c.T_x), c.p->y_off};
         SmoothDst<T, NX> dst{marg_ref2(ms, Ns, c.T_x)};
         StartPre<T, NX> st{nullptr, nullptr};
+        if (cov) {
+            using SSC = SmootherScanCov<T, NX>;
+            Carver cc{static_cast<char *>(ws)};
+            auto wc = carve_scan<SSC>(cc, c, sh);
+            SmootherSrc<T, NX, NY, true> src{gamma_ref(g, c.T_y), marg_ref2(mf, Nf, c.T_x),
+                                             selem_ref(stash, c.T_x), c.p->y_off};
+            return run_scan<SSC>(c, sh, wc, 1, src, dst, st, &selem_ref);
+        }
+        SmootherSrc<T, NX, NY> src{gamma_ref(g, c.T_y), marg_ref2(mf, Nf, c.T_x),
+                                   selem_ref(stash, c.T_x), c.p->y_off};
         return run_scan<SS>(c, sh, w, 1, src, dst, st, &selem_ref);
     }
 
     static int felem(const Ctx &c, const pss_gamma *g, const void *y, const pss_felem *out,
-                     bool ilv = false)
+                     bool ilv = false, bool cov = false)
     {
         int ilv_T = 0, ilv_E = 0;
         if (ilv) {
@@ -335,10 +356,16 @@ struct Core {
         er.Z = mptr<T>(out->Z);
         er.ld = c.T_y;
         const int tb = 128;
-        KTime kt(c.s, "filter_elements", "", 0);
-        hipLaunchKernelGGL((k_filter_elements<T, NX, NY>), dim3((unsigned)((c.T_y + tb - 1) / tb)),
-                           dim3(tb), 0, c.s, c.p->y_off, c.B, c.T_y, gamma_ref(g, c.T_y),
-                           cptr<T>(y), cptr<T>(c.p->m0), cptr<T>(c.p->N0), er, ilv_T, ilv_E);
+        KTime kt(c.s, cov ? "filter_elements_cov" : "filter_elements", "", 0);
+        const dim3 grid((unsigned)((c.T_y + tb - 1) / tb));
+        if (cov)
+            hipLaunchKernelGGL((k_filter_elements<T, NX, NY, true>), grid, dim3(tb), 0, c.s,
+                               c.p->y_off, c.B, c.T_y, gamma_ref(g, c.T_y), cptr<T>(y),
+                               cptr<T>(c.p->m0), cptr<T>(c.p->N0), er, ilv_T, ilv_E);
+        else
+            hipLaunchKernelGGL((k_filter_elements<T, NX, NY>), grid, dim3(tb), 0, c.s,
+                               c.p->y_off, c.B, c.T_y, gamma_ref(g, c.T_y), cptr<T>(y),
+                               cptr<T>(c.p->m0), cptr<T>(c.p->N0), er, ilv_T, ilv_E);
         return hip_check(hipGetLastError(), "filter elements launch");
     }
 
@@ -410,14 +437,15 @@ struct Core {
         void *mf = mf_out ? mf_out : (void *)mfb;
         void *Nf = mf_out ? Nf_out : (void *)(mfb + (size_t)NX * c.T_x);
         int rc = PSS_OK;
+        const bool cov = c.p->form == PSS_FORM_COV;
         for (int it = 0; it < n_iter && rc == PSS_OK; ++it) {
             if (is_ct(c) && (rc = slr(c, m_nom, N_nom, y, &gw)))
                 break;
-            if ((rc = felem(c, g, y, &el, true)))
+            if ((rc = felem(c, g, y, &el, true, cov)))
                 break;
-            if ((rc = fscan(c, &el, mf, Nf, scan_ws, true)))
+            if ((rc = fscan(c, &el, mf, Nf, scan_ws, true, cov)))
                 break;
-            rc = sscan(c, g, mf, Nf, m_nom, N_nom, scan_ws);
+            rc = sscan(c, g, mf, Nf, m_nom, N_nom, scan_ws, cov);
         }
         return rc;
     }
@@ -440,16 +468,22 @@ struct Core {
         int rc;
         if (is_ct(c) && (rc = slr(c, m_nom, N_nom, y, &gw)))
             return rc;
-        if ((rc = felem(c, g, y, &el, true)))
+        const bool cov = c.p->form == PSS_FORM_COV;
+        if ((rc = felem(c, g, y, &el, true, cov)))
             return rc;
-        if ((rc = fscan(c, &el, mfb, mfb + (size_t)NX * c.T_x, scan_ws, true)))
+        if ((rc = fscan(c, &el, mfb, mfb + (size_t)NX * c.T_x, scan_ws, true, cov)))
             return rc;
         const int tb = 128;
         KTime kt(c.s, "loglik_terms", "", 0);
-        hipLaunchKernelGGL((k_loglik_terms<T, NX, NY>),
-                           dim3((unsigned)((c.T_y + tb - 1) / tb)), dim3(tb), 0, c.s,
-                           c.p->y_off, c.B, c.T_y, c.T_x, gamma_ref(g, c.T_y), cptr<T>(y),
-                           marg_ref(mfb, c.T_x), ell);
+        const dim3 grid((unsigned)((c.T_y + tb - 1) / tb));
+        if (cov)
+            hipLaunchKernelGGL((k_loglik_terms_cov<T, NX, NY>), grid, dim3(tb), 0, c.s, c.p->y_off,
+                               c.B, c.T_y, c.T_x, gamma_ref(g, c.T_y), cptr<T>(y),
+                               marg_ref(mfb, c.T_x), ell);
+        else
+            hipLaunchKernelGGL((k_loglik_terms<T, NX, NY>), grid, dim3(tb), 0, c.s, c.p->y_off,
+                               c.B, c.T_y, c.T_x, gamma_ref(g, c.T_y), cptr<T>(y),
+                               marg_ref(mfb, c.T_x), ell);
         if ((rc = hip_check(hipGetLastError(), "loglik launch")))
             return rc;
         return launch_seq_sum(c, 1, ell, c.T_y, ll, scan_ws);
@@ -546,7 +580,8 @@ int Core<T, NX, NY>::slr(const Ctx &c, const void *m, const void *N, const void 
         hipLaunchKernelGGL((k_slr_ct<T>), dim3((unsigned)((c.T_x + tb - 1) / tb)), dim3(tb), 0,
                            c.s, c.p->y_off, c.B, c.T_x, c.T_y, P, marg_ref2(m, N, c.T_x),
                            cptr<T>(y), gamma_ref(out, c.T_y),
-                           c.p->linearization == PSS_LIN_TAYLOR ? 1 : 0);
+                           c.p->linearization == PSS_LIN_TAYLOR ? 1 : 0,
+                           c.p->form == PSS_FORM_COV ? 1 : 0);
         return hip_check(hipGetLastError(), "slr launch");
     } else {
         set_error("the coordinated-turn model needs nx = 5, ny = 2");

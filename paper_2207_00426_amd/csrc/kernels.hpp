@@ -20,6 +20,7 @@
 #pragma once
 
 #include "common.hpp"
+#include "device_cov.hpp"
 #include "device_ops.hpp"
 
 namespace pss {
@@ -321,6 +322,69 @@ struct SmootherScan {
     }
 };
 
+// Standard (covariance-form) scans over the same storage (device_cov.hpp)
+template <typename T_, int NX_>
+struct FilterScanCov {
+    using T = T_;
+    static constexpr int NX = NX_;
+    using Elem = FElem<T, NX>;
+    using Pre = Marg<T, NX>;
+    static constexpr int NE = Sizes<NX>::felem;
+    static constexpr int NP = Sizes<NX>::marg;
+    static constexpr const char *name = "filter_cov";
+    PSS_INL static FSlotV<T, NX, int> slot(T *lds, int Tb, int s)
+    {
+        return FSlotV<T, NX, int>{lds + s, Tb};
+    }
+    PSS_INL static FRegV<T, NX> reg(Elem &e) { return FRegV<T, NX>{&e}; }
+    template <int NZ = NX, class VA, class VB, class VO>
+    PSS_INL static void combine_v(const VA &a, const VB &b, const VO &o)
+    {
+        filter_combine_cov_v<T, NX>(a, b, o);
+    }
+    template <int NZ = NX, class VA>
+    PSS_INL static void apply_v(const Pre &p, const VA &a, Pre &o)
+    {
+        filter_apply_cov_v<T, NX>(p, a, o);
+    }
+    template <class VS, class VD>
+    PSS_INL static void copy_v(const VS &src, const VD &dst)
+    {
+        felem_copy<T, NX>(src, dst);
+    }
+};
+
+template <typename T_, int NX_>
+struct SmootherScanCov {
+    using T = T_;
+    static constexpr int NX = NX_;
+    using Elem = SElem<T, NX>;
+    using Pre = Marg<T, NX>;
+    static constexpr int NE = Sizes<NX>::selem;
+    static constexpr int NP = Sizes<NX>::marg;
+    static constexpr const char *name = "smoother_cov";
+    PSS_INL static SSlotV<T, NX, int> slot(T *lds, int Tb, int s)
+    {
+        return SSlotV<T, NX, int>{lds + s, Tb};
+    }
+    PSS_INL static SRegV<T, NX> reg(Elem &e) { return SRegV<T, NX>{&e}; }
+    template <int NZ = NX, class VA, class VB, class VO>
+    PSS_INL static void combine_v(const VA &a, const VB &b, const VO &o)
+    {
+        smoother_combine_cov_v<T, NX>(b, a, o);
+    }
+    template <int NZ = NX, class VA>
+    PSS_INL static void apply_v(const Pre &p, const VA &a, Pre &o)
+    {
+        smoother_apply_cov_v<T, NX>(a, p, o);
+    }
+    template <class VS, class VD>
+    PSS_INL static void copy_v(const VS &src, const VD &dst)
+    {
+        selem_copy<T, NX>(src, dst);
+    }
+};
+
 // LDS object access, component-major
 template <class Obj, typename T>
 PSS_INL void lds_get(Obj &o, const T *lds, int Tb, int s)
@@ -499,7 +563,7 @@ struct RefSrc {
 // smoother level 0: element of state k = n - p built from the transition
 // linearisation of slot (b, k) and the filtering marginal at k (Table 4),
 // stashed (tile-interleaved) during the up phase and re-read afterwards.
-template <typename T, int NX, int NY>
+template <typename T, int NX, int NY, bool COV = false>
 struct SmootherSrc {
     static constexpr bool lazy_up = false, lazy_down = true;
     static constexpr int leaf_nz = 0;
@@ -513,11 +577,14 @@ struct SmootherSrc {
         Marg<T, NX> f;
         filt.load(ti.off + k, f);
         if (k == n) {
-            smoother_element_last(f, e);
+            smoother_element_last(f, e); // {0, m, N}: also {0, m, P} in covariance form
         } else {
             T F[NX][NX], c[NX], S[NX][NX];
             gam.load_trans(y_off[ti.b] + k, F, c, S);
-            smoother_element(F, c, S, f, e);
+            if constexpr (COV)
+                smoother_element_cov(F, c, S, f, e);
+            else
+                smoother_element(F, c, S, f, e);
         }
         stash.store(ilv_slot(ti, p), e);
     }
@@ -602,6 +669,28 @@ struct StartPre {
 #pragma unroll
             for (int j = 0; j <= i; ++j)
                 p.N[i][j] = m0 ? N0[tri_idx(i, j)] : T(0);
+        }
+    }
+};
+
+// covariance form: the prior (m0, P0 = N0 N0^T)
+template <typename T, int NX>
+struct StartPreCov {
+    const T *m0;
+    const T *N0; // packed lower factor
+    PSS_INL void get(Marg<T, NX> &p) const
+    {
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+            p.m[i] = m0[i];
+#pragma unroll
+            for (int j = 0; j <= i; ++j) {
+                T s = T(0);
+#pragma unroll
+                for (int t = 0; t <= j; ++t)
+                    s = pfma(N0[tri_idx(i, t)], N0[tri_idx(j, t)], s);
+                p.N[i][j] = s;
+            }
         }
     }
 };
@@ -814,7 +903,7 @@ __global__ __launch_bounds__(1024) void k_plan(PlanArgs a);
 // ---------------------------------------------------------------------------
 // element-wise kernels
 // ---------------------------------------------------------------------------
-template <typename T, int NX, int NY>
+template <typename T, int NX, int NY, bool COV = false>
 __global__ __launch_bounds__(128) void k_filter_elements(const int64_t *y_off, int B, int64_t T_y,
                                                          GammaRef<T, NX, NY> gam, const T *y,
                                                          const T *m0, const T *N0,
@@ -851,9 +940,15 @@ __global__ __launch_bounds__(128) void k_filter_elements(const int64_t *y_off, i
             for (int j = 0; j <= i; ++j)
                 N[i][j] = N0[tri_idx(i, j)];
         }
-        filter_element_first(m, N, F, c, SL, H, d, SO, yy, e);
+        if constexpr (COV)
+            filter_element_first_cov(m, N, F, c, SL, H, d, SO, yy, e);
+        else
+            filter_element_first(m, N, F, c, SL, H, d, SO, yy, e);
     } else {
-        filter_element(F, c, SL, H, d, SO, yy, e);
+        if constexpr (COV)
+            filter_element_cov(F, c, SL, H, d, SO, yy, e);
+        else
+            filter_element(F, c, SL, H, d, SO, yy, e);
     }
     out.store(i, e);
 }
@@ -1046,7 +1141,8 @@ __global__ __launch_bounds__(64) void k_sequential(const int64_t *y_off, int B, 
 template <typename T>
 __global__ __launch_bounds__(128) void k_slr_ct(const int64_t *y_off, int B, int64_t T_x,
                                                 int64_t T_y, CTParams<T> P, MargRef<T, 5> nom,
-                                                const T *y, GammaRef<T, 5, 2> out, int taylor)
+                                                const T *y, GammaRef<T, 5, 2> out, int taylor,
+                                                int nominal_cov)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= T_x)
@@ -1055,6 +1151,17 @@ __global__ __launch_bounds__(128) void k_slr_ct(const int64_t *y_off, int B, int
     const int64_t x0 = y_off[b] + b, k = s - x0, n = y_off[b + 1] - y_off[b];
     Marg<T, 5> mg;
     nom.load(s, mg);
+    if (nominal_cov && !taylor) {
+        // covariance form: the nominal holds P; the sigma points need a factor
+        T P[5][5], L[5][5];
+        sym_full(P, [&](int i, int j) { return mg.N[i][j]; });
+        chol_lower(P, L);
+#pragma unroll
+        for (int i = 0; i < 5; ++i)
+#pragma unroll
+            for (int j = 0; j <= i; ++j)
+                mg.N[i][j] = L[i][j];
+    }
     if (k < n) {
         T G[5][5], off[5], S[5][5];
         if (taylor)
@@ -1073,6 +1180,68 @@ __global__ __launch_bounds__(128) void k_slr_ct(const int64_t *y_off, int B, int
             ct_slr_bearings(P, mg, yy, G, off, S);
         out.store_obs(t, G, off, S);
     }
+}
+
+// covariance form of the log-likelihood terms: P^- = F P^f F^T + Lambda,
+// S = H P^- H^T + Omega = Y Y^T (Cholesky), ell = log N(y; H m^- + d, S)
+template <typename T, int NX, int NY>
+__global__ __launch_bounds__(128) void k_loglik_terms_cov(const int64_t *y_off, int B,
+                                                          int64_t T_y, int64_t T_x,
+                                                          GammaRef<T, NX, NY> gam, const T *y,
+                                                          MargRef<T, NX> filt, double *ell)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T_y)
+        return;
+    const int b = find_seq(y_off, B, t, 0);
+    T F[NX][NX], c[NX], SL[NX][NX], H[NY][NX], d[NY], SO[NY][NY];
+    gam.load_trans(t, F, c, SL);
+    gam.load_obs(t, H, d, SO);
+    Marg<T, NX> f;
+    filt.load(t + b, f);
+    T mp[NX], P[NX][NX], FP[NX][NX], Pp[NX][NX], Om[NY][NY];
+    mv(F, f.m, mp);
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+        mp[i] += c[i];
+    sym_full(P, [&](int i, int j) { return f.N[i][j]; });
+    mm(F, P, FP);
+    gram_full(SL, Pp);
+    gram_full(SO, Om);
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+#pragma unroll
+        for (int j = 0; j < NX; ++j) {
+            T s = Pp[i][j];
+#pragma unroll
+            for (int k = 0; k < NX; ++k)
+                s = pfma(FP[i][k], F[j][k], s);
+            Pp[i][j] = s;
+        }
+    T HP[NY][NX], S[NY][NY], Y[NY][NY];
+    mm(H, Pp, HP);
+#pragma unroll
+    for (int a = 0; a < NY; ++a)
+#pragma unroll
+        for (int q = 0; q < NY; ++q) {
+            T s = Om[a][q];
+#pragma unroll
+            for (int j = 0; j < NX; ++j)
+                s = pfma(HP[a][j], H[q][j], s);
+            S[a][q] = s;
+        }
+    chol_lower(S, Y);
+    T Hm[NY], v[NY], u[NY];
+    mv(H, mp, Hm);
+#pragma unroll
+    for (int a = 0; a < NY; ++a)
+        v[a] = y[a * T_y + t] - Hm[a] - d[a];
+    lsolve_lower(Y, v, u);
+    double l = -0.5 * NY * 1.8378770664093454835606594728112; // log(2 pi)
+#pragma unroll
+    for (int a = 0; a < NY; ++a)
+        l -= (double)plog(Y[a][a]) + 0.5 * (double)u[a] * (double)u[a];
+    ell[t] = l;
 }
 
 // Score terms at a frozen nominal (Fisher's identity on the linearised

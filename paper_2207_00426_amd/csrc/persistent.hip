@@ -177,6 +177,10 @@ int validate_groups(const pss_group *gs, int ng)
             set_error("batched: groups must be CT (nx 5, ny 2) or linear (nx 4, ny 2)");
             return PSS_EUNSUPPORTED;
         }
+        if (p->form != PSS_FORM_SQRT) {
+            set_error("batched: the persistent pass is defined for the square-root form only");
+            return PSS_EUNSUPPORTED;
+        }
         if (p->dtype != gs[0].p->dtype) {
             set_error("batched: all groups need the same dtype");
             return PSS_EINVAL;

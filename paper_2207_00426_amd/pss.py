@@ -27,6 +27,8 @@ PSS_F32, PSS_F64 = 0, 1
 MODEL_LINEAR, MODEL_CT = 0, 1
 LIN_CUBATURE, LIN_TAYLOR = 0, 1
 LINEARIZATIONS = {"cubature": LIN_CUBATURE, "taylor": LIN_TAYLOR}
+FORM_SQRT, FORM_COV = 0, 1
+FORMS = {"sqrt": FORM_SQRT, "cov": FORM_COV}
 OPS = dict(slr=0, filter_elements=1, filter_scan=2, smoother_scan=3, ipls=4, loglik=5,
            loglik_grad=6, sequential=7)
 STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported", -3: "workspace too small",
@@ -53,7 +55,7 @@ class Problem(ctypes.Structure):
                 ("dt", ctypes.c_double), ("theta", ctypes.c_double * 3),
                 ("sensors", ctypes.c_double * 4),
                 ("scan_threads", ctypes.c_int32), ("scan_elems", ctypes.c_int32),
-                ("linearization", ctypes.c_int32)]
+                ("linearization", ctypes.c_int32), ("form", ctypes.c_int32)]
 
 
 class GroupC(ctypes.Structure):
@@ -221,7 +223,7 @@ class Batch:
 
     def __init__(self, model, dtype, nx, ny, y_off, m0, N0, device="cuda", dt=0.0,
                  theta=(0.0, 0.0, 0.0), sensors=(0.0, 0.0, 0.0, 0.0), scan_threads=0,
-                 scan_elems=0, linearization="cubature"):
+                 scan_elems=0, linearization="cubature", form="sqrt"):
         self.model = model
         self.torch_dtype = dtype
         self.nx, self.ny = nx, ny
@@ -240,6 +242,7 @@ class Batch:
         self.scan_threads = int(scan_threads)
         self.scan_elems = int(scan_elems)
         self.linearization = LINEARIZATIONS[linearization]
+        self.form = FORMS[form]
 
     @classmethod
     def ct(cls, y_off, model, dtype=torch.float64, device="cuda", theta=None, **kw):
@@ -269,6 +272,7 @@ class Batch:
         p.scan_threads = self.scan_threads
         p.scan_elems = self.scan_elems
         p.linearization = getattr(self, "linearization", LIN_CUBATURE)
+        p.form = getattr(self, "form", FORM_SQRT)
         return p
 
     # buffers -------------------------------------------------------------
@@ -279,9 +283,14 @@ class Batch:
         return self.empty(self.nx, self.T_x), self.empty(tri(self.nx), self.T_x)
 
     def prior_nominal(self):
-        """Nominal trajectory with the prior at every state (the initial IPLS nominal)."""
+        """Nominal trajectory with the prior at every state (the initial IPLS
+        nominal); in the covariance form its second part holds P0 = N0 N0^T."""
         m = self.m0[:, None].repeat(1, self.T_x).contiguous()
-        N = self.N0[:, None].repeat(1, self.T_x).contiguous()
+        N0 = self.N0
+        if getattr(self, "form", FORM_SQRT) == FORM_COV:
+            L = unpack_lower(self.N0.double().cpu().numpy(), self.nx)
+            N0 = torch.tensor(pack_lower(L @ L.T), dtype=self.torch_dtype, device=self.device)
+        N = N0[:, None].repeat(1, self.T_x).contiguous()
         return m, N
 
     def new_gamma(self, stride=1):

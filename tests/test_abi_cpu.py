@@ -130,3 +130,22 @@ def test_kernel_timing_switch_without_launches(L):
     pss.kernel_timing(True)
     pss.kernel_timing(False)
     assert pss.kernel_times() == {}
+
+
+def test_form_and_linearization_fields_are_validated(L):
+    b = _cpu_batch()
+    b.form = 2
+    assert pss.validate(b) == -1
+    b = _cpu_batch()
+    b.linearization = 3
+    assert pss.validate(b) == -1
+    assert pss.validate(_cpu_batch(form="cov")) == 0
+    # the covariance form is refused by the square-root-only entry points
+    # before anything is dereferenced or enqueued
+    p = _cpu_batch(form="cov").struct()
+    fe = pss.FElemC()
+    for k in ("A", "b", "U", "eta", "Z"):
+        setattr(fe, k, 8)
+    rc = L.pss_sqrt_filter_scan(ctypes.byref(p), ctypes.byref(fe), ctypes.c_void_p(8),
+                                ctypes.c_void_p(8), ctypes.c_void_p(8), 1, None)
+    assert rc == -2 and "square-root" in pss.last_error()

@@ -1,0 +1,67 @@
+"""GPU parity of the standard (covariance-form) parallel filter and smoother
+(left columns of Tables 1-5), run through pss_ipls_iterate / pss_loglik with
+form = PSS_FORM_COV, against the FP64 oracle (whose sequential recursions
+give the same marginals in any form).  Covariances come back as packed
+lower triangles of P."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as orc
+from paper_2207_00426_amd import pss
+from paper_2207_00426_amd import workloads as wl
+from tests import parity as par
+from tests.test_gpu_parity import DIMS, _linear_case, _oracle_linear, _split_states
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _cov_from_soa(m, P, nx):
+    mm = pss.from_soa(m, (nx,))
+    L = pss.unpack_lower(pss.from_soa(P, (pss.tri(nx),)), nx)
+    full = L + np.swapaxes(L, -1, -2) - np.einsum("...ii->...i", L)[..., None] * np.eye(nx)
+    return mm, full
+
+
+def _errs(m, P, mr, Nr):
+    Pr = par.gram(Nr)
+    return par.mean_err(m, mr, Pr), par.cov_err(P, Pr)
+
+
+@pytest.mark.parametrize("nx,ny", DIMS)
+def test_cov_form_linear_multilevel(nx, ny):
+    lengths = np.array([700, 1, 130, 2])
+    G, m0, N0, y, y_off = _linear_case(nx, ny, lengths, 31 + nx)
+    b = pss.Batch(pss.MODEL_LINEAR, torch.float64, nx, ny, y_off, m0, N0, device=DEV,
+                  scan_threads=64, scan_elems=2, form="cov")
+    g = b.gamma_from_numpy(G)
+    yd = pss.to_soa(y, torch.float64, DEV)
+    m, N = b.prior_nominal()
+    pss.ipls_iterate(b, yd, 1, m, N, gamma=g)
+    ll = pss.loglik(b, yd, m, N, gamma=g)
+    torch.cuda.synchronize()
+    ma, Pa = _cov_from_soa(m, N, nx)
+    ref = _oracle_linear(G, m0, N0, y, y_off)
+    for s, (ms_, Ps_) in enumerate(zip(_split_states(ma, y_off), _split_states(Pa, y_off))):
+        em, eP = _errs(ms_, Ps_, ref[s]["ms"], ref[s]["Ns"])
+        assert em < par.TOL["f64"]["m"] and eP < par.TOL["f64"]["P"], (s, em, eP)
+        assert par.ll_err(float(ll[s]), ref[s]["ll"]) < par.TOL["f64"]["ll"]
+
+
+def test_cov_form_ct_every_pass():
+    w = wl.ct_single(1000, seed=1)
+    M = 10
+    ref = orc.ct_ipls(orc.ct_params(), w.model.m0, np.eye(5), w.y, M, history=True)
+    b = pss.Batch.ct(w.y_off, w.model, dtype=torch.float64, device=DEV, form="cov")
+    yd = pss.to_soa(w.y, torch.float64, DEV)
+    m, N = b.prior_nominal()  # (m0, P0) at every state
+    for i in range(M):
+        pss.ipls_iterate(b, yd, 1, m, N)
+        torch.cuda.synchronize()
+        ma, Pa = _cov_from_soa(m, N, 5)
+        em, eP = _errs(ma, Pa, ref["hist_ms"][i], ref["hist_Ns"][i])
+        assert em < par.TOL["f64"]["m"] and eP < par.TOL["f64"]["P"], (i, em, eP)
+    ll = pss.loglik(b, yd, m, N)
+    ll_ref = orc.ct_loglik(orc.ct_params(), w.model.m0, np.eye(5), w.y, ref["ms"], ref["Ns"])
+    assert par.ll_err(float(ll.item()), ll_ref) < par.TOL["f64"]["ll"]
