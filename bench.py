@@ -28,6 +28,9 @@ Also in the line (same run):
                   vector ALU; traffic = counter HBM bytes per launch from the
                   committed rocprofv3 summary, when it was taken on these
                   kernels
+  fp32_divergence share of FP32 runs whose log-likelihood is NaN, square-root
+                  vs standard covariance form (15 CT sequences per length,
+                  20 passes; FP64 as a control)
   cpu_baseline    the FP64 oracle on the host, on a bounded prefix of the
                   same sequence
 """
@@ -350,6 +353,43 @@ def bench_batched(stream, dev, M, B=512, seed=3):
             "status_ok": ok, "nan": nan}
 
 
+def bench_divergence(stream, dev, sets=15, passes=20, lengths=(100, 1000, 4000, 8000),
+                     settings=((0.05, 0.1), (5e-4, 0.1), (5e-4, 1e-3))):
+    """FP32 robustness of the two forms: for each (bearing noise sigma,
+    process noise q1 = q2) setting and length, `sets` CT sequences (one
+    batch), `passes` IPLS passes, then the log-likelihood; the share of
+    sequences whose log-likelihood is not finite, square-root vs covariance
+    form (FP64 as a control).  The first setting is the tracking model used
+    everywhere else; the others make the measurements far more informative
+    than the dynamics, which is where the covariance form loses positive
+    definiteness in FP32."""
+    out = {}
+    for sigma, q in settings:
+        md = wl.CTModel(q1=q, q2=q, sigma=sigma)
+        key = "sigma%g_q%g" % (sigma, q)
+        out[key] = {}
+        for n in lengths:
+            rng = np.random.Generator(np.random.PCG64(100 + n))
+            ys = [wl.simulate_ct(n, rng, md)[1] for _ in range(sets)]
+            off = np.arange(sets + 1, dtype=np.int64) * n
+            row = {}
+            for dt in ("f32", "f64"):
+                tdt = torch.float32 if dt == "f32" else torch.float64
+                yd = pss.to_soa(np.concatenate(ys), tdt, dev)
+                for form in ("sqrt", "cov"):
+                    b = pss.Batch.ct(off, md, dtype=tdt, device=dev, form=form)
+                    m, N = b.prior_nominal()
+                    pss.ipls_iterate(b, yd, passes, m, N)
+                    ll = pss.loglik(b, yd, m, N)
+                    torch.cuda.synchronize()
+                    bad = int((~torch.isfinite(ll)).sum().item())
+                    row["%s_%s" % (form, dt)] = round(bad / sets, 4)
+            out[key]["n%d" % n] = row
+            log("divergence %s n=%d: FP32 non-finite share sqrt %.2f, cov %.2f" % (
+                key, n, row["sqrt_f32"], row["cov_f32"]))
+    return {"sets": sets, "passes": passes, "nonfinite_share": out}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -536,6 +576,7 @@ def main():
 
         if not args.no_extras:
             extras["batched_ragged_512"] = bench_batched(stream, dev, M)
+            extras["fp32_divergence"] = bench_divergence(stream, dev)
 
     cpu = None
     if not args.no_cpu_baseline:

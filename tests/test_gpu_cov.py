@@ -65,3 +65,27 @@ def test_cov_form_ct_every_pass():
     ll = pss.loglik(b, yd, m, N)
     ll_ref = orc.ct_loglik(orc.ct_params(), w.model.m0, np.eye(5), w.y, ref["ms"], ref["Ns"])
     assert par.ll_err(float(ll.item()), ll_ref) < par.TOL["f64"]["ll"]
+
+
+def test_fp32_square_root_form_does_not_diverge_where_covariance_form_does():
+    # informative bearings (sigma 5e-4) and slow dynamics (q 1e-3): the
+    # setting of the robustness comparison where the covariance form loses
+    # positive definiteness in FP32
+    md = wl.CTModel(q1=1e-3, q2=1e-3, sigma=5e-4)
+    sets, n = 15, 4000
+    rng = np.random.Generator(np.random.PCG64(7))
+    ys = [wl.simulate_ct(n, rng, md)[1] for _ in range(sets)]
+    off = np.arange(sets + 1, dtype=np.int64) * n
+    bad = {}
+    for form in ("sqrt", "cov"):
+        b = pss.Batch.ct(off, md, dtype=torch.float32, device=DEV, form=form)
+        yd = pss.to_soa(np.concatenate(ys), torch.float32, DEV)
+        m, N = b.prior_nominal()
+        pss.ipls_iterate(b, yd, 20, m, N)
+        ll = pss.loglik(b, yd, m, N)
+        torch.cuda.synchronize()
+        bad[form] = int((~torch.isfinite(ll)).sum().item())
+    print("FP32 non-finite log-likelihoods of 15: square root %d, covariance %d"
+          % (bad["sqrt"], bad["cov"]))
+    assert bad["sqrt"] == 0
+    assert bad["cov"] > 0
