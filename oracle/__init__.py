@@ -5,6 +5,12 @@ Yaghoobi, Corenflos, Hassan and Sarkka.  Only the tests, the smoke check and
 the CPU-baseline leg of the benchmark may import this package; the HIP library
 never does, and the two share no code.
 
+Models: the coordinated-turn bearings model (Section 6.2), the Ricker
+population model with Poisson counts (Section 6.1) and linear-Gaussian
+models; linearisations: first-order Taylor (Section 4.2) and the
+sigma-point GSLR of Section 4.3 with the cubature, unscented or
+Gauss-Hermite rule.
+
 Layout: numpy arrays, one row-major block per step/state, e.g. ``Nf`` has
 shape ``(n+1, nx, nx)`` and the linearisation parameters of step slot ``j``
 (transition x_j -> x_{j+1}, measurement of y_{j+1}) are ``F[j], c[j], SL[j],
@@ -44,6 +50,9 @@ def _load():
         _lib.or_ct_loglik.restype = ctypes.c_double
         _lib.or_ct_score.restype = ctypes.c_double
         _lib.or_lgssm_score_terms.restype = ctypes.c_double
+        _lib.or_ricker_loglik.restype = ctypes.c_double
+        _lib.or_ricker_f.restype = ctypes.c_double
+        _lib.or_ricker_f.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_double]
     return _lib
 
 
@@ -168,12 +177,116 @@ def ct_Q(prm):
 
 
 METHODS = {"cubature": 0, "cubature_literal": 1, "taylor": 2}
+RULE_METHODS = ("cubature_rule", "unscented", "gauss_hermite")
+_RULE = 3
 
 
-def ct_linearize(prm, ms, Ns, y, literal=False, method=None):
+# --------------------------------------------------------------------------
+# sigma-point rules (Section 4.3): unit points xi [np, nx] and positive
+# weights w [np] (sum 1) integrating the moments of N(0, I) up to order 2
+# --------------------------------------------------------------------------
+def rule_cubature(nx):
+    """Third-degree spherical-radial rule: +-sqrt(nx) e_i, weights 1/(2 nx)."""
+    xi = np.concatenate([np.sqrt(nx) * np.eye(nx), -np.sqrt(nx) * np.eye(nx)])
+    return xi, np.full(2 * nx, 1.0 / (2 * nx))
+
+
+def default_kappa(nx):
+    """Unscented spread kappa used when none is given: Julier's n + kappa = 3
+    where that keeps the centre weight positive, else 1."""
+    return float(max(3 - nx, 1))
+
+
+def rule_unscented(nx, kappa=None):
+    """Unscented transform with alpha = 1, beta = 0 (mean and covariance
+    weights equal, all positive for kappa >= 0): the centre with weight
+    kappa / (nx + kappa) and +-sqrt(nx + kappa) e_i with 1 / (2 (nx + kappa)).
+    A zero centre weight drops the centre point."""
+    k = default_kappa(nx) if kappa is None else float(kappa)
+    if not k >= 0:
+        raise ValueError("kappa must be >= 0 for positive weights")
+    s = np.sqrt(nx + k)
+    pts = [s * np.eye(nx), -s * np.eye(nx)]
+    ws = [np.full(2 * nx, 1.0 / (2 * (nx + k)))]
+    if k > 0:
+        pts.insert(0, np.zeros((1, nx)))
+        ws.insert(0, np.array([k / (nx + k)]))
+    return np.concatenate(pts), np.concatenate(ws)
+
+
+def rule_gauss_hermite(nx, order=3):
+    """Tensor product of the order-point Gauss-Hermite rule for N(0, 1)
+    (numpy's hermegauss: nodes of He_order, weights normalised to sum 1);
+    point index i = sum_j digit_j order^j, digit_0 the first coordinate."""
+    x1, w1 = np.polynomial.hermite_e.hermegauss(int(order))
+    w1 = w1 / w1.sum()
+    np_ = int(order) ** nx
+    xi = np.zeros((np_, nx))
+    w = np.ones(np_)
+    for i in range(np_):
+        r = i
+        for j in range(nx):
+            dgt = r % order
+            r //= order
+            xi[i, j] = x1[dgt]
+            w[i] *= w1[dgt]
+    return xi, w
+
+
+def make_rule(method, nx, kappa=None, gh_order=None):
+    if method == "cubature_rule" or method == "cubature":
+        return rule_cubature(nx)
+    if method == "unscented":
+        return rule_unscented(nx, kappa)
+    if method == "gauss_hermite":
+        return rule_gauss_hermite(nx, 3 if gh_order is None else gh_order)
+    raise ValueError(method)
+
+
+def set_rule(xi, w):
+    xi = _f64(xi)
+    w = _f64(w)
+    if _load().or_set_rule(I(xi.shape[1]), I(xi.shape[0]), _p(xi), _p(w)) != 0:
+        raise ValueError("rule too large")
+
+
+def _code(method, nx, kappa=None, gh_order=None, rule_for_cubature=False):
+    """Method code for the C linearisations; installs the rule if needed."""
+    if method in RULE_METHODS or (rule_for_cubature and method == "cubature"):
+        set_rule(*make_rule(method, nx, kappa, gh_order))
+        return _RULE
+    return METHODS[method]
+
+
+def slr_rule(xi, w, m, N, g, Snoise=None, Sg=None, literal=False):
+    """GSLR of a conditional model with mean g(x) (x [nx] -> [nz]) and
+    covariance factor Snoise (additive) or Sg(x) (per point) at N(m, N N^T)
+    with the rule (xi, w).  Returns (G, offset, S) (and the downdate
+    breakdown count when literal)."""
+    m = _f64(m); N = _f64(N); xi = _f64(xi); w = _f64(w)
+    nx = m.shape[0]
+    X = m[None, :] + xi @ N.T
+    Z = _f64(np.stack([np.atleast_1d(g(x)) for x in X]))
+    nz = Z.shape[1]
+    np_ = X.shape[0]
+    SgA = None
+    if Sg is not None:
+        SgA = _f64(np.stack([np.atleast_2d(Sg(x)) for x in X]))
+    Sn = None if Snoise is None else _f64(np.atleast_2d(Snoise))
+    G = np.zeros((nz, nx)); off = np.zeros(nz); S = np.zeros((nz, nz))
+    bad = _load().or_slr_rule(I(nx), I(nz), I(np_), _p(_f64(X)), _p(w), _p(m), _p(N), _p(Z),
+                              _p(SgA) if SgA is not None else None,
+                              _p(Sn) if Sn is not None else None, I(1 if literal else 0),
+                              _p(G), _p(off), _p(S))
+    return (G, off, S, int(bad)) if literal else (G, off, S)
+
+
+def ct_linearize(prm, ms, Ns, y, literal=False, method=None, kappa=None, gh_order=None):
     """Per-step linearisation of the CT model at the nominal (ms, Ns):
     method "cubature" (residual SLR, Section 4.3), "cubature_literal" (the
-    printed Tria + DownDate form) or "taylor" (first-order, Section 4.2)."""
+    printed Tria + DownDate form), "taylor" (first-order, Section 4.2), or a
+    general positive-weight rule: "cubature_rule", "unscented" (kappa),
+    "gauss_hermite" (gh_order points per coordinate)."""
     if method is None:
         method = "cubature_literal" if literal else "cubature"
     prm = _f64(prm)
@@ -183,12 +296,14 @@ def ct_linearize(prm, ms, Ns, y, literal=False, method=None):
     n = y.shape[0]
     F = np.zeros((n, 5, 5)); c = np.zeros((n, 5)); SL = np.zeros((n, 5, 5))
     H = np.zeros((n, 2, 5)); d = np.zeros((n, 2)); SO = np.zeros((n, 2, 2))
-    bad = _load().or_ct_linearize(I(n), _p(prm), _p(ms), _p(Ns), _p(y), I(METHODS[method]), _p(F),
+    code = _code(method, 5, kappa, gh_order)
+    bad = _load().or_ct_linearize(I(n), _p(prm), _p(ms), _p(Ns), _p(y), I(code), _p(F),
                                   _p(c), _p(SL), _p(H), _p(d), _p(SO))
     return dict(F=F, c=c, SL=SL, H=H, d=d, SO=SO, bad=int(bad))
 
 
-def ct_ipls(prm, m0, N0, y, M, ms_init=None, Ns_init=None, history=False, method="cubature"):
+def ct_ipls(prm, m0, N0, y, M, ms_init=None, Ns_init=None, history=False, method="cubature",
+            kappa=None, gh_order=None):
     """Algorithm 3 (sequential reference).  Initial nominal: the prior at every k.
     method "taylor": the iterated extended smoother (Section 4.2)."""
     prm = _f64(prm); m0 = _f64(m0); N0 = _f64(N0); y = _f64(y)
@@ -198,9 +313,10 @@ def ct_ipls(prm, m0, N0, y, M, ms_init=None, Ns_init=None, history=False, method
     hm = np.zeros((M, n + 1, 5)) if history else None
     hN = np.zeros((M, n + 1, 5, 5)) if history else None
     mf = np.zeros((n + 1, 5)); Nf = np.zeros((n + 1, 5, 5))
+    code = _code(method, 5, kappa, gh_order)
     rc = _load().or_ct_ipls(I(n), _p(prm), _p(m0), _p(N0), _p(y), I(M), _p(ms), _p(Ns),
                             _p(hm) if history else None, _p(hN) if history else None,
-                            _p(mf), _p(Nf), I(METHODS[method]))
+                            _p(mf), _p(Nf), I(code))
     if rc != 0:
         raise RuntimeError("oracle IPLS failed")
     out = dict(ms=ms, Ns=Ns, mf=mf, Nf=Nf)
@@ -210,22 +326,25 @@ def ct_ipls(prm, m0, N0, y, M, ms_init=None, Ns_init=None, history=False, method
     return out
 
 
-def ct_loglik(prm, m0, N0, y, ms, Ns, per_step=False, method="cubature"):
+def ct_loglik(prm, m0, N0, y, ms, Ns, per_step=False, method="cubature", kappa=None,
+              gh_order=None):
     prm = _f64(prm); m0 = _f64(m0); N0 = _f64(N0); y = _f64(y); ms = _f64(ms); Ns = _f64(Ns)
     n = y.shape[0]
     ell = np.zeros(n)
+    code = _code(method, 5, kappa, gh_order)
     tot = _load().or_ct_loglik(I(n), _p(prm), _p(m0), _p(N0), _p(y), _p(ms), _p(Ns), _p(ell),
-                               I(METHODS[method]))
+                               I(code))
     return (tot, ell) if per_step else tot
 
 
-def ct_score(prm, m0, N0, y, ms, Ns, method="cubature"):
+def ct_score(prm, m0, N0, y, ms, Ns, method="cubature", kappa=None, gh_order=None):
     """(loglik, d loglik / d (log q1, log q2, log sigma)) at a frozen nominal."""
     prm = _f64(prm); m0 = _f64(m0); N0 = _f64(N0); y = _f64(y); ms = _f64(ms); Ns = _f64(Ns)
     n = y.shape[0]
     g = np.zeros(3)
+    code = _code(method, 5, kappa, gh_order)
     tot = _load().or_ct_score(I(n), _p(prm), _p(m0), _p(N0), _p(y), _p(ms), _p(Ns), _p(g),
-                              I(METHODS[method]))
+                              I(code))
     return tot, g
 
 
@@ -248,6 +367,69 @@ def ct_theta_params(theta, base=None):
     prm[2] = np.exp(theta[1])
     prm[3] = np.exp(theta[2])
     return prm
+
+
+# --------------------------------------------------------------------------
+# Ricker population model with Poisson counts (Section 6.1); nx = ny = 1
+# --------------------------------------------------------------------------
+def ricker_params(a=44.7, b=10.0, Q=0.3 ** 2):
+    return np.array([a, b, Q], dtype=np.float64)
+
+
+def ricker_f(prm, x):
+    return float(_load().or_ricker_f(_p(_f64(prm)), ctypes.c_double(float(x))))
+
+
+def ricker_linearize(prm, ms, Ns, y, method="cubature", kappa=None, gh_order=None):
+    """Per-step GSLR of the Ricker model at the nominal (ms [n+1], Ns [n+1]
+    scalar factors): "taylor" (Section 4.2) or a rule ("cubature",
+    "unscented", "gauss_hermite"; Section 4.3).  Arrays of shape [n]."""
+    prm = _f64(prm); ms = _f64(np.ravel(ms)); Ns = _f64(np.ravel(Ns)); y = _f64(np.ravel(y))
+    n = y.shape[0]
+    out = {k: np.zeros(n) for k in ("F", "c", "SL", "H", "d", "SO")}
+    code = _code(method, 1, kappa, gh_order, rule_for_cubature=True)
+    rc = _load().or_ricker_linearize(I(n), _p(prm), _p(ms), _p(Ns), _p(y), I(code),
+                                     *[_p(out[k]) for k in ("F", "c", "SL", "H", "d", "SO")])
+    if rc != 0:
+        raise RuntimeError("oracle Ricker linearisation failed")
+    return out
+
+
+def ricker_ipls(prm, m0, N0, y, M, ms_init=None, Ns_init=None, history=False,
+                method="cubature", kappa=None, gh_order=None):
+    """Algorithm 3 on the Ricker model (sequential reference); initial
+    nominal: the prior (m0, N0) at every state.  Arrays of shape [n+1]."""
+    prm = _f64(prm); y = _f64(np.ravel(y))
+    n = y.shape[0]
+    m0a = _f64(np.ravel(m0)); N0a = _f64(np.ravel(N0))
+    ms = np.full(n + 1, m0a[0]) if ms_init is None else _f64(np.ravel(ms_init)).copy()
+    Ns = np.full(n + 1, N0a[0]) if Ns_init is None else _f64(np.ravel(Ns_init)).copy()
+    hm = np.zeros((M, n + 1)) if history else None
+    hN = np.zeros((M, n + 1)) if history else None
+    mf = np.zeros(n + 1); Nf = np.zeros(n + 1)
+    code = _code(method, 1, kappa, gh_order, rule_for_cubature=True)
+    rc = _load().or_ricker_ipls(I(n), _p(prm), _p(m0a), _p(N0a), _p(y), I(M), _p(ms), _p(Ns),
+                                _p(hm) if history else None, _p(hN) if history else None,
+                                _p(mf), _p(Nf), I(code))
+    if rc != 0:
+        raise RuntimeError("oracle Ricker IPLS failed")
+    out = dict(ms=ms, Ns=Ns, mf=mf, Nf=Nf)
+    if history:
+        out["hist_ms"] = hm
+        out["hist_Ns"] = hN
+    return out
+
+
+def ricker_loglik(prm, m0, N0, y, ms, Ns, per_step=False, method="cubature", kappa=None,
+                  gh_order=None):
+    prm = _f64(prm); y = _f64(np.ravel(y)); ms = _f64(np.ravel(ms)); Ns = _f64(np.ravel(Ns))
+    m0a = _f64(np.ravel(m0)); N0a = _f64(np.ravel(N0))
+    n = y.shape[0]
+    ell = np.zeros(n)
+    code = _code(method, 1, kappa, gh_order, rule_for_cubature=True)
+    tot = _load().or_ricker_loglik(I(n), _p(prm), _p(m0a), _p(N0a), _p(y), _p(ms), _p(Ns),
+                                   _p(ell), I(code))
+    return (tot, ell) if per_step else tot
 
 
 # --------------------------------------------------------------------------

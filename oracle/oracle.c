@@ -27,8 +27,16 @@
  *   - the first-order Taylor linearisation (iterated extended smoother) is
  *     pinned by finite differences of the model functions and by the
  *     cubature SLR's small-covariance limit;
+ *   - the general sigma-point rules (cubature, unscented, Gauss-Hermite) and
+ *     the generalised SLR with state-dependent conditional covariance are
+ *     pinned by moment exactness, the textbook special cases of the
+ *     unscented rule, exactness on affine maps, the printed DownDate form,
+ *     and, on the Ricker-Poisson model, by the closed-form lognormal moments
+ *     (high-order Gauss-Hermite), finite differences (Taylor) and the
+ *     small-spread limit;
  *   - the CT iterated smoother's output values have no printed reference in
- *     the paper: beyond the invariants tested, parity unpinned.
+ *     the paper: beyond the invariants tested, parity unpinned; the same
+ *     holds for the Ricker iterated smoother's outputs.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -450,6 +458,143 @@ int or_slr_literal(int nx, int nz, const double *m, const double *N, const doubl
 /* as a recursion; Algorithm 1 computes the same marginals by a scan).      */
 /* ell[j] = log N(y_{j+1}; predicted mean, predicted covariance): the full  */
 /* Gaussian log density including the -(ny/2) log(2 pi) constant.           */
+/* ------------------------------------------------------------------------ */
+/* Sigma-point rules with positive weights (Section 4.3).  A rule is a set  */
+/* of unit points xi_i (nx each) with weights w_i > 0 summing to one that    */
+/* integrates the first and second moments of N(0, I) exactly; for the      */
+/* Gaussian N(m, N N^T) its points are X_i = m + N xi_i.  The cubature,      */
+/* unscented and Gauss-Hermite rules are built by the Python wrapper and     */
+/* installed here with or_set_rule; linearisation method OR_RULE reads it.  */
+/* (The rule table is process-global: one rule at a time.)                  */
+/* ------------------------------------------------------------------------ */
+#define OR_RULE 3
+#define OR_MAXPTS 4096
+static int g_rule_nx = 0, g_rule_np = 0;
+static double g_rule_xi[OR_MAXPTS * 8], g_rule_w[OR_MAXPTS];
+
+int or_set_rule(int nx, int np, const double *xi, const double *w)
+{
+    if (nx < 1 || nx > 8 || np < 1 || np > OR_MAXPTS)
+        return -1;
+    g_rule_nx = nx;
+    g_rule_np = np;
+    memcpy(g_rule_xi, xi, sizeof(double) * (size_t)(np * nx));
+    memcpy(g_rule_w, w, sizeof(double) * (size_t)np);
+    return 0;
+}
+
+/* X_i = m + N xi_i for the installed rule ([np][nx]) */
+static void rule_points(int nx, const double *m, const double *N, double *X)
+{
+    for (int i = 0; i < g_rule_np; ++i)
+        for (int a = 0; a < nx; ++a) {
+            double s = m[a];
+            for (int b = 0; b <= a; ++b)
+                s += N[a * nx + b] * g_rule_xi[i * nx + b];
+            X[i * nx + a] = s;
+        }
+}
+
+/* L <- Tria([L, B]) for an nz x nz lower L and an nz x m block B, taking   */
+/* the columns of B a few at a time (Tria([A, B]) = Tria([Tria(A), B])).    */
+static void tria_accumulate(int nz, double *L, int m, const double *B)
+{
+    enum { CH = 16 };
+    double A[OR_MAXD * (OR_MAXD + CH)];
+    for (int c0 = 0; c0 < m; c0 += CH) {
+        int mc = m - c0 < CH ? m - c0 : CH;
+        int w = nz + mc;
+        for (int a = 0; a < nz; ++a) {
+            for (int b = 0; b < nz; ++b)
+                A[a * w + b] = L[a * nz + b];
+            for (int q = 0; q < mc; ++q)
+                A[a * w + nz + q] = B[(long)a * m + c0 + q];
+        }
+        or_tria(nz, w, A, L);
+    }
+}
+
+/* Generalised statistical linear regression (the GSLR moments of Section   */
+/* 2.3 with the sigma-point approximations of Section 4.3) of a conditional */
+/* model with mean g(x) and lower covariance factor Sg(x), at N(m, N N^T):  */
+/*   Z_i = g(X_i),  zbar = sum_i w_i Z_i,                                   */
+/*   G   = [sum_i w_i (Z_i - zbar)(X_i - m)^T] (N N^T)^{-1},                */
+/*   off = zbar - G m,                                                      */
+/*   S S^T = sum_i w_i Sg(X_i) Sg(X_i)^T + Zx Zx^T - G N N^T G^T,            */
+/*   Zx = [sqrt(w_i)(Z_i - zbar)]_i.                                        */
+/* The first sum is E[V[y|x]]; with additive noise it is Snoise Snoise^T    */
+/* (pass Snoise, Sg = NULL), else pass the per-point factors Sg [np][nz][nz].*/
+/* literal = 0: S = Tria([noise columns, sqrt(w_i)(Z_i - zbar - G(X_i - m))]),*/
+/*   whose residual columns have Gram matrix Zx Zx^T - G N N^T G^T exactly   */
+/*   because the rule integrates second moments exactly;                    */
+/* literal = 1: the printed S = DownDate(Tria([noise columns, Zx]), G N).    */
+/* Returns the downdate breakdown count (0 for literal = 0).                */
+int or_slr_rule(int nx, int nz, int np, const double *X, const double *w, const double *m,
+                const double *N, const double *Z, const double *Sg, const double *Snoise,
+                int literal, double *G, double *off, double *S)
+{
+    double zbar[OR_MAXD], C[OR_MAXD * OR_MAXD], T1[OR_MAXD * OR_MAXD], Gm[OR_MAXD];
+    for (int a = 0; a < nz; ++a) {
+        double s = 0.0;
+        for (int i = 0; i < np; ++i)
+            s += w[i] * Z[i * nz + a];
+        zbar[a] = s;
+    }
+    for (int a = 0; a < nz; ++a)
+        for (int b = 0; b < nx; ++b) {
+            double s = 0.0;
+            for (int i = 0; i < np; ++i)
+                s += w[i] * (Z[i * nz + a] - zbar[a]) * (X[i * nx + b] - m[b]);
+            C[a * nx + b] = s;
+        }
+    /* (N N^T)^{-1} = N^{-T} N^{-1} */
+    right_solve_lower_t(nz, nx, C, N, T1);
+    right_solve_lower(nz, nx, T1, N, G);
+    mat_vec(nz, nx, G, m, Gm);
+    for (int a = 0; a < nz; ++a)
+        off[a] = zbar[a] - Gm[a];
+    /* noise part */
+    double L[OR_MAXD * OR_MAXD];
+    for (int q = 0; q < nz * nz; ++q)
+        L[q] = 0.0;
+    if (Snoise) {
+        for (int a = 0; a < nz; ++a)
+            for (int b = 0; b < nz; ++b)
+                L[a * nz + b] = (b <= a) ? Snoise[a * nz + b] : 0.0;
+    } else {
+        int mc = np * nz;
+        double *B = malloc(sizeof(double) * (size_t)nz * (size_t)mc);
+        for (int i = 0; i < np; ++i) {
+            double sw = sqrt(w[i]);
+            for (int a = 0; a < nz; ++a)
+                for (int b = 0; b < nz; ++b)
+                    B[(long)a * mc + i * nz + b] = sw * Sg[(long)i * nz * nz + a * nz + b];
+        }
+        tria_accumulate(nz, L, mc, B);
+        free(B);
+    }
+    double *R = malloc(sizeof(double) * (size_t)nz * (size_t)np);
+    for (int i = 0; i < np; ++i) {
+        double sw = sqrt(w[i]), dx[OR_MAXD], gd[OR_MAXD];
+        for (int b = 0; b < nx; ++b)
+            dx[b] = X[i * nx + b] - m[b];
+        mat_vec(nz, nx, G, dx, gd);
+        for (int a = 0; a < nz; ++a)
+            R[(long)a * np + i] = sw * (Z[i * nz + a] - zbar[a] - (literal ? 0.0 : gd[a]));
+    }
+    tria_accumulate(nz, L, np, R);
+    free(R);
+    int bad = 0;
+    if (literal) {
+        double GN[OR_MAXD * OR_MAXD];
+        mat_mul(nz, nx, nx, G, N, GN);
+        bad = or_downdate(nz, nx, L, GN, S);
+    } else {
+        memcpy(S, L, sizeof(double) * (size_t)(nz * nz));
+    }
+    return bad;
+}
+
 /* ------------------------------------------------------------------------ */
 int or_sqrt_filter(int n, int nx, int ny, const double *m0, const double *N0, const double *F,
                    const double *c, const double *SL, const double *H, const double *d,
@@ -1155,6 +1300,30 @@ int or_ct_linearize(int n, const double *prm, const double *ms, const double *Ns
         }
         return 0;
     }
+    if (literal == OR_RULE) { /* the installed sigma-point rule */
+        if (g_rule_nx != nx)
+            return -1;
+        const int np = g_rule_np;
+        double *X = malloc(sizeof(double) * (size_t)np * nx);
+        double *Z = malloc(sizeof(double) * (size_t)np * nx);
+        for (int j = 0; j < n; ++j) {
+            const double *m = ms + (long)j * nx, *N = Ns + (long)j * nx * nx;
+            rule_points(nx, m, N, X);
+            for (int i = 0; i < np; ++i)
+                or_ct_f(prm, X + (long)i * nx, Z + (long)i * nx);
+            or_slr_rule(nx, nx, np, X, g_rule_w, m, N, Z, NULL, LQ, 0, F + (long)j * 25,
+                        c + (long)j * 5, SL + (long)j * 25);
+            const double *m1 = ms + (long)(j + 1) * nx, *N1 = Ns + (long)(j + 1) * nx * nx;
+            rule_points(nx, m1, N1, X);
+            for (int i = 0; i < np; ++i)
+                or_ct_h(prm, X + (long)i * nx, y + (long)j * ny, Z + (long)i * ny);
+            or_slr_rule(nx, ny, np, X, g_rule_w, m1, N1, Z, NULL, SOn, 0, H + (long)j * 10,
+                        d + (long)j * 2, SO + (long)j * 4);
+        }
+        free(X);
+        free(Z);
+        return 0;
+    }
     for (int j = 0; j < n; ++j) {
         double Xp[25], Xm[25], Zp[25], Zm[25], Yp[10], Ym[10];
         const double *m = ms + (long)j * nx, *N = Ns + (long)j * nx * nx;
@@ -1385,6 +1554,121 @@ double or_ct_score(int n, const double *prm, const double *m0, const double *N0,
         grad3[2] = g3;
     }
     free(F); free(c); free(SL); free(H); free(d); free(SO); free(Lam); free(Om); free(Lbar); free(Obar);
+    return total;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Ricker population model with Poisson counts (Section 6.1):               */
+/*   x_k = log a + x_{k-1} - exp(x_{k-1}) + q_k,   q_k ~ N(0, Q),           */
+/*   y_k | x_k ~ Poisson(b exp(x_k)),  so E[y|x] = V[y|x] = b exp(x).       */
+/* prm layout: a, b, Q.  The measurement noise is not additive: its         */
+/* conditional variance enters Omega through the E[V[y|x]] term of the GSLR */
+/* moments (Section 2.3).                                                    */
+/* method 2: first-order Taylor (Section 4.2): F = 1 - exp(m),              */
+/*   c = f(m) - F m, S_Lambda = sqrt(Q); H = b exp(m), d = b exp(m) - H m,  */
+/*   S_Omega = sqrt(V[y|x](m)) = sqrt(b exp(m));                            */
+/* method OR_RULE: the installed sigma-point rule (Section 4.3).            */
+/* ------------------------------------------------------------------------ */
+double or_ricker_f(const double *prm, double x) { return log(prm[0]) + x - exp(x); }
+
+int or_ricker_linearize(int n, const double *prm, const double *ms, const double *Ns,
+                        const double *y, int method, double *F, double *c, double *SL, double *H,
+                        double *d, double *SO)
+{
+    (void)y;
+    const double b = prm[1], sq = sqrt(prm[2]);
+    if (method == 2) {
+        for (int j = 0; j < n; ++j) {
+            const double m = ms[j], m1 = ms[j + 1];
+            F[j] = 1.0 - exp(m);
+            c[j] = or_ricker_f(prm, m) - F[j] * m;
+            SL[j] = sq;
+            H[j] = b * exp(m1);
+            d[j] = b * exp(m1) - H[j] * m1;
+            SO[j] = sqrt(b * exp(m1));
+        }
+        return 0;
+    }
+    if (method != OR_RULE || g_rule_nx != 1)
+        return -1;
+    const int np = g_rule_np;
+    double *X = malloc(sizeof(double) * (size_t)np), *Z = malloc(sizeof(double) * (size_t)np);
+    double *Sg = malloc(sizeof(double) * (size_t)np);
+    for (int j = 0; j < n; ++j) {
+        rule_points(1, ms + j, Ns + j, X);
+        for (int i = 0; i < np; ++i)
+            Z[i] = or_ricker_f(prm, X[i]);
+        or_slr_rule(1, 1, np, X, g_rule_w, ms + j, Ns + j, Z, NULL, &sq, 0, F + j, c + j, SL + j);
+        rule_points(1, ms + j + 1, Ns + j + 1, X);
+        for (int i = 0; i < np; ++i) {
+            Z[i] = b * exp(X[i]);
+            Sg[i] = sqrt(Z[i]);
+        }
+        or_slr_rule(1, 1, np, X, g_rule_w, ms + j + 1, Ns + j + 1, Z, Sg, NULL, 0, H + j, d + j,
+                    SO + j);
+    }
+    free(X);
+    free(Z);
+    free(Sg);
+    return 0;
+}
+
+/* Algorithm 3 for the Ricker model (sequential square-root filter and     */
+/* smoother on each pass's linearisation); arguments as or_ct_ipls.        */
+int or_ricker_ipls(int n, const double *prm, const double *m0, const double *N0,
+                   const double *y, int M, double *ms, double *Ns, double *hist_ms,
+                   double *hist_Ns, double *last_mf, double *last_Nf, int method)
+{
+    size_t nst = (size_t)(n + 1);
+    double *G = malloc(sizeof(double) * (size_t)n * 6), *mf = malloc(sizeof(double) * nst);
+    double *Nf = malloc(sizeof(double) * nst);
+    double *F = G, *c = G + n, *SL = G + 2 * n, *H = G + 3 * n, *d = G + 4 * n, *SO = G + 5 * n;
+    int rc = 0;
+    for (int it = 0; it < M && rc == 0; ++it) {
+        if (or_ricker_linearize(n, prm, ms, Ns, y, method, F, c, SL, H, d, SO) != 0) {
+            rc = -1;
+            break;
+        }
+        or_sqrt_filter(n, 1, 1, m0, N0, F, c, SL, H, d, SO, 1, y, mf, Nf, NULL);
+        or_sqrt_smoother(n, 1, F, c, SL, 1, mf, Nf, ms, Ns, NULL);
+        if (hist_ms)
+            memcpy(hist_ms + (size_t)it * nst, ms, sizeof(double) * nst);
+        if (hist_Ns)
+            memcpy(hist_Ns + (size_t)it * nst, Ns, sizeof(double) * nst);
+    }
+    if (last_mf)
+        memcpy(last_mf, mf, sizeof(double) * nst);
+    if (last_Nf)
+        memcpy(last_Nf, Nf, sizeof(double) * nst);
+    free(G);
+    free(mf);
+    free(Nf);
+    return rc;
+}
+
+/* Pseudo-log-likelihood (Section 5.1) of the Ricker model linearised at    */
+/* the given nominal; ell (optional, [n]) receives the per-step terms.      */
+double or_ricker_loglik(int n, const double *prm, const double *m0, const double *N0,
+                        const double *y, const double *ms, const double *Ns, double *ell,
+                        int method)
+{
+    size_t nst = (size_t)(n + 1);
+    double *G = malloc(sizeof(double) * (size_t)n * 6), *mf = malloc(sizeof(double) * nst);
+    double *Nf = malloc(sizeof(double) * nst), *l = malloc(sizeof(double) * (size_t)n);
+    double *F = G, *c = G + n, *SL = G + 2 * n, *H = G + 3 * n, *d = G + 4 * n, *SO = G + 5 * n;
+    double total = NAN;
+    if (or_ricker_linearize(n, prm, ms, Ns, y, method, F, c, SL, H, d, SO) == 0) {
+        or_sqrt_filter(n, 1, 1, m0, N0, F, c, SL, H, d, SO, 1, y, mf, Nf, l);
+        total = 0.0;
+        for (int j = 0; j < n; ++j)
+            total += l[j];
+        if (ell)
+            memcpy(ell, l, sizeof(double) * (size_t)n);
+    }
+    free(G);
+    free(mf);
+    free(Nf);
+    free(l);
     return total;
 }
 

@@ -11,12 +11,16 @@ Models
           nx = 5, ny = 2.
   * CV  - linear constant-velocity target with noisy position fixes,
           x = (px, py, vx, vy), nx = 4, ny = 2.
+  * RP  - stochastic Ricker population model with Poisson counts (the
+          paper's Section 6.1 experiment), nx = ny = 1.
 
-Simulation protocol (both models): ``rng = numpy.random.Generator(PCG64(seed))``;
+Simulation protocol (CT and CV): ``rng = numpy.random.Generator(PCG64(seed))``;
 x_0 = m0 + chol(P0) e_0; then a single (n, nx + ny) block of standard normals
 whose row k-1 holds the process noise of step k followed by its measurement
 noise; x_k = f(x_{k-1}) + chol(Q) e, y_k = h(x_k) + noise (bearings wrapped to
-[-pi, pi)).
+[-pi, pi)).  RP: x_0 = log c exactly (the paper's point-mass prior), then
+per step one standard normal for the process noise and one Poisson draw,
+x_k = log a + x_{k-1} - exp(x_{k-1}) + sqrt(Q) e_k, y_k ~ Poisson(b exp(x_k)).
 """
 from __future__ import annotations
 
@@ -98,6 +102,32 @@ class CVModel:
         return self.r ** 2 * np.eye(2)
 
 
+@dataclass
+class RickerModel:
+    """Ricker map with Poisson counts; parameters of the paper's Section 6.1.
+    The filter prior is N(log c, s0^2): the paper's point mass at log c
+    widened by s0 so that a sigma-point rule can regress around it."""
+    a: float = 44.7
+    b: float = 10.0
+    c: float = 7.0
+    Q: float = 0.3 ** 2
+    s0: float = 0.01
+    nx: int = 1
+    ny: int = 1
+
+    @property
+    def m0(self):
+        return np.array([math.log(self.c)])
+
+    @property
+    def P0(self):
+        return np.array([[self.s0 ** 2]])
+
+    @property
+    def theta(self):
+        return np.array([math.log(self.a), math.log(self.b), math.log(self.Q)])
+
+
 # ---------------------------------------------------------------------------
 # simulators
 # ---------------------------------------------------------------------------
@@ -154,6 +184,20 @@ def simulate_cv(n: int, rng: np.random.Generator, model: CVModel | None = None):
     x[1:, 2:] = v
     y = p + md.r * e[:, 4:]
     return x, y
+
+
+def simulate_ricker(n: int, rng: np.random.Generator, model: RickerModel | None = None):
+    """Simulate one Ricker trajectory; returns (x[n+1, 1], y[n, 1]) (counts
+    as float64)."""
+    md = RickerModel() if model is None else model
+    e = rng.standard_normal(n)
+    x = np.zeros(n + 1)
+    x[0] = math.log(md.c)
+    la, sq = math.log(md.a), math.sqrt(md.Q)
+    for k in range(n):
+        x[k + 1] = la + x[k] - math.exp(x[k]) + sq * e[k]
+    y = rng.poisson(md.b * np.exp(x[1:])).astype(np.float64)
+    return x[:, None], y[:, None]
 
 
 # ---------------------------------------------------------------------------
@@ -284,3 +328,24 @@ def simulate_linear(G, m0, N0, n: int, rng: np.random.Generator):
         x = pick("F", j) @ x + pick("c", j) + pick("SL", j) @ rng.standard_normal(nx)
         y[j] = pick("H", j) @ x + pick("d", j) + pick("SO", j) @ rng.standard_normal(ny)
     return y
+
+
+def ricker_single(n: int = 1000, seed: int = 5, M: int = 10) -> Workload:
+    """Ricker-Poisson model, one sequence."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    md = RickerModel()
+    x, y = simulate_ricker(n, rng, md)
+    yy, off = _pack([(x, y)])
+    return Workload("ricker_n%d_seed%d" % (n, seed), md, yy, off, np.full(1, 2, np.int64), [x],
+                    M=M)
+
+
+def ricker_batch(B: int = 100, n: int = 1000, seed: int = 6, M: int = 100) -> Workload:
+    """Batch of B equal-length Ricker sequences (the paper repeats each
+    configuration 100 times)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    md = RickerModel()
+    seqs = [simulate_ricker(n, rng, md) for _ in range(B)]
+    yy, off = _pack(seqs)
+    return Workload("ricker_B%d_n%d_seed%d" % (B, n, seed), md, yy, off, np.full(B, 2, np.int64),
+                    [s[0] for s in seqs], M=M)
