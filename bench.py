@@ -390,6 +390,70 @@ def bench_divergence(stream, dev, sets=15, passes=20, lengths=(100, 1000, 4000, 
     return {"sets": sets, "passes": passes, "nonfinite_share": out}
 
 
+def bench_ricker(stream, dev, lengths=(10 ** 3, 10 ** 4, 10 ** 5), M=100, seed=8):
+    """The Ricker-Poisson experiment of Section 6.1 on one sequence per
+    length: M = 100 passes of the iterated extended (Taylor) and cubature
+    smoothers, covariance and square-root forms, FP64, parallel; the
+    sequential square-root comparator timed over 2 passes (per pass)."""
+    out = {}
+    for n in lengths:
+        rng = np.random.Generator(np.random.PCG64(seed))
+        md = wl.RickerModel()
+        _, y = wl.simulate_ricker(n, rng, md)
+        off = np.array([0, n], dtype=np.int64)
+        yd = pss.to_soa(y, torch.float64, dev)
+        row = {}
+        for lin in ("taylor", "cubature"):
+            for form in ("cov", "sqrt"):
+                b = pss.Batch.ricker(off, md, dtype=torch.float64, device=dev, linearization=lin,
+                                     form=form)
+                m0, N0 = b.prior_nominal()
+                mm, NN = m0.clone(), N0.clone()
+                wi, _ = b.workspace("ipls")
+                t_par = timed(stream, lambda: (mm.copy_(m0), NN.copy_(N0),
+                                               pss.ipls_iterate(b, yd, M, mm, NN, ws=wi)), 2)
+                r = {"parallel_ms_M%d" % M: round(t_par, 3),
+                     "parallel_ms_per_pass": round(t_par / M, 4)}
+                if form == "sqrt":
+                    wsq, _ = b.workspace("sequential")
+                    t_seq = timed(stream, lambda: (mm.copy_(m0), NN.copy_(N0),
+                                                   pss.sequential_smoother(b, yd, 2, mm, NN,
+                                                                           ws=wsq)), 1) / 2
+                    r["sequential_ms_per_pass"] = round(t_seq, 4)
+                    r["speedup_per_pass"] = round(t_seq / (t_par / M), 2)
+                row["%s_%s" % (lin, form)] = r
+                log("ricker n=%d %s %s: %d passes %.3f ms%s" % (
+                    n, lin, form, M, t_par,
+                    "" if form == "cov" else ", sequential %.3f ms/pass" % r[
+                        "sequential_ms_per_pass"]))
+        out["n%d" % n] = row
+    return {"model": "ricker_poisson a=44.7 b=10 c=7 Q=0.09", "passes": M, "dtype": "f64",
+            "timings": out}
+
+
+def bench_ct_rules(stream, dev, full, n=10 ** 5):
+    """Per-pass time of the CT smoother (square-root form) with each
+    linearisation on a 10^5-step prefix of the main sequence."""
+    out = {}
+    wsub_y = full.y[:n]
+    off = np.array([0, n], dtype=np.int64)
+    for dt in ("f64", "f32"):
+        tdt = torch.float64 if dt == "f64" else torch.float32
+        yd = pss.to_soa(wsub_y, tdt, dev)
+        for lin, kw in (("cubature", {}), ("taylor", {}), ("unscented", {}),
+                        ("gauss_hermite", {"gh_order": 3})):
+            b = pss.Batch.ct(off, full.model, dtype=tdt, device=dev, linearization=lin, **kw)
+            m0, N0 = b.prior_nominal()
+            mm, NN = m0.clone(), N0.clone()
+            wi, _ = b.workspace("ipls")
+            t = timed(stream, lambda: (mm.copy_(m0), NN.copy_(N0),
+                                       pss.ipls_iterate(b, yd, 1, mm, NN, ws=wi)), 5)
+            key = lin if lin != "gauss_hermite" else "gauss_hermite3"
+            out["%s_%s" % (key, dt)] = round(t, 4)
+            log("CT n=%d %s %s: %.3f ms/pass" % (n, key, dt, t))
+    return {"n": n, "ms_per_pass": out}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -577,6 +641,8 @@ def main():
         if not args.no_extras:
             extras["batched_ragged_512"] = bench_batched(stream, dev, M)
             extras["fp32_divergence"] = bench_divergence(stream, dev)
+            extras["ricker_poisson"] = bench_ricker(stream, dev)
+            extras["ct_linearisations_1e5"] = bench_ct_rules(stream, dev, full)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -5,8 +5,10 @@
  * statistical linear regression for inference in nonlinear state space
  * models".  The library computes, on one GPU and for a batch of independent
  * sequences,
- *   - the cubature statistical linear regression of the model around a
- *     nominal trajectory (Section 4.3),
+ *   - the statistical linear regression of the model around a nominal
+ *     trajectory: the generalised SLR (Section 2.3) with a positive-weight
+ *     sigma-point rule (cubature, unscented or Gauss-Hermite; Section 4.3),
+ *     or the first-order Taylor expansion (Section 4.2),
  *   - the square-root parallel Kalman filter elements (Lemma 1, Tables 1-2)
  *     and their associative scan (Lemma 2, Table 3, Algorithm 1),
  *   - the square-root parallel RTS smoother (Lemmas 3-4, Tables 4-5,
@@ -71,17 +73,38 @@ typedef enum {
        x = (px, py, vx, vy, w), nx = 5, ny = 2, additive noise with
        Q(theta) = q1 Qv + q2 Qw (integrated white-noise acceleration) and
        R(theta) = sigma^2 I, theta = (log q1, log q2, log sigma). */
-    PSS_MODEL_CT_BEARINGS = 1
+    PSS_MODEL_CT_BEARINGS = 1,
+    /* stochastic Ricker population model with Poisson counts (Section 6.1):
+       nx = ny = 1, x_k = log a + x_{k-1} - exp(x_{k-1}) + q_k, q_k ~ N(0, Q),
+       y_k | x_k ~ Poisson(b exp(x_k)); theta = (log a, log b, log Q).  The
+       measurement noise is not additive: E[y|x] = V[y|x] = b exp(x), and the
+       conditional variance enters S_Omega through E[V[y|x]] (GSLR moments,
+       Section 2.3).  The paper's point-mass prior at log c is given as m0 =
+       log c with a small factor N0 > 0 (a sigma-point rule regresses on the
+       spread of the marginal, so a zero factor has no regression). */
+    PSS_MODEL_RICKER_POISSON = 2
 } pss_model_kind;
 
-/* linearisation of a nonlinear model (PSS_MODEL_CT_BEARINGS) */
+/* linearisation of a nonlinear model (every model but PSS_MODEL_LINEAR).
+   The sigma-point rules have positive weights w_i summing to one and unit
+   points xi_i; for the marginal N(m, N N^T) the points are m + N xi_i. */
 typedef enum {
     /* statistical linear regression with the third-degree cubature rule
-       (Section 4.3): the iterated posterior-linearisation smoother */
+       (Section 4.3), 2 nx points +-sqrt(nx) e_i: the iterated posterior-
+       linearisation smoother */
     PSS_LIN_CUBATURE = 0,
     /* first-order Taylor expansion at the nominal mean (Section 4.2): the
-       iterated extended smoother; Lambda = Q, Omega = R */
-    PSS_LIN_TAYLOR = 1
+       iterated extended smoother; S_Lambda and S_Omega are the conditional
+       covariance factors at the mean */
+    PSS_LIN_TAYLOR = 1,
+    /* unscented rule with alpha = 1, beta = 0 and spread kappa = ut_kappa
+       (>= 0, so every weight is positive): the centre with weight
+       kappa / (nx + kappa) (dropped when kappa = 0) and +-sqrt(nx + kappa) e_i
+       with weight 1 / (2 (nx + kappa)) */
+    PSS_LIN_UNSCENTED = 2,
+    /* tensor-product Gauss-Hermite rule with gh_order points per coordinate
+       (gh_order^nx points, at most 1024; gh_order in 2..20) */
+    PSS_LIN_GAUSS_HERMITE = 3
 } pss_linearization;
 
 /* form of the parallel filter and smoother */
@@ -120,10 +143,11 @@ typedef struct pss_problem {
     const int64_t *y_off_host;  /* host copy of y_off (launch planning)        */
     const void *m0;             /* device [nx] prior mean, shared by sequences */
     const void *N0;             /* device [nx(nx+1)/2] packed prior factor     */
-    /* coordinated-turn constants (ignored by PSS_MODEL_LINEAR) */
-    double dt;
-    double theta[3];            /* log q1, log q2, log sigma                   */
-    double sensors[4];          /* s1x, s1y, s2x, s2y                          */
+    /* model constants (ignored by PSS_MODEL_LINEAR) */
+    double dt;                  /* CT time step                                */
+    double theta[3];            /* CT: log q1, log q2, log sigma;
+                                   Ricker: log a, log b, log Q                 */
+    double sensors[4];          /* CT: s1x, s1y, s2x, s2y                      */
     /* launch shape overrides (0 = library default / autotuned):
        block threads per scan tile (64, 128 or 256; default 64) and elements
        folded sequentially per thread (>= 1) at the finest level of both
@@ -136,6 +160,10 @@ typedef struct pss_problem {
     int32_t linearization;
     /* pss_form; 0 = square root */
     int32_t form;
+    /* PSS_LIN_GAUSS_HERMITE: points per coordinate (2..20) */
+    int32_t gh_order;
+    /* PSS_LIN_UNSCENTED: spread kappa (finite, >= 0) */
+    double ut_kappa;
 } pss_problem;
 
 /* Square-root linearisation parameters Gamma^sqrt (eq. Gamma-s), SoA over
@@ -162,13 +190,19 @@ typedef struct pss_felem {
    sets the last error for an invalid problem. */
 size_t pss_workspace_size(const pss_problem *p, int32_t op);
 
-/* Cubature statistical linear regression (Sections 4.1 and 4.3) of the
-   model around the nominal marginals (m_nom [nx][T_x], N_nom packed [T_x]):
-   third-degree spherical-radial rule with 2 nx points m +/- sqrt(nx) N e_i.
+/* Statistical linear regression (Sections 2.3, 4.1-4.3) of a nonlinear model
+   around the nominal marginals (m_nom [nx][T_x], N_nom packed [T_x]) with
+   the problem's linearisation (a sigma-point rule or the Taylor expansion).
    Transition parameters of slot (b, k) come from the marginal at state k-1,
-   measurement parameters from the marginal at state k.  Bearings are taken
-   on the branch nearest to the measurement y (y [ny][T_y]).  Writes `out`
-   (stride must be 1).  PSS_MODEL_CT_BEARINGS only. */
+   measurement parameters from the marginal at state k.  CT bearings are
+   taken on the branch nearest to the measurement y (y [ny][T_y]).  The
+   regression residual enters the noise factors without a downdate:
+   S = Tria([noise columns, sqrt(w_i)(Z_i - zbar - G(X_i - m))]), equal to
+   the paper's DownDate(Tria([noise columns, Zx]), G N) because the rules
+   integrate second moments exactly; noise columns are the constant factor
+   (additive noise) or sqrt(w_i) times the conditional factor at each point
+   (Poisson counts).  Writes `out` (stride must be 1).  Nonlinear models
+   only. */
 int pss_slr_linearize(const pss_problem *p, const void *m_nom, const void *N_nom,
                       const void *y, const pss_gamma *out, hipStream_t stream);
 
@@ -199,14 +233,15 @@ int pss_sqrt_smoother_scan(const pss_problem *p, const pss_gamma *g, const void 
    entry and the final smoothing marginals on exit.  m_f / N_f (nullable)
    receive the last pass's filtering marginals.  For PSS_MODEL_LINEAR the
    linearisation `g` is used as is on every pass (the SLR of an affine model
-   is the model itself); for PSS_MODEL_CT_BEARINGS `g` must be NULL.
+   is the model itself); for a nonlinear model `g` must be NULL.
    ws: pss_workspace_size(PSS_OP_IPLS). */
 int pss_ipls_iterate(const pss_problem *p, const pss_gamma *g, const void *y, int32_t n_iter,
                      void *m_nom, void *N_nom, void *m_f, void *N_f, void *ws, size_t ws_bytes,
                      hipStream_t stream);
 
 /* Pseudo-log-likelihood of Section 5.1: the model is linearised at the
-   nominal (CT; for LINEAR `g` is used), filtered with Algorithm 1, and
+   nominal (nonlinear models; for LINEAR `g` is used), filtered with
+   Algorithm 1, and
    ll[b] = sum_k log N(y_k; H_k m^-_k + d_k, Y_k Y_k^T) with the predicted
    factor Y_k = Tria([H_k Tria([F_{k-1} N^f_{k-1}, S_Lambda]), S_Omega]).
    ll: device double [B] (FP64 accumulation for both dtypes).
@@ -216,8 +251,8 @@ int pss_loglik(const pss_problem *p, const pss_gamma *g, const void *m_nom, cons
 
 /* Gradient of the pseudo-log-likelihood with respect to theta = (log q1,
    log q2, log sigma) at a FROZEN nominal (the partial derivative term of
-   eq. gradient; PSS_MODEL_CT_BEARINGS only).  With the nominal fixed, theta
-   enters only through S_Lambda and S_Omega.  The sensitivities dl/dLambda_k
+   eq. gradient; PSS_MODEL_CT_BEARINGS only, any linearisation).  With the
+   nominal fixed, theta enters only through S_Lambda and S_Omega.  The sensitivities dl/dLambda_k
    and dl/dOmega_k are the posterior expectations of the complete-data score
    (Fisher's identity), computed from the parallel square-root smoother of
    the linearised model; they are contracted with dQ/dtheta and dR/dtheta.
@@ -240,9 +275,10 @@ int pss_sequential_smoother(const pss_problem *p, const pss_gamma *g, const void
 /* ---- ragged batches of several model groups in one persistent launch ---- */
 
 /* One model group of a batched call: a ragged batch of sequences of one
-   model.  Supported groups: PSS_MODEL_CT_BEARINGS (nx 5, ny 2) and
-   PSS_MODEL_LINEAR with nx 4, ny 2 (e.g. constant velocity).  All groups of a
-   call share the dtype and the launch-shape overrides. */
+   model.  Supported groups: PSS_MODEL_CT_BEARINGS (nx 5, ny 2) with the
+   cubature or Taylor linearisation, and PSS_MODEL_LINEAR with nx 4, ny 2
+   (e.g. constant velocity).  All groups of a call share the dtype and the
+   launch-shape overrides. */
 typedef struct pss_group {
     const pss_problem *p;  /* model, dimensions, batch offsets, prior        */
     const pss_gamma *g;    /* linear: its parameters (stride 0/1); CT: NULL  */

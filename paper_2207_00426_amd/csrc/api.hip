@@ -12,6 +12,7 @@
 #include <utility>
 #include <vector>
 
+#include "rules_host.hpp"
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -284,6 +285,57 @@ CTHost ct_host(const pss_problem *p)
     return h;
 }
 
+RickerHost ricker_host(const pss_problem *p)
+{
+    RickerHost h;
+    h.loga = p->theta[0];
+    h.b = exp(p->theta[1]);
+    h.sqQ = exp(0.5 * p->theta[2]);
+    return h;
+}
+
+bool rule_host(const pss_problem *p, int nx, RuleHost &r)
+{
+    r = RuleHost{};
+    switch (p->linearization) {
+    case PSS_LIN_UNSCENTED: {
+        const double k = p->ut_kappa;
+        r.kind = 1;
+        r.w0 = k / (nx + k);
+        r.wi = 1.0 / (2.0 * (nx + k));
+        r.spread = sqrt(nx + k);
+        r.np = 2 * nx + (k > 0.0 ? 1 : 0);
+        return true;
+    }
+    case PSS_LIN_GAUSS_HERMITE: {
+        const int q = p->gh_order;
+        if (q < 2 || q > kMaxGH) {
+            set_error("gh_order must be in 2..20");
+            return false;
+        }
+        int64_t np = 1;
+        for (int j = 0; j < nx; ++j)
+            np *= q;
+        if (np > kMaxRulePoints) {
+            set_error("Gauss-Hermite rule: gh_order^nx must not exceed 1024 points");
+            return false;
+        }
+        r.kind = 2;
+        r.p = q;
+        r.np = (int)np;
+        gauss_hermite_1d(q, r.gx, r.gw);
+        return true;
+    }
+    default: // cubature
+        r.kind = 0;
+        r.w0 = 0.0;
+        r.wi = 1.0 / (2.0 * nx);
+        r.spread = sqrt((double)nx);
+        r.np = 2 * nx;
+        return true;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // dispatch
 // ---------------------------------------------------------------------------
@@ -328,7 +380,8 @@ static int validate(const pss_problem *p)
         set_error("null problem");
         return PSS_EINVAL;
     }
-    if (p->model != PSS_MODEL_LINEAR && p->model != PSS_MODEL_CT_BEARINGS) {
+    if (p->model != PSS_MODEL_LINEAR && p->model != PSS_MODEL_CT_BEARINGS &&
+        p->model != PSS_MODEL_RICKER_POISSON) {
         set_error("unknown model");
         return PSS_EINVAL;
     }
@@ -342,6 +395,10 @@ static int validate(const pss_problem *p)
     }
     if (p->model == PSS_MODEL_CT_BEARINGS && (p->nx != 5 || p->ny != 2)) {
         set_error("the coordinated-turn model has nx = 5, ny = 2");
+        return PSS_EINVAL;
+    }
+    if (p->model == PSS_MODEL_RICKER_POISSON && (p->nx != 1 || p->ny != 1)) {
+        set_error("the Ricker-Poisson model has nx = ny = 1");
         return PSS_EINVAL;
     }
     if (!dims_built(p->nx, p->ny)) {
@@ -374,9 +431,19 @@ static int validate(const pss_problem *p)
         set_error("form must be PSS_FORM_SQRT or PSS_FORM_COV");
         return PSS_EINVAL;
     }
-    if (p->linearization != PSS_LIN_CUBATURE && p->linearization != PSS_LIN_TAYLOR) {
-        set_error("linearization must be PSS_LIN_CUBATURE or PSS_LIN_TAYLOR");
+    if (p->linearization < PSS_LIN_CUBATURE || p->linearization > PSS_LIN_GAUSS_HERMITE) {
+        set_error("linearization must be one of the pss_linearization values");
         return PSS_EINVAL;
+    }
+    if (p->model != PSS_MODEL_LINEAR) {
+        if (p->linearization == PSS_LIN_UNSCENTED &&
+            !(isfinite(p->ut_kappa) && p->ut_kappa >= 0.0)) {
+            set_error("the unscented rule needs a finite ut_kappa >= 0 (positive weights)");
+            return PSS_EINVAL;
+        }
+        RuleHost r;
+        if (p->linearization == PSS_LIN_GAUSS_HERMITE && !rule_host(p, p->nx, r))
+            return PSS_EINVAL;
     }
     if (p->scan_elems < 0 || p->scan_elems > 256) {
         set_error("scan_elems must be in 0..256");
@@ -388,6 +455,11 @@ static int validate(const pss_problem *p)
             set_error("coordinated-turn model needs dt > 0 and a finite theta");
             return PSS_EINVAL;
         }
+    }
+    if (p->model == PSS_MODEL_RICKER_POISSON &&
+        !(isfinite(p->theta[0]) && isfinite(p->theta[1]) && isfinite(p->theta[2]))) {
+        set_error("Ricker-Poisson model needs a finite theta");
+        return PSS_EINVAL;
     }
     return PSS_OK;
 }
@@ -543,7 +615,7 @@ int pss_slr_linearize(const pss_problem *p, const void *m_nom, const void *N_nom
         int rc = validate(p);
         if (rc)
             return rc;
-        if (p->model != PSS_MODEL_CT_BEARINGS) {
+        if (p->model == PSS_MODEL_LINEAR) {
             set_error("slr_linearize needs a nonlinear model");
             return PSS_EUNSUPPORTED;
         }
@@ -641,7 +713,7 @@ int pss_ipls_iterate(const pss_problem *p, const pss_gamma *g, const void *y, in
             return PSS_EINVAL;
         }
         if (p->model == PSS_MODEL_LINEAR ? !gamma_ok(g) : g != nullptr) {
-            set_error("ipls_iterate: a linear model needs g, the CT model takes g = NULL");
+            set_error("ipls_iterate: a linear model needs g, a nonlinear model takes g = NULL");
             return PSS_EINVAL;
         }
         const Ctx c = make_ctx(p, stream);
@@ -666,7 +738,7 @@ int pss_loglik(const pss_problem *p, const pss_gamma *g, const void *m_nom, cons
             return PSS_EINVAL;
         }
         if (p->model == PSS_MODEL_LINEAR ? !gamma_ok(g) : (!m_nom || !N_nom)) {
-            set_error("loglik: a linear model needs g, the CT model needs the nominal");
+            set_error("loglik: a linear model needs g, a nonlinear model needs the nominal");
             return PSS_EINVAL;
         }
         const Ctx c = make_ctx(p, stream);
@@ -722,7 +794,8 @@ int pss_sequential_smoother(const pss_problem *p, const pss_gamma *g, const void
             return PSS_EINVAL;
         }
         if (p->model == PSS_MODEL_LINEAR ? !gamma_ok(g) : g != nullptr) {
-            set_error("sequential_smoother: a linear model needs g, the CT model takes g = NULL");
+            set_error("sequential_smoother: a linear model needs g, a nonlinear model takes g = "
+                      "NULL");
             return PSS_EINVAL;
         }
         const Ctx c = make_ctx(p, stream);

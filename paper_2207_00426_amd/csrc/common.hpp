@@ -90,6 +90,25 @@ struct CTHost {
 };
 CTHost ct_host(const pss_problem *p);
 
+// Ricker-Poisson constants (host, double precision)
+struct RickerHost {
+    double loga, b, sqQ;
+};
+RickerHost ricker_host(const pss_problem *p);
+
+// positive-weight sigma-point rule of the problem's linearisation (host):
+// cubature (kind 0), unscented (1) or tensor Gauss-Hermite (2), see pss.h
+constexpr int kMaxGH = 20;
+constexpr int kMaxRulePoints = 1024;
+struct RuleHost {
+    int kind = 0, np = 0, p = 0;
+    double w0 = 0.0, wi = 0.0, spread = 0.0;
+    double gx[kMaxGH] = {}, gw[kMaxGH] = {};
+};
+// builds the rule for dimension nx; returns false (with the error set) for
+// an invalid order or too many points
+bool rule_host(const pss_problem *p, int nx, RuleHost &r);
+
 // one implementation per (dtype, nx, ny); defined in impl.hpp, explicitly
 // instantiated in inst.hip
 template <typename T, int NX, int NY>

@@ -392,7 +392,8 @@ struct Core {
         carve_gamma(cv, c.T_y);
         return cv.used;
     }
-    static bool is_ct(const Ctx &c) { return c.p->model == PSS_MODEL_CT_BEARINGS; }
+    // nonlinear models are linearised on every pass; a linear one is given
+    static bool nonlinear(const Ctx &c) { return c.p->model != PSS_MODEL_LINEAR; }
 
     static size_t ws_size(const Ctx &c, int op)
     {
@@ -431,7 +432,7 @@ struct Core {
         T *fel = cv.template take<T>((size_t)Sizes<NX>::felem * c.T_y);
         T *mfb = cv.template take<T>((size_t)Sizes<NX>::marg * c.T_x);
         void *scan_ws = cv.base + cv.used;
-        const pss_gamma *g = is_ct(c) ? &gw : gin;
+        const pss_gamma *g = nonlinear(c) ? &gw : gin;
         FElemRef<T, NX> fr = felem_ref(fel, c.T_y);
         pss_felem el{fr.A, fr.b, fr.U, fr.eta, fr.Z};
         void *mf = mf_out ? mf_out : (void *)mfb;
@@ -439,7 +440,7 @@ struct Core {
         int rc = PSS_OK;
         const bool cov = c.p->form == PSS_FORM_COV;
         for (int it = 0; it < n_iter && rc == PSS_OK; ++it) {
-            if (is_ct(c) && (rc = slr(c, m_nom, N_nom, y, &gw)))
+            if (nonlinear(c) && (rc = slr(c, m_nom, N_nom, y, &gw)))
                 break;
             if ((rc = felem(c, g, y, &el, true, cov)))
                 break;
@@ -460,13 +461,13 @@ struct Core {
         mfb = cv.template take<T>((size_t)Sizes<NX>::marg * c.T_x);
         double *ell = cv.template take<double>((size_t)c.T_y);
         scan_ws = cv.base + cv.used;
-        const pss_gamma *g = is_ct(c) ? &gw : gin;
-        if (!is_ct(c))
+        const pss_gamma *g = nonlinear(c) ? &gw : gin;
+        if (!nonlinear(c))
             gw = *gin;
         FElemRef<T, NX> fr = felem_ref(fel, c.T_y);
         pss_felem el{fr.A, fr.b, fr.U, fr.eta, fr.Z};
         int rc;
-        if (is_ct(c) && (rc = slr(c, m_nom, N_nom, y, &gw)))
+        if (nonlinear(c) && (rc = slr(c, m_nom, N_nom, y, &gw)))
             return rc;
         const bool cov = c.p->form == PSS_FORM_COV;
         if ((rc = felem(c, g, y, &el, true, cov)))
@@ -540,12 +541,12 @@ struct Core {
         Carver cv{static_cast<char *>(ws)};
         pss_gamma gw = carve_gamma(cv, c.T_y);
         T *mfb = cv.template take<T>((size_t)Sizes<NX>::marg * c.T_x);
-        const pss_gamma *g = is_ct(c) ? &gw : gin;
+        const pss_gamma *g = nonlinear(c) ? &gw : gin;
         void *mf = mf_out ? mf_out : (void *)mfb;
         void *Nf = mf_out ? Nf_out : (void *)(mfb + (size_t)NX * c.T_x);
         int rc = PSS_OK;
         for (int it = 0; it < n_iter && rc == PSS_OK; ++it) {
-            if (is_ct(c) && (rc = slr(c, m_nom, N_nom, y, &gw)))
+            if (nonlinear(c) && (rc = slr(c, m_nom, N_nom, y, &gw)))
                 break;
             const int tb = 64;
             KTime kt(c.s, "sequential", "", 0);
@@ -559,34 +560,83 @@ struct Core {
     }
 };
 
+template <typename T>
+static bool rule_spec(const pss_problem *p, int nx, RuleSpec<T> &R)
+{
+    RuleHost h;
+    if (!rule_host(p, nx, h))
+        return false;
+    R.kind = h.kind;
+    R.np = h.np;
+    R.p = h.p;
+    R.w0 = (T)h.w0;
+    R.wi = (T)h.wi;
+    R.spread = (T)h.spread;
+    for (int q = 0; q < kMaxGH; ++q) {
+        R.gx[q] = (T)h.gx[q];
+        R.gw[q] = (T)h.gw[q];
+    }
+    return true;
+}
+
 template <typename T, int NX, int NY>
 int Core<T, NX, NY>::slr(const Ctx &c, const void *m, const void *N, const void *y,
                          const pss_gamma *out)
 {
+    const int tb = 128;
+    const dim3 grid((unsigned)((c.T_x + tb - 1) / tb));
+    const int lin = c.p->linearization;
+    const int cov = c.p->form == PSS_FORM_COV ? 1 : 0;
     if constexpr (NX == 5 && NY == 2) {
-        const CTHost h = ct_host(c.p);
-        CTParams<T> P;
-        P.dt = (T)h.dt;
-        P.s1x = (T)h.s1x;
-        P.s1y = (T)h.s1y;
-        P.s2x = (T)h.s2x;
-        P.s2y = (T)h.s2y;
-        P.sigma = (T)h.sigma;
-        for (int i = 0; i < 5; ++i)
-            for (int j = 0; j < 5; ++j)
-                P.LQ[i][j] = (T)h.LQ[i][j];
-        const int tb = 128;
-        KTime kt(c.s, "slr", "", 0);
-        hipLaunchKernelGGL((k_slr_ct<T>), dim3((unsigned)((c.T_x + tb - 1) / tb)), dim3(tb), 0,
-                           c.s, c.p->y_off, c.B, c.T_x, c.T_y, P, marg_ref2(m, N, c.T_x),
-                           cptr<T>(y), gamma_ref(out, c.T_y),
-                           c.p->linearization == PSS_LIN_TAYLOR ? 1 : 0,
-                           c.p->form == PSS_FORM_COV ? 1 : 0);
-        return hip_check(hipGetLastError(), "slr launch");
-    } else {
-        set_error("the coordinated-turn model needs nx = 5, ny = 2");
-        return PSS_EUNSUPPORTED;
+        if (c.p->model == PSS_MODEL_CT_BEARINGS) {
+            const CTHost h = ct_host(c.p);
+            CTParams<T> P;
+            P.dt = (T)h.dt;
+            P.s1x = (T)h.s1x;
+            P.s1y = (T)h.s1y;
+            P.s2x = (T)h.s2x;
+            P.s2y = (T)h.s2y;
+            P.sigma = (T)h.sigma;
+            for (int i = 0; i < 5; ++i)
+                for (int j = 0; j < 5; ++j)
+                    P.LQ[i][j] = (T)h.LQ[i][j];
+            if (lin == PSS_LIN_CUBATURE || lin == PSS_LIN_TAYLOR) {
+                KTime kt(c.s, "slr", "", 0);
+                hipLaunchKernelGGL((k_slr_ct<T>), grid, dim3(tb), 0, c.s, c.p->y_off, c.B, c.T_x,
+                                   c.T_y, P, marg_ref2(m, N, c.T_x), cptr<T>(y),
+                                   gamma_ref(out, c.T_y), lin == PSS_LIN_TAYLOR ? 1 : 0, cov);
+            } else {
+                RuleSpec<T> R;
+                if (!rule_spec(c.p, NX, R))
+                    return PSS_EINVAL;
+                KTime kt(c.s, "slr", "", 0);
+                hipLaunchKernelGGL((k_slr_ct_rule<T>), grid, dim3(tb), 0, c.s, c.p->y_off, c.B,
+                                   c.T_x, c.T_y, P, marg_ref2(m, N, c.T_x), cptr<T>(y),
+                                   gamma_ref(out, c.T_y), R, cov);
+            }
+            return hip_check(hipGetLastError(), "slr launch");
+        }
     }
+    if constexpr (NX == 1 && NY == 1) {
+        if (c.p->model == PSS_MODEL_RICKER_POISSON) {
+            const RickerHost h = ricker_host(c.p);
+            RickerParams<T> P;
+            P.loga = (T)h.loga;
+            P.b = (T)h.b;
+            P.sqQ = (T)h.sqQ;
+            RuleSpec<T> R{};
+            if (lin != PSS_LIN_TAYLOR && !rule_spec(c.p, NX, R))
+                return PSS_EINVAL;
+            KTime kt(c.s, "slr", "", 0);
+            hipLaunchKernelGGL((k_slr_ricker<T>), grid, dim3(tb), 0, c.s, c.p->y_off, c.B, c.T_x, P,
+                               marg_ref2(m, N, c.T_x), gamma_ref(out, c.T_y),
+                               lin == PSS_LIN_TAYLOR ? 1 : 0, R, cov);
+            return hip_check(hipGetLastError(), "slr launch");
+        }
+    }
+    (void)y;
+    set_error("no linearisation is built for this model and dimension pair");
+    return PSS_EUNSUPPORTED;
 }
 
 template <typename T, int NX, int NY>

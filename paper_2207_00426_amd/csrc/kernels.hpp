@@ -22,6 +22,7 @@
 #include "common.hpp"
 #include "device_cov.hpp"
 #include "device_ops.hpp"
+#include "device_rules.hpp"
 
 namespace pss {
 
@@ -1180,6 +1181,77 @@ __global__ __launch_bounds__(128) void k_slr_ct(const int64_t *y_off, int B, int
             ct_slr_bearings(P, mg, yy, G, off, S);
         out.store_obs(t, G, off, S);
     }
+}
+
+// the CT model with the unscented or Gauss-Hermite rule (one thread per
+// state, the slots as k_slr_ct)
+template <typename T>
+__global__ __launch_bounds__(128) void k_slr_ct_rule(const int64_t *y_off, int B, int64_t T_x,
+                                                     int64_t T_y, CTParams<T> P,
+                                                     MargRef<T, 5> nom, const T *y,
+                                                     GammaRef<T, 5, 2> out, RuleSpec<T> R,
+                                                     int nominal_cov)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= T_x)
+        return;
+    const int b = find_seq(y_off, B, s, 1);
+    const int64_t x0 = y_off[b] + b, k = s - x0, n = y_off[b + 1] - y_off[b];
+    Marg<T, 5> mg;
+    nom.load(s, mg);
+    if (nominal_cov) {
+        T Pm[5][5], L[5][5];
+        sym_full(Pm, [&](int i, int j) { return mg.N[i][j]; });
+        chol_lower(Pm, L);
+#pragma unroll
+        for (int i = 0; i < 5; ++i)
+#pragma unroll
+            for (int j = 0; j <= i; ++j)
+                mg.N[i][j] = L[i][j];
+    }
+    if (k < n) {
+        T G[5][5], off[5], S[5][5];
+        ct_rule_transition(R, P, mg, G, off, S);
+        out.store_trans(y_off[b] + k, G, off, S);
+    }
+    if (k >= 1) {
+        const int64_t t = y_off[b] + k - 1;
+        T yy[2] = {y[t], y[T_y + t]};
+        T G[2][5], off[2], S[2][2];
+        ct_rule_bearings(R, P, mg, yy, G, off, S);
+        out.store_obs(t, G, off, S);
+    }
+}
+
+// Ricker-Poisson model: first-order Taylor (taylor != 0) or the rule R
+template <typename T>
+__global__ __launch_bounds__(128) void k_slr_ricker(const int64_t *y_off, int B, int64_t T_x,
+                                                    RickerParams<T> P, MargRef<T, 1> nom,
+                                                    GammaRef<T, 1, 1> out, int taylor,
+                                                    RuleSpec<T> R, int nominal_cov)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= T_x)
+        return;
+    const int b = find_seq(y_off, B, s, 1);
+    const int64_t x0 = y_off[b] + b, k = s - x0, n = y_off[b + 1] - y_off[b];
+    Marg<T, 1> mg;
+    nom.load(s, mg);
+    if (nominal_cov) // the nominal holds the variance
+        mg.N[0][0] = psqrt(mg.N[0][0]);
+    T F[1][1], c[1], SL[1][1], H[1][1], d[1], SO[1][1];
+    if (taylor) {
+        ricker_taylor(P, mg, mg, k < n, k >= 1, F, c, SL, H, d, SO);
+    } else {
+        if (k < n)
+            ricker_rule_transition(R, P, mg, F, c, SL);
+        if (k >= 1)
+            ricker_rule_poisson(R, P, mg, H, d, SO);
+    }
+    if (k < n)
+        out.store_trans(y_off[b] + k, F, c, SL);
+    if (k >= 1)
+        out.store_obs(y_off[b] + k - 1, H, d, SO);
 }
 
 // covariance form of the log-likelihood terms: P^- = F P^f F^T + Lambda,

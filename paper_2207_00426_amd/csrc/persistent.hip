@@ -181,6 +181,12 @@ int validate_groups(const pss_group *gs, int ng)
             set_error("batched: the persistent pass is defined for the square-root form only");
             return PSS_EUNSUPPORTED;
         }
+        if (p->model != PSS_MODEL_LINEAR && p->linearization != PSS_LIN_CUBATURE &&
+            p->linearization != PSS_LIN_TAYLOR) {
+            set_error("batched: the persistent pass fuses the cubature or Taylor linearisation "
+                      "only");
+            return PSS_EUNSUPPORTED;
+        }
         if (p->dtype != gs[0].p->dtype) {
             set_error("batched: all groups need the same dtype");
             return PSS_EINVAL;

@@ -24,9 +24,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpss.so")
 
 PSS_F32, PSS_F64 = 0, 1
-MODEL_LINEAR, MODEL_CT = 0, 1
-LIN_CUBATURE, LIN_TAYLOR = 0, 1
-LINEARIZATIONS = {"cubature": LIN_CUBATURE, "taylor": LIN_TAYLOR}
+MODEL_LINEAR, MODEL_CT, MODEL_RICKER = 0, 1, 2
+LIN_CUBATURE, LIN_TAYLOR, LIN_UNSCENTED, LIN_GAUSS_HERMITE = 0, 1, 2, 3
+LINEARIZATIONS = {"cubature": LIN_CUBATURE, "taylor": LIN_TAYLOR, "unscented": LIN_UNSCENTED,
+                  "gauss_hermite": LIN_GAUSS_HERMITE}
 FORM_SQRT, FORM_COV = 0, 1
 FORMS = {"sqrt": FORM_SQRT, "cov": FORM_COV}
 OPS = dict(slr=0, filter_elements=1, filter_scan=2, smoother_scan=3, ipls=4, loglik=5,
@@ -55,7 +56,8 @@ class Problem(ctypes.Structure):
                 ("dt", ctypes.c_double), ("theta", ctypes.c_double * 3),
                 ("sensors", ctypes.c_double * 4),
                 ("scan_threads", ctypes.c_int32), ("scan_elems", ctypes.c_int32),
-                ("linearization", ctypes.c_int32), ("form", ctypes.c_int32)]
+                ("linearization", ctypes.c_int32), ("form", ctypes.c_int32),
+                ("gh_order", ctypes.c_int32), ("ut_kappa", ctypes.c_double)]
 
 
 class GroupC(ctypes.Structure):
@@ -223,7 +225,7 @@ class Batch:
 
     def __init__(self, model, dtype, nx, ny, y_off, m0, N0, device="cuda", dt=0.0,
                  theta=(0.0, 0.0, 0.0), sensors=(0.0, 0.0, 0.0, 0.0), scan_threads=0,
-                 scan_elems=0, linearization="cubature", form="sqrt"):
+                 scan_elems=0, linearization="cubature", form="sqrt", gh_order=3, ut_kappa=None):
         self.model = model
         self.torch_dtype = dtype
         self.nx, self.ny = nx, ny
@@ -243,6 +245,10 @@ class Batch:
         self.scan_elems = int(scan_elems)
         self.linearization = LINEARIZATIONS[linearization]
         self.form = FORMS[form]
+        self.gh_order = int(gh_order)
+        # unscented spread: Julier's nx + kappa = 3 where the centre weight
+        # stays positive, else 1
+        self.ut_kappa = float(max(3 - nx, 1) if ut_kappa is None else ut_kappa)
 
     @classmethod
     def ct(cls, y_off, model, dtype=torch.float64, device="cuda", theta=None, **kw):
@@ -252,6 +258,14 @@ class Batch:
         return cls(MODEL_CT, dtype, 5, 2, y_off, model.m0, np.linalg.cholesky(model.P0),
                    device=device, dt=model.dt, theta=th,
                    sensors=(s[0][0], s[0][1], s[1][0], s[1][1]), **kw)
+
+    @classmethod
+    def ricker(cls, y_off, model, dtype=torch.float64, device="cuda", theta=None, **kw):
+        """Ricker-Poisson model (workloads.RickerModel): theta = (log a,
+        log b, log Q); prior N(log c, s0^2)."""
+        th = model.theta if theta is None else theta
+        return cls(MODEL_RICKER, dtype, 1, 1, y_off, model.m0, np.sqrt(model.P0),
+                   device=device, theta=th, **kw)
 
     @property
     def pss_dtype(self):
@@ -273,6 +287,8 @@ class Batch:
         p.scan_elems = self.scan_elems
         p.linearization = getattr(self, "linearization", LIN_CUBATURE)
         p.form = getattr(self, "form", FORM_SQRT)
+        p.gh_order = getattr(self, "gh_order", 3)
+        p.ut_kappa = getattr(self, "ut_kappa", 1.0)
         return p
 
     # buffers -------------------------------------------------------------

@@ -137,7 +137,7 @@ def test_form_and_linearization_fields_are_validated(L):
     b.form = 2
     assert pss.validate(b) == -1
     b = _cpu_batch()
-    b.linearization = 3
+    b.linearization = 4
     assert pss.validate(b) == -1
     assert pss.validate(_cpu_batch(form="cov")) == 0
     # the covariance form is refused by the square-root-only entry points
@@ -149,3 +149,48 @@ def test_form_and_linearization_fields_are_validated(L):
     rc = L.pss_sqrt_filter_scan(ctypes.byref(p), ctypes.byref(fe), ctypes.c_void_p(8),
                                 ctypes.c_void_p(8), ctypes.c_void_p(8), 1, None)
     assert rc == -2 and "square-root" in pss.last_error()
+
+
+def _ricker_cpu(**kw):
+    args = dict(model=pss.MODEL_RICKER, dtype=torch.float64, nx=1, ny=1,
+                y_off=np.array([0, 10, 25]), m0=np.array([np.log(7.0)]),
+                N0=np.array([[0.01]]), device="cpu", theta=(np.log(44.7), np.log(10.0),
+                                                           np.log(0.09)))
+    args.update(kw)
+    return pss.Batch(**args)
+
+
+def test_ricker_model_and_sigma_point_rules_are_validated(L):
+    for lin in ("cubature", "taylor", "unscented", "gauss_hermite"):
+        assert pss.validate(_ricker_cpu(linearization=lin)) == 0, lin
+        assert pss.validate(_ricker_cpu(linearization=lin, form="cov")) == 0, lin
+    # the Ricker model is scalar
+    assert pss.validate(_ricker_cpu(nx=2, m0=np.zeros(2), N0=np.eye(2))) == -1
+    b = _ricker_cpu()
+    b.theta = (float("nan"), 0.0, 0.0)
+    assert pss.validate(b) == -1
+    # unscented: kappa >= 0 keeps every weight positive
+    assert pss.validate(_ricker_cpu(linearization="unscented", ut_kappa=-0.5)) == -1
+    assert "kappa" in pss.last_error()
+    assert pss.validate(_ricker_cpu(linearization="unscented", ut_kappa=0.0)) == 0
+    # Gauss-Hermite: order 2..20 and at most 1024 points
+    assert pss.validate(_ricker_cpu(linearization="gauss_hermite", gh_order=1)) == -1
+    assert pss.validate(_ricker_cpu(linearization="gauss_hermite", gh_order=20)) == 0
+    assert pss.validate(_ricker_cpu(linearization="gauss_hermite", gh_order=21)) == -1
+    ct = dict(model=pss.MODEL_CT, nx=5, ny=2, m0=np.zeros(5), N0=np.eye(5), dt=0.01)
+    assert pss.validate(_cpu_batch(linearization="gauss_hermite", gh_order=4, **ct)) == 0
+    assert pss.validate(_cpu_batch(linearization="gauss_hermite", gh_order=5, **ct)) == -1
+    assert "1024" in pss.last_error()
+    # the gradient is defined for the CT model only; refused before any HIP call
+    p = _ricker_cpu().struct()
+    rc = L.pss_loglik_grad(ctypes.byref(p), None, None, None, None, None, None, None, None, 0,
+                           None)
+    assert rc == -2
+    # the persistent pass fuses the cubature / Taylor CT SLR only
+    y = ctypes.c_void_p(8)
+    for bad in (_ricker_cpu(), _cpu_batch(linearization="unscented", **ct)):
+        pb = bad.struct()
+        g = pss.GroupC(ctypes.pointer(pb), None, y, y, y)
+        assert L.pss_batched_workspace_size(ctypes.byref(g), 1) == 0
+        rc = L.pss_ipls_batched(ctypes.byref(g), 1, 1, None, None, 0, None)
+        assert rc == -2, pss.last_error()
