@@ -348,6 +348,36 @@ def ct_score(prm, m0, N0, y, ms, Ns, method="cubature", kappa=None, gh_order=Non
     return tot, g
 
 
+def ct_score_total(prm, m0, N0, y, M=60, h=1e-4, method="cubature", kappa=None,
+                   gh_order=None):
+    """Total derivative of the pseudo-log-likelihood at the IPLS fixed point,
+    l(theta) = lhat(theta, n*(theta)) with n* = KS(n*, theta) (the quantity
+    that eq. implicity_function_theorem / Algorithm 4 reach through a linear
+    fixed point), taken here from its definition: central differences in
+    theta = (log q1, log q2, log sigma) at steps 2h and h, combined by
+    Richardson extrapolation (error O(h^4)); every evaluation runs its own
+    M-pass IPLS from the prior (M = 60 converges the CT iteration to
+    round-off).  Returns (l(theta), gradient [3], n*(theta) as (ms, Ns))."""
+    prm = _f64(prm)
+    th = np.log(prm[1:4])
+    kw = dict(method=method, kappa=kappa, gh_order=gh_order)
+
+    def L(t):
+        p = ct_theta_params(t, prm)
+        r = ct_ipls(p, m0, N0, y, M, **kw)
+        return ct_loglik(p, m0, N0, y, r["ms"], r["Ns"], **kw), r
+
+    l0, r0 = L(th)
+    g = np.zeros(3)
+    for j in range(3):
+        e = np.zeros(3)
+        e[j] = 1.0
+        d1 = (L(th + h * e)[0] - L(th - h * e)[0]) / (2 * h)
+        d2 = (L(th + 2 * h * e)[0] - L(th - 2 * h * e)[0]) / (4 * h)
+        g[j] = (4.0 * d1 - d2) / 3.0
+    return l0, g, r0["ms"], r0["Ns"]
+
+
 def ct_jac_f(prm, x):
     J = np.zeros((5, 5))
     _load().or_ct_jac_f(_p(_f64(prm)), _p(_f64(x)), _p(J))
