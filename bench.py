@@ -431,6 +431,56 @@ def bench_ricker(stream, dev, lengths=(10 ** 3, 10 ** 4, 10 ** 5), M=100, seed=8
             "timings": out}
 
 
+def bench_fixed_point(stream, dev, n=1000, seed=1, passes=40, ift_iter=30):
+    """Gradient at the IPLS fixed point (Algorithm 4) on one CT sequence
+    whose IPLS converges: time per call against the frozen-nominal
+    gradient, their difference, the tangent iteration's last change, and
+    L-BFGS from theta* + 0.5 with either gradient (IPLS re-run to
+    convergence at every evaluation); the true gradient at each end point
+    is the fixed-point one."""
+    w = wl.ct_single(n, seed=seed)
+    b = pss.Batch.ct(w.y_off, w.model, dtype=torch.float64, device=dev)
+    yd = pss.to_soa(w.y, torch.float64, dev)
+    m, N = pss.ipls_iterate(b, yd, passes)
+    wi, _ = b.workspace("loglik_grad_ift")
+    wg, _ = b.workspace("loglik_grad")
+    t_ift = timed(stream, lambda: pss.loglik_grad_ift(b, m, N, yd, n_iter=ift_iter, ws=wi), 2)
+    t_fro = timed(stream, lambda: pss.loglik_grad(b, m, N, yd, ws=wg), 10)
+    _, g_ift, delta = pss.loglik_grad_ift(b, m, N, yd, n_iter=ift_iter, ws=wi, with_delta=True)
+    _, g_fro, _ = pss.loglik_grad(b, m, N, yd, ws=wg)
+    torch.cuda.synchronize()
+    out = {"n": n, "ift_iter": ift_iter, "ms_fixed_point_gradient": round(t_ift, 3),
+           "ms_frozen_gradient": round(t_fro, 4),
+           "gradient_fixed_point": [round(v, 6) for v in g_ift[:, 0].tolist()],
+           "gradient_frozen": [round(v, 6) for v in g_fro[:, 0].tolist()],
+           "tangent_change_last_iteration": float(delta[0])}
+    log("fixed-point gradient n=%d: %.2f ms (%d iterations), frozen %.3f ms; g %s vs frozen %s" % (
+        n, t_ift, ift_iter, t_fro, out["gradient_fixed_point"], out["gradient_frozen"]))
+    th_star = [float(v) for v in w.model.theta]
+    fits = {}
+    for grad in ("fixed_point", "frozen"):
+        t0 = time.perf_counter()
+        fit = estimate.fit_theta_lbfgs(b, yd, [v + 0.5 for v in th_star], n_steps=40,
+                                       passes=passes, gradient=grad, ift_iter=ift_iter)
+        dt = time.perf_counter() - t0
+        b2 = pss._with_theta(b, fit["theta"])
+        m2, N2 = pss.ipls_iterate(b2, yd, passes)
+        _, gt = pss.loglik_grad_ift(b2, m2, N2, yd, n_iter=ift_iter, ws=wi)
+        torch.cuda.synchronize()
+        fits[grad] = {"iterations": fit["iterations"], "evaluations": fit["evaluations"],
+                      "theta_final": [round(v, 5) for v in fit["theta"]],
+                      "loss_final": fit["loss_final"],
+                      "true_gradient_inf_at_end": float(gt.abs().max()) / n,
+                      "total_s": round(dt, 3)}
+        log("L-BFGS with the %s gradient: %d iterations, %d evaluations, theta %s, |true grad| "
+            "%.2e, %.1f s" % (grad, fit["iterations"], fit["evaluations"],
+                              fits[grad]["theta_final"], fits[grad]["true_gradient_inf_at_end"],
+                              dt))
+    out["lbfgs"] = fits
+    out["theta_true"] = [round(v, 5) for v in th_star]
+    return out
+
+
 def bench_ct_rules(stream, dev, full, n=10 ** 5):
     """Per-pass time of the CT smoother (square-root form) with each
     linearisation on a 10^5-step prefix of the main sequence."""
@@ -643,6 +693,8 @@ def main():
             extras["fp32_divergence"] = bench_divergence(stream, dev)
             extras["ricker_poisson"] = bench_ricker(stream, dev)
             extras["ct_linearisations_1e5"] = bench_ct_rules(stream, dev, full)
+            if args.dtype == "f64":
+                extras["fixed_point_gradient"] = bench_fixed_point(stream, dev)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -130,7 +130,8 @@ typedef enum {
     PSS_OP_IPLS = 4,
     PSS_OP_LOGLIK = 5,
     PSS_OP_LOGLIK_GRAD = 6,
-    PSS_OP_SEQUENTIAL = 7
+    PSS_OP_SEQUENTIAL = 7,
+    PSS_OP_LOGLIK_GRAD_IFT = 8
 } pss_op;
 
 /* ---- problem description (host struct, read during the call only) ----- */
@@ -262,6 +263,30 @@ int pss_loglik(const pss_problem *p, const pss_gamma *g, const void *m_nom, cons
 int pss_loglik_grad(const pss_problem *p, const void *m_nom, const void *N_nom, const void *y,
                     const double *ll_bar, double *ll, double *grad, double *theta_bar, void *ws,
                     size_t ws_bytes, hipStream_t stream);
+
+/* Gradient of the pseudo-log-likelihood at the IPLS fixed point (Section
+   5.2, eq. implicity_function_theorem, Algorithm 4): the total derivative of
+   l(theta) = lhat(theta, n*(theta)) with respect to theta = (log q1, log q2,
+   log sigma), where n* = KS(n*, theta) is the nominal that IPLS converges to
+   (the caller passes it: m_nom, N_nom in the problem's form, e.g. after
+   enough pss_ipls_iterate passes).  The derivative of n* with respect to
+   theta solves the linear fixed point dn = (dKS/dn) dn + dKS/dtheta; each
+   of the n_iter iterations (>= 1; the error
+   contracts like the IPLS iteration itself) is one parallel covariance-form
+   pass (SLR, elements, filter scan, smoother scan) evaluated with three
+   tangents per number, the value held at n*.  A last tangent pass gives
+   the log-likelihood and its total derivative.  PSS_MODEL_CT_BEARINGS,
+   FP64, any linearisation.  The iteration converges where the IPLS
+   iteration itself converges at n* (the operator-norm condition of the
+   paper); where IPLS has no fixed point (it can cycle on long bearings-only
+   tracks started from the prior) the tangents grow without bound.  Outputs
+   (device double): ll [B]; grad [3][B] per sequence, component-major;
+   delta [B] (nullable): per sequence, the largest change of the nominal's
+   tangents in the last iteration relative to max(1, their size) -- a
+   convergence check.  ws: pss_workspace_size(PSS_OP_LOGLIK_GRAD_IFT). */
+int pss_loglik_grad_ift(const pss_problem *p, const void *m_nom, const void *N_nom,
+                        const void *y, int32_t n_iter, double *ll, double *grad, double *delta,
+                        void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* Sequential square-root comparator: the same n_iter passes as
    pss_ipls_iterate, but the filter and smoother run as the sequential

@@ -41,7 +41,9 @@ def build(jobs: int | None = None, verbose: bool = False, extra_flags=()) -> str
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or min(8, os.cpu_count() or 4)
     units = [(os.path.join(CSRC, "api.hip"), os.path.join(BUILD, "api.o"), []),
-             (os.path.join(CSRC, "persistent.hip"), os.path.join(BUILD, "persistent.o"), [])]
+             (os.path.join(CSRC, "persistent.hip"), os.path.join(BUILD, "persistent.o"), []),
+             (os.path.join(CSRC, "ift.hip"), os.path.join(BUILD, "ift.o"), []),
+             (os.path.join(CSRC, "ift_smoother.hip"), os.path.join(BUILD, "ift_smoother.o"), [])]
     for t in DTYPES:
         for nx, ny in DIMS:
             obj = os.path.join(BUILD, "inst_%s_%d_%d.o" % (t[0], nx, ny))

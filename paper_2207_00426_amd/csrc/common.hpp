@@ -109,6 +109,9 @@ struct RuleHost {
 // an invalid order or too many points
 bool rule_host(const pss_problem *p, int nx, RuleHost &r);
 
+// workspace of pss_loglik_grad_ift (defined in ift.hip)
+size_t ift_ws_size(const pss_problem *p);
+
 // one implementation per (dtype, nx, ny); defined in impl.hpp, explicitly
 // instantiated in inst.hip
 template <typename T, int NX, int NY>

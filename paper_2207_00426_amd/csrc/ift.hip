@@ -1,0 +1,400 @@
+// Gradient of the pseudo-log-likelihood at the IPLS fixed point (Section 5.2,
+// eq. implicity_function_theorem, Algorithm 4) for the coordinated-turn model.
+//
+// At the fixed point n* = KS(n*, theta) the total derivative of
+// l(theta) = lhat(theta, n*(theta)) needs dn*/dtheta, which solves the linear
+// fixed point dn = dKS/dn dn + dKS/dtheta.  Algorithm 4 iterates that
+// equation; here each iteration is one pass of the parallel covariance-form
+// smoother (SLR, filter elements, filter scan, smoother scan) run on numbers
+// that carry three tangents (Dual<double, 3>, one per theta component): with
+// the nominal's value held at n* and its tangents set to the previous
+// iterate, the pass's output tangents are exactly dKS/dn dn + dKS/dtheta.
+// The same scans, operators and storage layouts as the value pass are used,
+// instantiated for the dual type; every step keeps the O(log n) span.  The
+// covariance form is used (as Algorithm 4 states it): its operators are
+// smooth wherever they are defined, whereas the square-root form's Tria is
+// not differentiable where a factor loses rank (leaf elements have rank ny).
+// A final dual pass evaluates the log-likelihood terms, whose tangents are
+// the gradient.
+#include <math.h>
+
+#include <string>
+
+#include "ift.hpp"
+
+namespace pss {
+
+// value-only dual copy of a double array
+__global__ __launch_bounds__(256) void k_to_dual(const double *x, D *out, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        out[i] = D(x[i]);
+}
+
+// dual nominal from the caller's fixed point (m [5][T_x], N packed [15][T_x],
+// a factor when is_factor, else the covariance): the covariance form's
+// (m, P); tangents zeroed (value_only = 0) or kept (value_only = 1).  With
+// value_only, stat[s] receives the largest change of state s's tangents
+// since the previous call relative to max(1, their size), and prev keeps
+// the tangents for the next call ([20 values][3 tangents][T_x]).
+__global__ __launch_bounds__(128) void k_ift_nominal(int64_t T_x, const double *m,
+                                                     const double *N, int is_factor, D *nm, D *nP,
+                                                     int value_only, double *prev, double *stat)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= T_x)
+        return;
+    double dmax = 0.0, amax = 0.0;
+    auto track = [&](int q, const D &x) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int64_t at = ((int64_t)q * 3 + k) * T_x + s;
+            const double t = value_only ? x.d[k] : 0.0;
+            dmax = fmax(dmax, fabs(t - prev[at]));
+            amax = fmax(amax, fabs(t));
+            prev[at] = t;
+        }
+    };
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+        track(i, nm[(int64_t)i * T_x + s]);
+#pragma unroll
+    for (int q = 0; q < 15; ++q)
+        track(5 + q, nP[(int64_t)q * T_x + s]);
+    stat[s] = dmax / fmax(1.0, amax);
+    double L[5][5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+#pragma unroll
+        for (int j = 0; j < 5; ++j)
+            L[i][j] = j <= i ? N[(int64_t)tri_idx(i, j) * T_x + s] : 0.0;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        const double v = m[(int64_t)i * T_x + s];
+        if (value_only)
+            nm[(int64_t)i * T_x + s].v = v;
+        else
+            nm[(int64_t)i * T_x + s] = D(v);
+    }
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+#pragma unroll
+        for (int j = 0; j <= i; ++j) {
+            double v = L[i][j];
+            if (is_factor) {
+                v = 0.0;
+#pragma unroll
+                for (int t = 0; t <= j; ++t)
+                    v = fma(L[i][t], L[j][t], v);
+            }
+            const int64_t at = (int64_t)tri_idx(i, j) * T_x + s;
+            if (value_only)
+                nP[at].v = v;
+            else
+                nP[at] = D(v);
+        }
+}
+
+// per sequence: the largest stat over its states (one block per sequence)
+__global__ __launch_bounds__(256) void k_seq_max(const int64_t *y_off, const double *stat,
+                                                 double *out)
+{
+    __shared__ double red[256];
+    const int b = blockIdx.x;
+    const int64_t x0 = y_off[b] + b, x1 = y_off[b + 1] + b + 1;
+    double v = 0.0;
+    for (int64_t s = x0 + threadIdx.x; s < x1; s += blockDim.x)
+        v = fmax(v, stat[s]);
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        out[b] = red[0];
+}
+
+// covariance-form log-likelihood terms (as k_loglik_terms_cov) in dual
+// numbers: ell[0][t] the value, ell[1 + k][t] its tangent k
+__global__ __launch_bounds__(128) void k_loglik_terms_cov_dual(const int64_t *y_off, int B,
+                                                               int64_t T_y, GammaRef<D, 5, 2> gam,
+                                                               const double *y, MargRef<D, 5> filt,
+                                                               double *ell)
+{
+    constexpr int NX = 5, NY = 2;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T_y)
+        return;
+    const int b = find_seq(y_off, B, t, 0);
+    D F[NX][NX], c[NX], SL[NX][NX], H[NY][NX], d[NY], SO[NY][NY];
+    gam.load_trans(t, F, c, SL);
+    gam.load_obs(t, H, d, SO);
+    Marg<D, NX> f;
+    filt.load(t + b, f);
+    D mp[NX], P[NX][NX], FP[NX][NX], Pp[NX][NX], Om[NY][NY];
+    mv(F, f.m, mp);
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+        mp[i] += c[i];
+    sym_full(P, [&](int i, int j) { return f.N[i][j]; });
+    mm(F, P, FP);
+    gram_full(SL, Pp);
+    gram_full(SO, Om);
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+#pragma unroll
+        for (int j = 0; j < NX; ++j) {
+            D s = Pp[i][j];
+#pragma unroll
+            for (int k = 0; k < NX; ++k)
+                s = pfma(FP[i][k], F[j][k], s);
+            Pp[i][j] = s;
+        }
+    D HP[NY][NX], S[NY][NY], Y[NY][NY];
+    mm(H, Pp, HP);
+#pragma unroll
+    for (int a = 0; a < NY; ++a)
+#pragma unroll
+        for (int q = 0; q < NY; ++q) {
+            D s = Om[a][q];
+#pragma unroll
+            for (int j = 0; j < NX; ++j)
+                s = pfma(HP[a][j], H[q][j], s);
+            S[a][q] = s;
+        }
+    chol_lower(S, Y);
+    D Hm[NY], v[NY], u[NY];
+    mv(H, mp, Hm);
+#pragma unroll
+    for (int a = 0; a < NY; ++a)
+        v[a] = (D(y[a * T_y + t]) - Hm[a]) - d[a];
+    lsolve_lower(Y, v, u);
+    D l(-0.5 * NY * 1.8378770664093454835606594728112); // log(2 pi)
+#pragma unroll
+    for (int a = 0; a < NY; ++a)
+        l -= plog(Y[a][a]) + 0.5 * (u[a] * u[a]);
+    ell[t] = l.v;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        ell[(int64_t)(1 + k) * T_y + t] = l.d[k];
+}
+
+namespace {
+
+size_t scan_ws_bytes(const Ctx &c)
+{
+    Carver a{nullptr};
+    C::carve_scan<FSC>(a, c, C::filter_shape(c));
+    Carver b{nullptr};
+    C::carve_scan<SSC>(b, c, C::smoother_shape(c));
+    b.take<D>((size_t)Sizes<5>::selem * c.T_x); // smoother element stash
+    return std::max(std::max(a.used, b.used), seq_sum_bytes(c, 3));
+}
+
+IftBufs carve_ift(const Ctx &c, void *base)
+{
+    Carver cv{static_cast<char *>(base)};
+    IftBufs w;
+    w.nm = cv.take<D>((size_t)5 * c.T_x);
+    w.nP = cv.take<D>((size_t)15 * c.T_x);
+    w.mf = cv.take<D>((size_t)5 * c.T_x);
+    w.Pf = cv.take<D>((size_t)15 * c.T_x);
+    w.yd = cv.take<D>((size_t)2 * c.T_y);
+    w.m0d = cv.take<D>(5);
+    w.N0d = cv.take<D>(15);
+    w.gam = C::carve_gamma(cv, c.T_y);
+    D *fel = cv.take<D>((size_t)Sizes<5>::felem * c.T_y);
+    w.fel = C::felem_ref(fel, c.T_y);
+    w.ell = cv.take<double>((size_t)4 * c.T_y);
+    w.prev = cv.take<double>((size_t)60 * c.T_x);
+    w.stat = cv.take<double>((size_t)c.T_x);
+    w.scan_ws = cv.base ? cv.base + cv.used : nullptr;
+    w.used = cv.used + scan_ws_bytes(c);
+    return w;
+}
+
+int ift_validate(const pss_problem *p)
+{
+    int rc = pss_validate(p);
+    if (rc)
+        return rc;
+    if (p->model != PSS_MODEL_CT_BEARINGS) {
+        set_error("loglik_grad_ift: theta is defined for the coordinated-turn model");
+        return PSS_EUNSUPPORTED;
+    }
+    if (p->dtype != PSS_F64) {
+        set_error("loglik_grad_ift: built for FP64");
+        return PSS_EUNSUPPORTED;
+    }
+    return PSS_OK;
+}
+
+int launch_slr(const Ctx &c, const IftBufs &w)
+{
+    const CTHost h = ct_host(c.p);
+    CTParams<D> P;
+    P.dt = D(h.dt);
+    P.s1x = D(h.s1x);
+    P.s1y = D(h.s1y);
+    P.s2x = D(h.s2x);
+    P.s2y = D(h.s2y);
+    // theta = (log q1, log q2, log sigma): the q1 part of the factor scales
+    // as sqrt(q1), the q2 part as sqrt(q2), sigma as e^theta3
+    P.sigma = D(h.sigma);
+    P.sigma.d[2] = h.sigma;
+    for (int i = 0; i < 5; ++i)
+        for (int j = 0; j < 5; ++j) {
+            P.LQ[i][j] = D(h.LQ[i][j]);
+            P.LQ[i][j].d[0] = 0.5 * h.L1[i][j];
+            P.LQ[i][j].d[1] = 0.5 * h.L2[i][j];
+        }
+    const int tb = 128;
+    const dim3 grid((unsigned)((c.T_x + tb - 1) / tb));
+    const int lin = c.p->linearization;
+    KTime kt(c.s, "ift_slr", "", 0);
+    if (lin == PSS_LIN_CUBATURE || lin == PSS_LIN_TAYLOR) {
+        hipLaunchKernelGGL((k_slr_ct<D>), grid, dim3(tb), 0, c.s, c.p->y_off, c.B, c.T_x, c.T_y,
+                           P, C::marg_ref2(w.nm, w.nP, c.T_x), w.yd, C::gamma_ref(&w.gam, c.T_y),
+                           lin == PSS_LIN_TAYLOR ? 1 : 0, 1);
+    } else {
+        RuleSpec<double> Rd;
+        if (!rule_spec(c.p, 5, Rd))
+            return PSS_EINVAL;
+        RuleSpec<D> R;
+        R.kind = Rd.kind;
+        R.np = Rd.np;
+        R.p = Rd.p;
+        R.w0 = D(Rd.w0);
+        R.wi = D(Rd.wi);
+        R.spread = D(Rd.spread);
+        for (int q = 0; q < kMaxGH; ++q) {
+            R.gx[q] = D(Rd.gx[q]);
+            R.gw[q] = D(Rd.gw[q]);
+        }
+        hipLaunchKernelGGL((k_slr_ct_rule<D>), grid, dim3(tb), 0, c.s, c.p->y_off, c.B, c.T_x,
+                           c.T_y, P, C::marg_ref2(w.nm, w.nP, c.T_x), w.yd,
+                           C::gamma_ref(&w.gam, c.T_y), R, 1);
+    }
+    return hip_check(hipGetLastError(), "ift slr launch");
+}
+
+int launch_felem(const Ctx &c, const IftBufs &w)
+{
+    const ScanShape sh = C::filter_shape(c);
+    const int tb = 128;
+    KTime kt(c.s, "ift_filter_elements", "", 0);
+    hipLaunchKernelGGL((k_filter_elements<D, 5, 2, true>), dim3((unsigned)((c.T_y + tb - 1) / tb)),
+                       dim3(tb), 0, c.s, c.p->y_off, c.B, c.T_y, C::gamma_ref(&w.gam, c.T_y), w.yd,
+                       w.m0d, w.N0d, w.fel, sh.T[0], sh.E[0]);
+    return hip_check(hipGetLastError(), "ift filter elements launch");
+}
+
+int run_fscan(const Ctx &c, const IftBufs &w)
+{
+    const ScanShape sh = C::filter_shape(c);
+    Carver cv{static_cast<char *>(w.scan_ws)};
+    auto sw = C::carve_scan<FSC>(cv, c, sh);
+    FiltDst<D, 5> dst{C::marg_ref2(w.mf, w.Pf, c.T_x), c.p->y_off};
+    StartPreCov<D, 5> st{w.m0d, w.N0d};
+    RefSrc<FSC, FElemRef<D, 5>, true> src{w.fel};
+    return C::run_scan<FSC>(c, sh, sw, 0, src, dst, st, &C::felem_ref);
+}
+
+} // namespace
+
+size_t ift_ws_size(const pss_problem *p)
+{
+    Ctx c;
+    c.p = p;
+    c.B = p->B;
+    c.T_y = p->y_off_host[p->B];
+    c.T_x = c.T_y + p->B;
+    c.s = nullptr;
+    return carve_ift(c, nullptr).used;
+}
+
+} // namespace pss
+
+using namespace pss;
+
+extern "C" int pss_loglik_grad_ift(const pss_problem *p, const void *m_nom, const void *N_nom,
+                                   const void *y, int32_t n_iter, double *ll, double *grad,
+                                   double *delta, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    try {
+        int rc = ift_validate(p);
+        if (rc)
+            return rc;
+        if (!m_nom || !N_nom || !y || !ll || !grad || n_iter < 1) {
+            set_error("loglik_grad_ift: null buffer or n_iter < 1");
+            return PSS_EINVAL;
+        }
+        Ctx c;
+        c.p = p;
+        c.B = p->B;
+        c.T_y = p->y_off_host[p->B];
+        c.T_x = c.T_y + p->B;
+        c.s = stream;
+        const size_t need = ift_ws_size(p);
+        if (!ws || ws_bytes < need) {
+            set_error("workspace too small: need " + std::to_string(need) + " bytes");
+            return PSS_EWORKSPACE;
+        }
+        const IftBufs w = carve_ift(c, ws);
+        const int is_factor = p->form == PSS_FORM_SQRT ? 1 : 0;
+        const dim3 blk(256);
+        hipLaunchKernelGGL(k_to_dual, dim3((unsigned)((2 * c.T_y + 255) / 256)), blk, 0, stream,
+                           static_cast<const double *>(y), w.yd, 2 * c.T_y);
+        hipLaunchKernelGGL(k_to_dual, dim3(1), blk, 0, stream, static_cast<const double *>(p->m0),
+                           w.m0d, (int64_t)5);
+        hipLaunchKernelGGL(k_to_dual, dim3(1), blk, 0, stream, static_cast<const double *>(p->N0),
+                           w.N0d, (int64_t)15);
+        const dim3 gx((unsigned)((c.T_x + 127) / 128));
+        const double *mn = static_cast<const double *>(m_nom);
+        const double *Nn = static_cast<const double *>(N_nom);
+        hipLaunchKernelGGL(k_ift_nominal, gx, dim3(128), 0, stream, c.T_x, mn, Nn, is_factor,
+                           w.nm, w.nP, 0, w.prev, w.stat);
+        if ((rc = hip_check(hipGetLastError(), "ift setup launch")))
+            return rc;
+        for (int it = 0; it < n_iter; ++it) {
+            if ((rc = launch_slr(c, w)) || (rc = launch_felem(c, w)) || (rc = run_fscan(c, w)) ||
+                (rc = run_sscan(c, w)))
+                return rc;
+            // hold the value at the fixed point; keep the new tangents
+            hipLaunchKernelGGL(k_ift_nominal, gx, dim3(128), 0, stream, c.T_x, mn, Nn, is_factor,
+                               w.nm, w.nP, 1, w.prev, w.stat);
+            if ((rc = hip_check(hipGetLastError(), "ift nominal launch")))
+                return rc;
+        }
+        if (delta) {
+            hipLaunchKernelGGL(k_seq_max, dim3((unsigned)c.B), dim3(256), 0, stream, p->y_off,
+                               w.stat, delta);
+            if ((rc = hip_check(hipGetLastError(), "ift delta launch")))
+                return rc;
+        }
+        // log-likelihood of the linearisation at (n*, dn*/dtheta)
+        if ((rc = launch_slr(c, w)) || (rc = launch_felem(c, w)) || (rc = run_fscan(c, w)))
+            return rc;
+        {
+            KTime kt(stream, "ift_loglik_terms", "", 0);
+            hipLaunchKernelGGL(k_loglik_terms_cov_dual, dim3((unsigned)((c.T_y + 127) / 128)),
+                               dim3(128), 0, stream, p->y_off, c.B, c.T_y,
+                               C::gamma_ref(&w.gam, c.T_y), static_cast<const double *>(y),
+                               C::marg_ref2(w.mf, w.Pf, c.T_x), w.ell);
+            if ((rc = hip_check(hipGetLastError(), "ift loglik launch")))
+                return rc;
+        }
+        if ((rc = launch_seq_sum(c, 1, w.ell, c.T_y, ll, w.scan_ws)))
+            return rc;
+        return launch_seq_sum(c, 3, w.ell + c.T_y, c.T_y, grad, w.scan_ws);
+    } catch (const std::exception &ex) {
+        set_error(ex.what());
+        return PSS_EINVAL;
+    } catch (...) {
+        set_error("unknown exception in loglik_grad_ift");
+        return PSS_EINVAL;
+    }
+}

@@ -4,19 +4,21 @@ theta = (log q1, log q2, log sigma) is fitted by maximising the pseudo
 log-likelihood of Section 5.1, summed over a batch.  Every objective
 evaluation first recomputes the nominal trajectory by IPLS (Algorithm 3) at
 the current theta, so the objective is the likelihood of the model
-linearised where IPLS puts it for that theta; its gradient is the library's
-frozen-nominal one (the nominal's own dependence on theta through the
-iterated linearisation is not differentiated), which makes it an
-approximation of the objective's derivative.  Holding one nominal fixed over
-many steps instead is not a usable objective: linearised at a poor starting
-theta it can prefer parameters far from the generating ones.
+linearised where IPLS puts it for that theta.  Two gradients:
 
-Because the gradient is approximate, the optimiser is a limited-memory BFGS
-with an Armijo backtracking line search (which needs only a descent
-direction, not the curvature condition of a Wolfe search) and a cap on the
-step length.  Only argument marshalling happens here; every pass is a
-library call, and the gradient comes through the autograd binding
-(pss.LogLik).
+* "frozen": the library's frozen-nominal one (the nominal's own dependence
+  on theta through the iterated linearisation is not differentiated), an
+  approximation of the objective's derivative (pss.LogLik);
+* "fixed_point": the total derivative at the IPLS fixed point (Algorithm 4,
+  pss_loglik_grad_ift through pss.LogLikFixedPoint), exact for the
+  objective once IPLS has converged.
+
+Holding one nominal fixed over many steps instead is not a usable objective:
+linearised at a poor starting theta it can prefer parameters far from the
+generating ones.  The optimiser is a limited-memory BFGS with an Armijo
+backtracking line search (which needs only a descent direction, so it also
+works with the approximate gradient) and a cap on the step length.  Only
+argument marshalling happens here; every pass is a library call.
 """
 from __future__ import annotations
 
@@ -100,11 +102,15 @@ def lbfgs(fg, x0, n_steps=50, history=10, max_step=1.0, c1=1e-4, max_backtracks=
     return x, f, trace
 
 
-def fit_theta_lbfgs(batch, y, theta0, n_steps=50, passes=10, history=10, max_step=1.0):
+def fit_theta_lbfgs(batch, y, theta0, n_steps=50, passes=10, history=10, max_step=1.0,
+                    gradient="frozen", ift_iter=30):
     """Returns a dict: final theta, the objective (mean negative
     log-likelihood per step) at the start and end and after every step, the
     number of L-BFGS iterations and objective evaluations, and timings (IPLS
-    and loglik + gradient separately)."""
+    and loglik + gradient separately).  gradient: "frozen" or "fixed_point"
+    (ift_iter tangent iterations; FP64 only)."""
+    if gradient not in ("frozen", "fixed_point"):
+        raise ValueError(gradient)
     pss._require_gpu()
     n_total = float(batch.y_off_host[-1])
     times = {"ipls": 0.0, "eval": 0.0}
@@ -117,7 +123,10 @@ def fit_theta_lbfgs(batch, y, theta0, n_steps=50, passes=10, history=10, max_ste
         t1 = time.perf_counter()
         # objective and gradient through the autograd binding
         tt = torch.tensor(np.asarray(th, dtype=np.float64), requires_grad=True)
-        loss = -pss.LogLik.apply(tt, batch, y, m_nom, N_nom) / n_total
+        if gradient == "frozen":
+            loss = -pss.LogLik.apply(tt, batch, y, m_nom, N_nom) / n_total
+        else:
+            loss = -pss.LogLikFixedPoint.apply(tt, batch, y, m_nom, N_nom, ift_iter) / n_total
         loss.backward()
         f = float(loss.detach())
         g = tt.grad.numpy().copy()

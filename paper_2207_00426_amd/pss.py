@@ -31,7 +31,7 @@ LINEARIZATIONS = {"cubature": LIN_CUBATURE, "taylor": LIN_TAYLOR, "unscented": L
 FORM_SQRT, FORM_COV = 0, 1
 FORMS = {"sqrt": FORM_SQRT, "cov": FORM_COV}
 OPS = dict(slr=0, filter_elements=1, filter_scan=2, smoother_scan=3, ipls=4, loglik=5,
-           loglik_grad=6, sequential=7)
+           loglik_grad=6, sequential=7, loglik_grad_ift=8)
 STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported", -3: "workspace too small",
           -4: "HIP error"}
 EXPORTS = ["pss_workspace_size", "pss_slr_linearize", "pss_sqrt_filter_elements",
@@ -39,7 +39,7 @@ EXPORTS = ["pss_workspace_size", "pss_slr_linearize", "pss_sqrt_filter_elements"
            "pss_loglik_grad", "pss_sequential_smoother", "pss_validate", "pss_last_error",
            "pss_version", "pss_batched_workspace_size", "pss_ipls_batched",
            "pss_autotune_workspace_size", "pss_autotune", "pss_kernel_timing",
-           "pss_kernel_times"]
+           "pss_kernel_times", "pss_loglik_grad_ift"]
 
 
 class PssError(RuntimeError):
@@ -106,6 +106,7 @@ def lib():
         L.pss_loglik_grad.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
         L.pss_sequential_smoother.argtypes = [P, ctypes.POINTER(GammaC), vp, i32, vp, vp, vp, vp,
                                               vp, sz, vp]
+        L.pss_loglik_grad_ift.argtypes = [P, vp, vp, vp, i32, vp, vp, vp, vp, sz, vp]
         G = ctypes.POINTER(GroupC)
         L.pss_batched_workspace_size.restype = sz
         L.pss_batched_workspace_size.argtypes = [G, i32]
@@ -121,7 +122,8 @@ def lib():
         L.pss_kernel_times.restype = ctypes.c_int64
         for name in ("pss_slr_linearize", "pss_sqrt_filter_elements", "pss_sqrt_filter_scan",
                      "pss_sqrt_smoother_scan", "pss_ipls_iterate", "pss_loglik",
-                     "pss_loglik_grad", "pss_sequential_smoother", "pss_validate"):
+                     "pss_loglik_grad", "pss_sequential_smoother", "pss_validate",
+                     "pss_loglik_grad_ift"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -510,6 +512,48 @@ class LogLik(torch.autograd.Function):
             device=b2.device, dtype=torch.float64)
         _, _, tb = loglik_grad(b2, m_nom, N_nom, y, ll_bar=w)
         return tb.to(device=theta.device, dtype=theta.dtype), None, None, None, None
+
+
+def loglik_grad_ift(batch, m_nom, N_nom, y, n_iter=30, ws=None, with_delta=False):
+    """(ll [B], grad [3, B][, delta [B]]): the total derivative of the
+    pseudo-log-likelihood at the IPLS fixed point (m_nom, N_nom) (Algorithm
+    4), FP64 CT only; delta is the per-sequence tangent change of the last
+    iteration (a convergence check)."""
+    _require_gpu()
+    dev = batch.device
+    ll = torch.empty(batch.B, dtype=torch.float64, device=dev)
+    grad = torch.empty((3, batch.B), dtype=torch.float64, device=dev)
+    delta = torch.empty(batch.B, dtype=torch.float64, device=dev) if with_delta else None
+    if ws is None:
+        ws, n = batch.workspace("loglik_grad_ift")
+    else:
+        n = ws.numel()
+    p = batch.struct()
+    _check(lib().pss_loglik_grad_ift(ctypes.byref(p), _ptr(m_nom), _ptr(N_nom), _ptr(y),
+                                     int(n_iter), _ptr(ll), _ptr(grad), _ptr(delta), _ptr(ws), n,
+                                     _stream()))
+    return (ll, grad, delta) if with_delta else (ll, grad)
+
+
+class LogLikFixedPoint(torch.autograd.Function):
+    """sum_b l_b(theta) at the IPLS fixed point (m_nom, N_nom) computed for
+    theta; backward returns the total derivative (Algorithm 4) through
+    pss_loglik_grad_ift."""
+
+    @staticmethod
+    def forward(ctx, theta, batch, y, m_nom, N_nom, n_iter=30):
+        th = tuple(float(v) for v in theta.detach().cpu().tolist())
+        b2 = _with_theta(batch, th)
+        ll, grad = loglik_grad_ift(b2, m_nom, N_nom, y, n_iter=n_iter)
+        ctx.save_for_backward(theta)
+        ctx.grad = grad.sum(dim=1)
+        return ll.sum().to(theta.dtype)
+
+    @staticmethod
+    def backward(ctx, g):
+        (theta,) = ctx.saved_tensors
+        tb = ctx.grad * g.to(device=ctx.grad.device, dtype=torch.float64)
+        return tb.to(device=theta.device, dtype=theta.dtype), None, None, None, None, None
 
 
 def _with_theta(batch, theta):
