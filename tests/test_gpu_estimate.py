@@ -27,3 +27,26 @@ def test_lbfgs_improves_the_objective_and_sigma(dtype):
     assert fit["loss_final"] < fit["loss_start"] - 0.1
     # the bearing noise is pinned down well by the data
     assert abs(th[2] - th_true[2]) < 0.1 < abs(th0[2] - th_true[2])
+
+
+def test_lbfgs_with_the_fixed_point_gradient_reaches_a_stationary_point():
+    # one sequence whose IPLS converges from the prior: with the gradient at
+    # the fixed point (Algorithm 4) the objective's true gradient vanishes at
+    # the end; the frozen-nominal gradient stops short of that
+    w = wl.ct_single(1000, seed=1)
+    b = pss.Batch.ct(w.y_off, w.model, dtype=torch.float64, device="cuda")
+    y = pss.to_soa(w.y, torch.float64, "cuda")
+    th0 = np.array(w.model.theta) + 0.5
+    ends = {}
+    for grad in ("fixed_point", "frozen"):
+        fit = estimate.fit_theta_lbfgs(b, y, th0, n_steps=40, passes=40, gradient=grad)
+        assert fit["loss_final"] < fit["loss_start"]
+        b2 = pss._with_theta(b, fit["theta"])
+        m, N = pss.ipls_iterate(b2, y, 40)
+        _, g, delta = pss.loglik_grad_ift(b2, m, N, y, n_iter=30, with_delta=True)
+        torch.cuda.synchronize()
+        assert float(delta[0]) < 1e-8
+        ends[grad] = (float(g.abs().max()) / 1000, fit["loss_final"])
+    print("true gradient at the end (fixed point, frozen):", ends)
+    assert ends["fixed_point"][0] < 1e-8
+    assert ends["fixed_point"][1] <= ends["frozen"][1] + 1e-9
