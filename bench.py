@@ -390,7 +390,7 @@ def bench_divergence(stream, dev, sets=15, passes=20, lengths=(100, 1000, 4000, 
     return {"sets": sets, "passes": passes, "nonfinite_share": out}
 
 
-def bench_ricker(stream, dev, lengths=(10 ** 3, 10 ** 4, 10 ** 5), M=100, seed=8):
+def bench_ricker(stream, dev, lengths=(10 ** 2, 10 ** 3, 10 ** 4, 10 ** 5), M=100, seed=8):
     """The Ricker-Poisson experiment of Section 6.1 on one sequence per
     length: M = 100 passes of the iterated extended (Taylor) and cubature
     smoothers, covariance and square-root forms, FP64, parallel; the
@@ -410,10 +410,27 @@ def bench_ricker(stream, dev, lengths=(10 ** 3, 10 ** 4, 10 ** 5), M=100, seed=8
                 m0, N0 = b.prior_nominal()
                 mm, NN = m0.clone(), N0.clone()
                 wi, _ = b.workspace("ipls")
-                t_par = timed(stream, lambda: (mm.copy_(m0), NN.copy_(N0),
-                                               pss.ipls_iterate(b, yd, M, mm, NN, ws=wi)), 2)
+
+                def run():
+                    mm.copy_(m0)
+                    NN.copy_(N0)
+                    pss.ipls_iterate(b, yd, M, mm, NN, ws=wi)
+
+                t_par = timed(stream, run, 2)
+                eager = mm.clone()
+                # the same 100 passes captured in one HIP graph (replay checked
+                # bitwise against the eager run)
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g, stream=stream):
+                    run()
+                g.replay()
+                torch.cuda.synchronize()
+                assert torch.equal(mm.view(torch.int64), eager.view(torch.int64))
+                t_graph = timed(stream, g.replay, 3)
                 r = {"parallel_ms_M%d" % M: round(t_par, 3),
-                     "parallel_ms_per_pass": round(t_par / M, 4)}
+                     "parallel_ms_per_pass": round(t_par / M, 4),
+                     "graph_ms_M%d" % M: round(t_graph, 3),
+                     "graph_ms_per_pass": round(t_graph / M, 4)}
                 if form == "sqrt":
                     wsq, _ = b.workspace("sequential")
                     t_seq = timed(stream, lambda: (mm.copy_(m0), NN.copy_(N0),
@@ -422,8 +439,8 @@ def bench_ricker(stream, dev, lengths=(10 ** 3, 10 ** 4, 10 ** 5), M=100, seed=8
                     r["sequential_ms_per_pass"] = round(t_seq, 4)
                     r["speedup_per_pass"] = round(t_seq / (t_par / M), 2)
                 row["%s_%s" % (lin, form)] = r
-                log("ricker n=%d %s %s: %d passes %.3f ms%s" % (
-                    n, lin, form, M, t_par,
+                log("ricker n=%d %s %s: %d passes %.3f ms (graph %.3f ms)%s" % (
+                    n, lin, form, M, t_par, t_graph,
                     "" if form == "cov" else ", sequential %.3f ms/pass" % r[
                         "sequential_ms_per_pass"]))
         out["n%d" % n] = row
