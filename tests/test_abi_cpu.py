@@ -194,3 +194,23 @@ def test_ricker_model_and_sigma_point_rules_are_validated(L):
         assert L.pss_batched_workspace_size(ctypes.byref(g), 1) == 0
         rc = L.pss_ipls_batched(ctypes.byref(g), 1, 1, None, None, 0, None)
         assert rc == -2, pss.last_error()
+
+
+def test_fixed_point_gradient_is_validated_before_any_hip_call(L):
+    ct = dict(model=pss.MODEL_CT, nx=5, ny=2, m0=np.zeros(5), N0=np.eye(5), dt=0.01)
+    b = _cpu_batch(**ct)
+    assert pss.workspace_size(b, "loglik_grad_ift") > pss.workspace_size(b, "loglik_grad")
+    d = ctypes.c_void_p(8)
+    # FP32 and non-CT models are refused
+    for bad in (_cpu_batch(dtype=torch.float32, **ct), _ricker_cpu(), _cpu_batch()):
+        p = bad.struct()
+        assert pss.workspace_size(bad, "loglik_grad_ift") == 0
+        rc = L.pss_loglik_grad_ift(ctypes.byref(p), d, d, d, 5, d, d, None, d, 1 << 40, None)
+        assert rc == -2, pss.last_error()
+    p = b.struct()
+    # n_iter >= 1, non-null buffers, a large enough workspace
+    assert L.pss_loglik_grad_ift(ctypes.byref(p), d, d, d, 0, d, d, None, d, 1 << 40, None) == -1
+    assert L.pss_loglik_grad_ift(ctypes.byref(p), None, d, d, 5, d, d, None, d, 1 << 40,
+                                 None) == -1
+    assert L.pss_loglik_grad_ift(ctypes.byref(p), d, d, d, 5, d, d, None, d, 16, None) == -3
+    assert "workspace" in pss.last_error()
