@@ -113,7 +113,8 @@ typedef enum {
        library's method */
     PSS_FORM_SQRT = 0,
     /* standard covariance form (left columns of Tables 1-5), for comparison;
-       honoured by pss_slr_linearize, pss_ipls_iterate and pss_loglik only.
+       honoured by pss_slr_linearize, pss_ipls_iterate, pss_loglik and
+       pss_sequential_smoother only.
        The "N" buffers of marginals, the nominal's included (on input and on
        output), then hold the packed lower triangle of the covariance P, not a
        factor; the cubature SLR factors P itself (Cholesky).  The prior is
@@ -288,10 +289,12 @@ int pss_loglik_grad_ift(const pss_problem *p, const void *m_nom, const void *N_n
                         const void *y, int32_t n_iter, double *ll, double *grad, double *delta,
                         void *ws, size_t ws_bytes, hipStream_t stream);
 
-/* Sequential square-root comparator: the same n_iter passes as
-   pss_ipls_iterate, but the filter and smoother run as the sequential
-   recursions (one thread per sequence walks k = 1..n then n-1..0); only the
-   SLR is parallel.  Same arguments and outputs as pss_ipls_iterate.
+/* Sequential comparator: the same n_iter passes as pss_ipls_iterate, but
+   the filter and smoother run as the sequential recursions (one thread per
+   sequence walks k = 1..n then n-1..0); only the SLR is parallel.  The
+   square-root recursions, or with PSS_FORM_COV the standard Kalman filter
+   and RTS smoother (marginals then hold P, as in pss_ipls_iterate).  Same
+   arguments and outputs as pss_ipls_iterate.
    ws: pss_workspace_size(PSS_OP_SEQUENTIAL). */
 int pss_sequential_smoother(const pss_problem *p, const pss_gamma *g, const void *y,
                             int32_t n_iter, void *m_nom, void *N_nom, void *m_f, void *N_f,

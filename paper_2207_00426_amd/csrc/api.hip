@@ -790,8 +790,6 @@ int pss_sequential_smoother(const pss_problem *p, const pss_gamma *g, const void
         int rc = validate(p);
         if (rc)
             return rc;
-        if ((rc = need_sqrt(p, "sequential_smoother")))
-            return rc;
         if (!y || !m_nom || !N_nom || n_iter < 0 || ((m_f == nullptr) != (N_f == nullptr))) {
             set_error("sequential_smoother: null buffer or negative n_iter");
             return PSS_EINVAL;

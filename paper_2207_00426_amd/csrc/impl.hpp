@@ -549,11 +549,18 @@ struct Core {
             if (nonlinear(c) && (rc = slr(c, m_nom, N_nom, y, &gw)))
                 break;
             const int tb = 64;
+            const dim3 grid((unsigned)((c.B + tb - 1) / tb));
             KTime kt(c.s, "sequential", "", 0);
-            hipLaunchKernelGGL((k_sequential<T, NX, NY>), dim3((unsigned)((c.B + tb - 1) / tb)),
-                               dim3(tb), 0, c.s, c.p->y_off, c.B, c.T_y, gamma_ref(g, c.T_y),
-                               cptr<T>(y), cptr<T>(c.p->m0), cptr<T>(c.p->N0),
-                               marg_ref2(mf, Nf, c.T_x), marg_ref2(m_nom, N_nom, c.T_x));
+            if (c.p->form == PSS_FORM_COV)
+                hipLaunchKernelGGL((k_sequential_cov<T, NX, NY>), grid, dim3(tb), 0, c.s,
+                                   c.p->y_off, c.B, c.T_y, gamma_ref(g, c.T_y), cptr<T>(y),
+                                   cptr<T>(c.p->m0), cptr<T>(c.p->N0), marg_ref2(mf, Nf, c.T_x),
+                                   marg_ref2(m_nom, N_nom, c.T_x));
+            else
+                hipLaunchKernelGGL((k_sequential<T, NX, NY>), grid, dim3(tb), 0, c.s,
+                                   c.p->y_off, c.B, c.T_y, gamma_ref(g, c.T_y), cptr<T>(y),
+                                   cptr<T>(c.p->m0), cptr<T>(c.p->N0), marg_ref2(mf, Nf, c.T_x),
+                                   marg_ref2(m_nom, N_nom, c.T_x));
             rc = hip_check(hipGetLastError(), "sequential launch");
         }
         return rc;

@@ -1134,6 +1134,133 @@ __global__ __launch_bounds__(64) void k_sequential(const int64_t *y_off, int B, 
     }
 }
 
+// sequential covariance-form comparator (the standard Kalman filter and RTS
+// smoother, one thread per sequence): predict mp = F m + c,
+// Pp = F P F^T + Lambda; update with S = H Pp H^T + Omega = Y Y^T,
+// K = Pp H^T S^{-1}, m = mp + K (y - H mp - d), P = Pp - K H Pp (symmetrised);
+// the backward pass applies the smoother element of Table 4 (standard
+// column), which is the RTS step.  Marginals hold (m, packed P).
+template <typename T, int NX, int NY>
+__global__ __launch_bounds__(64) void k_sequential_cov(const int64_t *y_off, int B, int64_t T_y,
+                                                       GammaRef<T, NX, NY> gam, const T *y,
+                                                       const T *m0, const T *N0,
+                                                       MargRef<T, NX> filt, MargRef<T, NX> smooth)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B)
+        return;
+    const int64_t a = y_off[b], n = y_off[b + 1] - a, x0 = a + b;
+    T m[NX], P[NX][NX];
+    {
+        T L0[NX][NX];
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+            m[i] = m0[i];
+#pragma unroll
+            for (int j = 0; j < NX; ++j)
+                L0[i][j] = j <= i ? N0[tri_idx(i, j)] : T(0);
+        }
+        gram_full(L0, P);
+    }
+    Marg<T, NX> f;
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+        f.m[i] = m[i];
+#pragma unroll
+        for (int j = 0; j <= i; ++j)
+            f.N[i][j] = P[i][j];
+    }
+    filt.store(x0, f);
+    for (int64_t k = 0; k < n; ++k) {
+        T F[NX][NX], c[NX], SL[NX][NX], H[NY][NX], d[NY], SO[NY][NY];
+        gam.load_trans(a + k, F, c, SL);
+        gam.load_obs(a + k, H, d, SO);
+        T mp[NX], FP[NX][NX], Pp[NX][NX];
+        mv(F, m, mp);
+#pragma unroll
+        for (int i = 0; i < NX; ++i)
+            mp[i] += c[i];
+        mm(F, P, FP);
+        gram_full(SL, Pp);
+#pragma unroll
+        for (int i = 0; i < NX; ++i)
+#pragma unroll
+            for (int j = 0; j < NX; ++j) {
+                T s = Pp[i][j];
+#pragma unroll
+                for (int t = 0; t < NX; ++t)
+                    s = pfma(FP[i][t], F[j][t], s);
+                Pp[i][j] = s;
+            }
+        T HP[NY][NX], S[NY][NY], Y[NY][NY], PHt[NX][NY], K[NX][NY];
+        mm(H, Pp, HP);
+        gram_full(SO, S);
+#pragma unroll
+        for (int q = 0; q < NY; ++q)
+#pragma unroll
+            for (int r = 0; r < NY; ++r) {
+                T s = S[q][r];
+#pragma unroll
+                for (int t = 0; t < NX; ++t)
+                    s = pfma(HP[q][t], H[r][t], s);
+                S[q][r] = s;
+            }
+        chol_lower(S, Y);
+#pragma unroll
+        for (int i = 0; i < NX; ++i)
+#pragma unroll
+            for (int q = 0; q < NY; ++q)
+                PHt[i][q] = HP[q][i];
+        rsolve_spd(PHt, Y, K);
+        T Hm[NY], v[NY];
+        mv(H, mp, Hm);
+#pragma unroll
+        for (int q = 0; q < NY; ++q)
+            v[q] = y[q * T_y + a + k] - Hm[q] - d[q];
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+            T s = mp[i];
+#pragma unroll
+            for (int q = 0; q < NY; ++q)
+                s = pfma(K[i][q], v[q], s);
+            m[i] = s;
+        }
+#pragma unroll
+        for (int i = 0; i < NX; ++i)
+#pragma unroll
+            for (int j = 0; j <= i; ++j) {
+                T s = Pp[i][j], t = Pp[i][j];
+#pragma unroll
+                for (int q = 0; q < NY; ++q) {
+                    s = pfma(-K[i][q], HP[q][j], s);
+                    t = pfma(-K[j][q], HP[q][i], t);
+                }
+                P[i][j] = P[j][i] = T(0.5) * (s + t);
+            }
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+            f.m[i] = m[i];
+#pragma unroll
+            for (int j = 0; j <= i; ++j)
+                f.N[i][j] = P[i][j];
+        }
+        filt.store(x0 + k + 1, f);
+    }
+    Marg<T, NX> s = f;
+    smooth.store(x0 + n, s);
+    for (int64_t k = n - 1; k >= 0; --k) {
+        T F[NX][NX], c[NX], SL[NX][NX];
+        gam.load_trans(a + k, F, c, SL);
+        Marg<T, NX> fk, o;
+        filt.load(x0 + k, fk);
+        SElem<T, NX> e;
+        smoother_element_cov(F, c, SL, fk, e);
+        smoother_apply_cov_v<T, NX>(SRegV<T, NX>{&e}, s, o);
+        s = o;
+        smooth.store(x0 + k, s);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // coordinated-turn model kernels
 // ---------------------------------------------------------------------------

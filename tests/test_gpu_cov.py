@@ -89,3 +89,25 @@ def test_fp32_square_root_form_does_not_diverge_where_covariance_form_does():
           % (bad["sqrt"], bad["cov"]))
     assert bad["sqrt"] == 0
     assert bad["cov"] > 0
+
+
+@pytest.mark.parametrize("tag", ["f64", "f32"])
+def test_sequential_covariance_comparator_ct(tag):
+    # the standard Kalman filter / RTS smoother (one thread per sequence) on
+    # the CT model, ragged batch, against the oracle's pass
+    rng = np.random.default_rng(41)
+    ct = wl.CTModel()
+    lens = [300, 1, 800]
+    ys = [wl.simulate_ct(n, rng, ct)[1] for n in lens]
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    dt = torch.float64 if tag == "f64" else torch.float32
+    b = pss.Batch.ct(off, ct, dtype=dt, device=DEV, form="cov")
+    m, P = b.prior_nominal()
+    pss.sequential_smoother(b, pss.to_soa(np.concatenate(ys), dt, DEV), 1, m, P)
+    torch.cuda.synchronize()
+    ma, Pa = _cov_from_soa(m.double(), P.double(), 5)
+    for s, y in enumerate(ys):
+        r = orc.ct_ipls(orc.ct_params(), ct.m0, np.eye(5), y, 1)
+        a, z = off[s] + s, off[s + 1] + s + 1
+        em, eP = _errs(ma[a:z], Pa[a:z], r["ms"], r["Ns"])
+        assert em < par.TOL[tag]["m"] and eP < par.TOL[tag]["P"], (s, em, eP)

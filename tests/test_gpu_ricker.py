@@ -166,19 +166,25 @@ def test_ricker_loglik(form, lin, kw):
         assert par.ll_err(float(ll[s]), want) < par.TOL["f64"]["ll"], (s, float(ll[s]), want)
 
 
-def test_ricker_sequential_comparator():
+@pytest.mark.parametrize("form", ["sqrt", "cov"])
+@pytest.mark.parametrize("lin", ["taylor", "cubature"])
+def test_ricker_sequential_comparator(form, lin):
+    # the square-root recursions, or the standard Kalman filter and RTS
+    # smoother in the covariance form (the paper's Section 6.1 comparator)
     md, ys, off = _ricker_case([400, 900], 25)
     prm = orc.ricker_params()
-    b = pss.Batch.ricker(off, md, dtype=torch.float64, device=DEV, linearization="taylor")
+    b = pss.Batch.ricker(off, md, dtype=torch.float64, device=DEV, linearization=lin,
+                         form=form)
     m, N = b.prior_nominal()
     pss.sequential_smoother(b, pss.to_soa(np.concatenate(ys), torch.float64, DEV), 2, m, N)
     torch.cuda.synchronize()
     ma, Na = m[0].cpu().numpy(), N[0].cpu().numpy()
+    Pa = Na if form == "cov" else Na ** 2
     for s, y in enumerate(ys):
-        r = orc.ricker_ipls(prm, md.m0, math.sqrt(md.P0[0, 0]), y, 2, method="taylor")
+        r = orc.ricker_ipls(prm, md.m0, math.sqrt(md.P0[0, 0]), y, 2, method=lin)
         Pr = (r["Ns"] ** 2)[:, None, None]
         em = par.mean_err(_split(ma, off)[s][:, None], r["ms"][:, None], Pr)
-        eP = par.cov_err((_split(Na, off)[s] ** 2)[:, None, None], Pr)
+        eP = par.cov_err(_split(Pa, off)[s][:, None, None], Pr)
         assert em < par.TOL["f64"]["m"] and eP < par.TOL["f64"]["P"], (s, em, eP)
 
 
