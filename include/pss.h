@@ -284,7 +284,7 @@ int pss_loglik_grad(const pss_problem *p, const void *m_nom, const void *N_nom, 
    (device double): ll [B]; grad [3][B] per sequence, component-major;
    delta [B] (nullable): per sequence, the largest change of the nominal's
    tangents in the last iteration relative to max(1, their size) -- a
-   convergence check.  ws: pss_workspace_size(PSS_OP_LOGLIK_GRAD_IFT). */
+   convergence check (infinite once a tangent has overflowed).  ws: pss_workspace_size(PSS_OP_LOGLIK_GRAD_IFT). */
 int pss_loglik_grad_ift(const pss_problem *p, const void *m_nom, const void *N_nom,
                         const void *y, int32_t n_iter, double *ll, double *grad, double *delta,
                         void *ws, size_t ws_bytes, hipStream_t stream);

@@ -46,11 +46,13 @@ __global__ __launch_bounds__(128) void k_ift_nominal(int64_t T_x, const double *
     if (s >= T_x)
         return;
     double dmax = 0.0, amax = 0.0;
+    bool finite = true;
     auto track = [&](int q, const D &x) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const int64_t at = ((int64_t)q * 3 + k) * T_x + s;
             const double t = value_only ? x.d[k] : 0.0;
+            finite = finite && isfinite(t);
             dmax = fmax(dmax, fabs(t - prev[at]));
             amax = fmax(amax, fabs(t));
             prev[at] = t;
@@ -62,7 +64,8 @@ __global__ __launch_bounds__(128) void k_ift_nominal(int64_t T_x, const double *
 #pragma unroll
     for (int q = 0; q < 15; ++q)
         track(5 + q, nP[(int64_t)q * T_x + s]);
-    stat[s] = dmax / fmax(1.0, amax);
+    // a tangent that overflowed reports an infinite change
+    stat[s] = finite ? dmax / fmax(1.0, amax) : INFINITY;
     double L[5][5];
 #pragma unroll
     for (int i = 0; i < 5; ++i)

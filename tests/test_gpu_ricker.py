@@ -212,8 +212,9 @@ CT_RULES = [("unscented", {"ut_kappa": 1.0}), ("unscented", {"ut_kappa": 0.0}),
 
 
 @pytest.mark.parametrize("tag", ["f64", "f32"])
-@pytest.mark.parametrize("lin,kw", CT_RULES)
+@pytest.mark.parametrize("lin,kw", CT_RULES + [("gauss_hermite", {"gh_order": 4})])
 def test_ct_rule_linearisation_matches_oracle(tag, lin, kw):
+    # gh_order 4 is the largest CT rule (4^5 = 1024 points)
     w = wl.ct_single(300, seed=12)
     prm = orc.ct_params()
     ref = orc.ct_ipls(prm, w.model.m0, np.eye(5), w.y, 3, method=lin, **_okw(kw))
