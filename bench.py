@@ -523,7 +523,7 @@ def bench_ct_rules(stream, dev, full, n=10 ** 5):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if not torch.cuda.is_available():
