@@ -19,7 +19,8 @@ DEV = "cuda"
 
 
 @pytest.mark.parametrize("form", ["sqrt", "cov"])
-@pytest.mark.parametrize("lin,kw", [("cubature", {}), ("unscented", {"ut_kappa": 1.0})])
+@pytest.mark.parametrize("lin,kw", [("cubature", {}), ("unscented", {"ut_kappa": 1.0}),
+                                    ("taylor", {})])
 def test_fixed_point_gradient_matches_total_derivative(form, lin, kw):
     w = wl.ct_single(400, seed=3)
     prm = orc.ct_params()
