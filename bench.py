@@ -465,7 +465,14 @@ def bench_fixed_point(stream, dev, n=1000, seed=1, passes=40, ift_iter=30):
     _, g_ift, delta = pss.loglik_grad_ift(b, m, N, yd, n_iter=ift_iter, ws=wi, with_delta=True)
     _, g_fro, _ = pss.loglik_grad(b, m, N, yd, ws=wg)
     torch.cuda.synchronize()
+    b32 = pss.Batch.ct(w.y_off, w.model, dtype=torch.float32, device=dev)
+    y32 = pss.to_soa(w.y, torch.float32, dev)
+    m32, N32 = pss.ipls_iterate(b32, y32, passes)
+    wi32, _ = b32.workspace("loglik_grad_ift")
+    t_ift32 = timed(stream, lambda: pss.loglik_grad_ift(b32, m32, N32, y32, n_iter=ift_iter,
+                                                        ws=wi32), 2)
     out = {"n": n, "ift_iter": ift_iter, "ms_fixed_point_gradient": round(t_ift, 3),
+           "ms_fixed_point_gradient_f32": round(t_ift32, 3),
            "ms_frozen_gradient": round(t_fro, 4),
            "gradient_fixed_point": [round(v, 6) for v in g_ift[:, 0].tolist()],
            "gradient_frozen": [round(v, 6) for v in g_fro[:, 0].tolist()],

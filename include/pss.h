@@ -277,7 +277,7 @@ int pss_loglik_grad(const pss_problem *p, const void *m_nom, const void *N_nom, 
    pass (SLR, elements, filter scan, smoother scan) evaluated with three
    tangents per number, the value held at n*.  A last tangent pass gives
    the log-likelihood and its total derivative.  PSS_MODEL_CT_BEARINGS,
-   FP64, any linearisation.  The iteration converges where the IPLS
+   FP64 or FP32 (the terms are summed in FP64), any linearisation.  The iteration converges where the IPLS
    iteration itself converges at n* (the operator-norm condition of the
    paper); where IPLS has no fixed point (it can cycle on long bearings-only
    tracks started from the prior) the tangents grow without bound.  Outputs

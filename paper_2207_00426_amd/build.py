@@ -42,8 +42,13 @@ def build(jobs: int | None = None, verbose: bool = False, extra_flags=()) -> str
     jobs = jobs or min(8, os.cpu_count() or 4)
     units = [(os.path.join(CSRC, "api.hip"), os.path.join(BUILD, "api.o"), []),
              (os.path.join(CSRC, "persistent.hip"), os.path.join(BUILD, "persistent.o"), []),
-             (os.path.join(CSRC, "ift.hip"), os.path.join(BUILD, "ift.o"), []),
-             (os.path.join(CSRC, "ift_smoother.hip"), os.path.join(BUILD, "ift_smoother.o"), [])]
+             (os.path.join(CSRC, "ift_api.hip"), os.path.join(BUILD, "ift_api.o"), [])]
+    # the fixed-point gradient's dual-number passes: one unit per precision
+    # and half (they are the slowest units to compile)
+    for t in DTYPES:
+        for src in ("ift", "ift_smoother"):
+            units.append((os.path.join(CSRC, src + ".hip"),
+                          os.path.join(BUILD, "%s_%s.o" % (src, t[0])), ["-DPSS_IFT_T=%s" % t]))
     for t in DTYPES:
         for nx, ny in DIMS:
             obj = os.path.join(BUILD, "inst_%s_%d_%d.o" % (t[0], nx, ny))

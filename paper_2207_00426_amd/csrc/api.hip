@@ -595,8 +595,7 @@ size_t pss_workspace_size(const pss_problem *p, int32_t op)
         if (validate(p) != PSS_OK)
             return 0;
         if (op == PSS_OP_LOGLIK_GRAD_IFT)
-            return (p->model == PSS_MODEL_CT_BEARINGS && p->dtype == PSS_F64) ? ift_ws_size(p)
-                                                                               : 0;
+            return p->model == PSS_MODEL_CT_BEARINGS ? ift_ws_size(p) : 0;
         const Ctx c = make_ctx(p, nullptr);
         size_t n = 0;
         dispatch(p, [&](auto tag) {

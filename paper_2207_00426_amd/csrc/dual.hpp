@@ -7,6 +7,8 @@
 // value only: the derivative is that of the branch taken.
 #pragma once
 
+#include <type_traits>
+
 #include "device_math.hpp"
 #include "device_ops.hpp"
 
@@ -17,13 +19,14 @@ struct Dual {
     T v;
     T d[K];
     Dual() = default;
-    PSS_INL Dual(T x) : v(x)
+    // a constant (zero tangents) from any plain number
+    template <typename U, typename = typename std::enable_if<std::is_arithmetic<U>::value>::type>
+    PSS_INL Dual(U x) : v(T(x))
     {
 #pragma unroll
         for (int k = 0; k < K; ++k)
             d[k] = T(0);
     }
-    PSS_INL Dual(int x) : Dual(T(x)) {}
     PSS_INL Dual &operator+=(const Dual &o)
     {
         v += o.v;

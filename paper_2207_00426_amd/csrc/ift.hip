@@ -6,7 +6,8 @@
 // fixed point dn = dKS/dn dn + dKS/dtheta.  Algorithm 4 iterates that
 // equation; here each iteration is one pass of the parallel covariance-form
 // smoother (SLR, filter elements, filter scan, smoother scan) run on numbers
-// that carry three tangents (Dual<double, 3>, one per theta component): with
+// that carry three tangents (Dual<S, 3> for S = double or float, one per theta
+// component; this file is compiled once per S, with PSS_IFT_T set): with
 // the nominal's value held at n* and its tangents set to the previous
 // iterate, the pass's output tangents are exactly dKS/dn dn + dKS/dtheta.
 // The same scans, operators and storage layouts as the value pass are used,
@@ -24,9 +25,11 @@
 
 namespace pss {
 
-// value-only dual copy of a double array
-__global__ __launch_bounds__(256) void k_to_dual(const double *x, D *out, int64_t n)
+// value-only dual copy of an array
+template <typename S>
+__global__ __launch_bounds__(256) void k_to_dual(const S *x, Dual<S, 3> *out, int64_t n)
 {
+    using D = Dual<S, 3>;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n)
         out[i] = D(x[i]);
@@ -38,10 +41,13 @@ __global__ __launch_bounds__(256) void k_to_dual(const double *x, D *out, int64_
 // value_only, stat[s] receives the largest change of state s's tangents
 // since the previous call relative to max(1, their size), and prev keeps
 // the tangents for the next call ([20 values][3 tangents][T_x]).
-__global__ __launch_bounds__(128) void k_ift_nominal(int64_t T_x, const double *m,
-                                                     const double *N, int is_factor, D *nm, D *nP,
-                                                     int value_only, double *prev, double *stat)
+template <typename S>
+__global__ __launch_bounds__(128) void k_ift_nominal(int64_t T_x, const S *m, const S *N,
+                                                     int is_factor, Dual<S, 3> *nm,
+                                                     Dual<S, 3> *nP, int value_only,
+                                                     double *prev, double *stat)
 {
+    using D = Dual<S, 3>;
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= T_x)
         return;
@@ -51,7 +57,7 @@ __global__ __launch_bounds__(128) void k_ift_nominal(int64_t T_x, const double *
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const int64_t at = ((int64_t)q * 3 + k) * T_x + s;
-            const double t = value_only ? x.d[k] : 0.0;
+            const double t = value_only ? (double)x.d[k] : 0.0;
             finite = finite && isfinite(t);
             dmax = fmax(dmax, fabs(t - prev[at]));
             amax = fmax(amax, fabs(t));
@@ -66,15 +72,15 @@ __global__ __launch_bounds__(128) void k_ift_nominal(int64_t T_x, const double *
         track(5 + q, nP[(int64_t)q * T_x + s]);
     // a tangent that overflowed reports an infinite change
     stat[s] = finite ? dmax / fmax(1.0, amax) : INFINITY;
-    double L[5][5];
+    S L[5][5];
 #pragma unroll
     for (int i = 0; i < 5; ++i)
 #pragma unroll
         for (int j = 0; j < 5; ++j)
-            L[i][j] = j <= i ? N[(int64_t)tri_idx(i, j) * T_x + s] : 0.0;
+            L[i][j] = j <= i ? N[(int64_t)tri_idx(i, j) * T_x + s] : S(0);
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
-        const double v = m[(int64_t)i * T_x + s];
+        const S v = m[(int64_t)i * T_x + s];
         if (value_only)
             nm[(int64_t)i * T_x + s].v = v;
         else
@@ -84,12 +90,12 @@ __global__ __launch_bounds__(128) void k_ift_nominal(int64_t T_x, const double *
     for (int i = 0; i < 5; ++i)
 #pragma unroll
         for (int j = 0; j <= i; ++j) {
-            double v = L[i][j];
+            S v = L[i][j];
             if (is_factor) {
-                v = 0.0;
+                v = S(0);
 #pragma unroll
                 for (int t = 0; t <= j; ++t)
-                    v = fma(L[i][t], L[j][t], v);
+                    v = pfma(L[i][t], L[j][t], v);
             }
             const int64_t at = (int64_t)tri_idx(i, j) * T_x + s;
             if (value_only)
@@ -100,8 +106,8 @@ __global__ __launch_bounds__(128) void k_ift_nominal(int64_t T_x, const double *
 }
 
 // per sequence: the largest stat over its states (one block per sequence)
-__global__ __launch_bounds__(256) void k_seq_max(const int64_t *y_off, const double *stat,
-                                                 double *out)
+static __global__ __launch_bounds__(256) void k_seq_max(const int64_t *y_off,
+                                                        const double *stat, double *out)
 {
     __shared__ double red[256];
     const int b = blockIdx.x;
@@ -122,11 +128,15 @@ __global__ __launch_bounds__(256) void k_seq_max(const int64_t *y_off, const dou
 
 // covariance-form log-likelihood terms (as k_loglik_terms_cov) in dual
 // numbers: ell[0][t] the value, ell[1 + k][t] its tangent k
+template <typename S>
 __global__ __launch_bounds__(128) void k_loglik_terms_cov_dual(const int64_t *y_off, int B,
-                                                               int64_t T_y, GammaRef<D, 5, 2> gam,
-                                                               const double *y, MargRef<D, 5> filt,
+                                                               int64_t T_y,
+                                                               GammaRef<Dual<S, 3>, 5, 2> gam,
+                                                               const S *y,
+                                                               MargRef<Dual<S, 3>, 5> filt,
                                                                double *ell)
 {
+    using D = Dual<S, 3>;
     constexpr int NX = 5, NY = 2;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= T_y)
@@ -156,7 +166,7 @@ __global__ __launch_bounds__(128) void k_loglik_terms_cov_dual(const int64_t *y_
                 s = pfma(FP[i][k], F[j][k], s);
             Pp[i][j] = s;
         }
-    D HP[NY][NX], S[NY][NY], Y[NY][NY];
+    D HP[NY][NX], Sy[NY][NY], Y[NY][NY];
     mm(H, Pp, HP);
 #pragma unroll
     for (int a = 0; a < NY; ++a)
@@ -166,41 +176,54 @@ __global__ __launch_bounds__(128) void k_loglik_terms_cov_dual(const int64_t *y_
 #pragma unroll
             for (int j = 0; j < NX; ++j)
                 s = pfma(HP[a][j], H[q][j], s);
-            S[a][q] = s;
+            Sy[a][q] = s;
         }
-    chol_lower(S, Y);
+    chol_lower(Sy, Y);
     D Hm[NY], v[NY], u[NY];
     mv(H, mp, Hm);
 #pragma unroll
     for (int a = 0; a < NY; ++a)
         v[a] = (D(y[a * T_y + t]) - Hm[a]) - d[a];
     lsolve_lower(Y, v, u);
-    D l(-0.5 * NY * 1.8378770664093454835606594728112); // log(2 pi)
+    // the sum in FP64 for both precisions, as the value pass does
+    double lv = -0.5 * NY * 1.8378770664093454835606594728112; // log(2 pi)
+    double ld[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-    for (int a = 0; a < NY; ++a)
-        l -= plog(Y[a][a]) + 0.5 * (u[a] * u[a]);
-    ell[t] = l.v;
+    for (int a = 0; a < NY; ++a) {
+        const D q = plog(Y[a][a]) + S(0.5) * (u[a] * u[a]);
+        lv -= (double)q.v;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            ld[k] -= (double)q.d[k];
+    }
+    ell[t] = lv;
 #pragma unroll
     for (int k = 0; k < 3; ++k)
-        ell[(int64_t)(1 + k) * T_y + t] = l.d[k];
+        ell[(int64_t)(1 + k) * T_y + t] = ld[k];
 }
 
-namespace {
-
-size_t scan_ws_bytes(const Ctx &c)
+template <typename S>
+static size_t scan_ws_bytes(const Ctx &c)
 {
+    using D = Dual<S, 3>;
+    using C = IftC<S>;
+    using FSC = FilterScanCov<D, 5>;
+    using SSC = SmootherScanCov<D, 5>;
     Carver a{nullptr};
-    C::carve_scan<FSC>(a, c, C::filter_shape(c));
+    C::template carve_scan<FSC>(a, c, C::filter_shape(c));
     Carver b{nullptr};
-    C::carve_scan<SSC>(b, c, C::smoother_shape(c));
+    C::template carve_scan<SSC>(b, c, C::smoother_shape(c));
     b.take<D>((size_t)Sizes<5>::selem * c.T_x); // smoother element stash
     return std::max(std::max(a.used, b.used), seq_sum_bytes(c, 3));
 }
 
-IftBufs carve_ift(const Ctx &c, void *base)
+template <typename S>
+static IftBufs<S> carve_ift(const Ctx &c, void *base)
 {
+    using D = Dual<S, 3>;
+    using C = IftC<S>;
     Carver cv{static_cast<char *>(base)};
-    IftBufs w;
+    IftBufs<S> w;
     w.nm = cv.take<D>((size_t)5 * c.T_x);
     w.nP = cv.take<D>((size_t)15 * c.T_x);
     w.mf = cv.take<D>((size_t)5 * c.T_x);
@@ -215,28 +238,15 @@ IftBufs carve_ift(const Ctx &c, void *base)
     w.prev = cv.take<double>((size_t)60 * c.T_x);
     w.stat = cv.take<double>((size_t)c.T_x);
     w.scan_ws = cv.base ? cv.base + cv.used : nullptr;
-    w.used = cv.used + scan_ws_bytes(c);
+    w.used = cv.used + scan_ws_bytes<S>(c);
     return w;
 }
 
-int ift_validate(const pss_problem *p)
+template <typename S>
+static int launch_slr(const Ctx &c, const IftBufs<S> &w)
 {
-    int rc = pss_validate(p);
-    if (rc)
-        return rc;
-    if (p->model != PSS_MODEL_CT_BEARINGS) {
-        set_error("loglik_grad_ift: theta is defined for the coordinated-turn model");
-        return PSS_EUNSUPPORTED;
-    }
-    if (p->dtype != PSS_F64) {
-        set_error("loglik_grad_ift: built for FP64");
-        return PSS_EUNSUPPORTED;
-    }
-    return PSS_OK;
-}
-
-int launch_slr(const Ctx &c, const IftBufs &w)
-{
+    using D = Dual<S, 3>;
+    using C = IftC<S>;
     const CTHost h = ct_host(c.p);
     CTParams<D> P;
     P.dt = D(h.dt);
@@ -247,12 +257,12 @@ int launch_slr(const Ctx &c, const IftBufs &w)
     // theta = (log q1, log q2, log sigma): the q1 part of the factor scales
     // as sqrt(q1), the q2 part as sqrt(q2), sigma as e^theta3
     P.sigma = D(h.sigma);
-    P.sigma.d[2] = h.sigma;
+    P.sigma.d[2] = (S)h.sigma;
     for (int i = 0; i < 5; ++i)
         for (int j = 0; j < 5; ++j) {
             P.LQ[i][j] = D(h.LQ[i][j]);
-            P.LQ[i][j].d[0] = 0.5 * h.L1[i][j];
-            P.LQ[i][j].d[1] = 0.5 * h.L2[i][j];
+            P.LQ[i][j].d[0] = (S)(0.5 * h.L1[i][j]);
+            P.LQ[i][j].d[1] = (S)(0.5 * h.L2[i][j]);
         }
     const int tb = 128;
     const dim3 grid((unsigned)((c.T_x + tb - 1) / tb));
@@ -266,6 +276,7 @@ int launch_slr(const Ctx &c, const IftBufs &w)
         RuleSpec<double> Rd;
         if (!rule_spec(c.p, 5, Rd))
             return PSS_EINVAL;
+        // the rule's nodes and weights enter with zero tangents
         RuleSpec<D> R;
         R.kind = Rd.kind;
         R.np = Rd.np;
@@ -284,8 +295,11 @@ int launch_slr(const Ctx &c, const IftBufs &w)
     return hip_check(hipGetLastError(), "ift slr launch");
 }
 
-int launch_felem(const Ctx &c, const IftBufs &w)
+template <typename S>
+static int launch_felem(const Ctx &c, const IftBufs<S> &w)
 {
+    using D = Dual<S, 3>;
+    using C = IftC<S>;
     const ScanShape sh = C::filter_shape(c);
     const int tb = 128;
     KTime kt(c.s, "ift_filter_elements", "", 0);
@@ -295,20 +309,23 @@ int launch_felem(const Ctx &c, const IftBufs &w)
     return hip_check(hipGetLastError(), "ift filter elements launch");
 }
 
-int run_fscan(const Ctx &c, const IftBufs &w)
+template <typename S>
+static int run_fscan(const Ctx &c, const IftBufs<S> &w)
 {
+    using D = Dual<S, 3>;
+    using C = IftC<S>;
+    using FSC = FilterScanCov<D, 5>;
     const ScanShape sh = C::filter_shape(c);
     Carver cv{static_cast<char *>(w.scan_ws)};
-    auto sw = C::carve_scan<FSC>(cv, c, sh);
+    auto sw = C::template carve_scan<FSC>(cv, c, sh);
     FiltDst<D, 5> dst{C::marg_ref2(w.mf, w.Pf, c.T_x), c.p->y_off};
     StartPreCov<D, 5> st{w.m0d, w.N0d};
     RefSrc<FSC, FElemRef<D, 5>, true> src{w.fel};
-    return C::run_scan<FSC>(c, sh, sw, 0, src, dst, st, &C::felem_ref);
+    return C::template run_scan<FSC>(c, sh, sw, 0, src, dst, st, &C::felem_ref);
 }
 
-} // namespace
-
-size_t ift_ws_size(const pss_problem *p)
+template <typename S>
+size_t ift_ws(const pss_problem *p)
 {
     Ctx c;
     c.p = p;
@@ -316,88 +333,77 @@ size_t ift_ws_size(const pss_problem *p)
     c.T_y = p->y_off_host[p->B];
     c.T_x = c.T_y + p->B;
     c.s = nullptr;
-    return carve_ift(c, nullptr).used;
+    return carve_ift<S>(c, nullptr).used;
 }
+
+template <typename S>
+int ift_run(const pss_problem *p, const void *m_nom, const void *N_nom, const void *y,
+            int32_t n_iter, double *ll, double *grad, double *delta, void *ws,
+            hipStream_t stream)
+{
+    using C = IftC<S>;
+    Ctx c;
+    c.p = p;
+    c.B = p->B;
+    c.T_y = p->y_off_host[p->B];
+    c.T_x = c.T_y + p->B;
+    c.s = stream;
+    const IftBufs<S> w = carve_ift<S>(c, ws);
+    const int is_factor = p->form == PSS_FORM_SQRT ? 1 : 0;
+    const dim3 blk(256);
+    const S *ys = static_cast<const S *>(y);
+    hipLaunchKernelGGL(k_to_dual<S>, dim3((unsigned)((2 * c.T_y + 255) / 256)), blk, 0, stream, ys,
+                       w.yd, 2 * c.T_y);
+    hipLaunchKernelGGL(k_to_dual<S>, dim3(1), blk, 0, stream, static_cast<const S *>(p->m0), w.m0d,
+                       (int64_t)5);
+    hipLaunchKernelGGL(k_to_dual<S>, dim3(1), blk, 0, stream, static_cast<const S *>(p->N0), w.N0d,
+                       (int64_t)15);
+    const dim3 gx((unsigned)((c.T_x + 127) / 128));
+    const S *mn = static_cast<const S *>(m_nom);
+    const S *Nn = static_cast<const S *>(N_nom);
+    hipLaunchKernelGGL(k_ift_nominal<S>, gx, dim3(128), 0, stream, c.T_x, mn, Nn, is_factor, w.nm,
+                       w.nP, 0, w.prev, w.stat);
+    int rc;
+    if ((rc = hip_check(hipGetLastError(), "ift setup launch")))
+        return rc;
+    for (int it = 0; it < n_iter; ++it) {
+        if ((rc = launch_slr<S>(c, w)) || (rc = launch_felem<S>(c, w)) ||
+            (rc = run_fscan<S>(c, w)) || (rc = run_sscan<S>(c, w)))
+            return rc;
+        // hold the value at the fixed point; keep the new tangents
+        hipLaunchKernelGGL(k_ift_nominal<S>, gx, dim3(128), 0, stream, c.T_x, mn, Nn, is_factor,
+                           w.nm, w.nP, 1, w.prev, w.stat);
+        if ((rc = hip_check(hipGetLastError(), "ift nominal launch")))
+            return rc;
+    }
+    if (delta) {
+        hipLaunchKernelGGL(k_seq_max, dim3((unsigned)c.B), dim3(256), 0, stream, p->y_off, w.stat,
+                           delta);
+        if ((rc = hip_check(hipGetLastError(), "ift delta launch")))
+            return rc;
+    }
+    // log-likelihood of the linearisation at (n*, dn*/dtheta)
+    if ((rc = launch_slr<S>(c, w)) || (rc = launch_felem<S>(c, w)) || (rc = run_fscan<S>(c, w)))
+        return rc;
+    {
+        KTime kt(stream, "ift_loglik_terms", "", 0);
+        hipLaunchKernelGGL(k_loglik_terms_cov_dual<S>, dim3((unsigned)((c.T_y + 127) / 128)),
+                           dim3(128), 0, stream, p->y_off, c.B, c.T_y, C::gamma_ref(&w.gam, c.T_y),
+                           ys, C::marg_ref2(w.mf, w.Pf, c.T_x), w.ell);
+        if ((rc = hip_check(hipGetLastError(), "ift loglik launch")))
+            return rc;
+    }
+    if ((rc = launch_seq_sum(c, 1, w.ell, c.T_y, ll, w.scan_ws)))
+        return rc;
+    return launch_seq_sum(c, 3, w.ell + c.T_y, c.T_y, grad, w.scan_ws);
+}
+
+#if !defined(PSS_IFT_T)
+#error "compile with -DPSS_IFT_T=<double|float>"
+#endif
+template size_t ift_ws<PSS_IFT_T>(const pss_problem *p);
+template int ift_run<PSS_IFT_T>(const pss_problem *p, const void *m_nom, const void *N_nom,
+                                const void *y, int32_t n_iter, double *ll, double *grad,
+                                double *delta, void *ws, hipStream_t stream);
 
 } // namespace pss
-
-using namespace pss;
-
-extern "C" int pss_loglik_grad_ift(const pss_problem *p, const void *m_nom, const void *N_nom,
-                                   const void *y, int32_t n_iter, double *ll, double *grad,
-                                   double *delta, void *ws, size_t ws_bytes, hipStream_t stream)
-{
-    try {
-        int rc = ift_validate(p);
-        if (rc)
-            return rc;
-        if (!m_nom || !N_nom || !y || !ll || !grad || n_iter < 1) {
-            set_error("loglik_grad_ift: null buffer or n_iter < 1");
-            return PSS_EINVAL;
-        }
-        Ctx c;
-        c.p = p;
-        c.B = p->B;
-        c.T_y = p->y_off_host[p->B];
-        c.T_x = c.T_y + p->B;
-        c.s = stream;
-        const size_t need = ift_ws_size(p);
-        if (!ws || ws_bytes < need) {
-            set_error("workspace too small: need " + std::to_string(need) + " bytes");
-            return PSS_EWORKSPACE;
-        }
-        const IftBufs w = carve_ift(c, ws);
-        const int is_factor = p->form == PSS_FORM_SQRT ? 1 : 0;
-        const dim3 blk(256);
-        hipLaunchKernelGGL(k_to_dual, dim3((unsigned)((2 * c.T_y + 255) / 256)), blk, 0, stream,
-                           static_cast<const double *>(y), w.yd, 2 * c.T_y);
-        hipLaunchKernelGGL(k_to_dual, dim3(1), blk, 0, stream, static_cast<const double *>(p->m0),
-                           w.m0d, (int64_t)5);
-        hipLaunchKernelGGL(k_to_dual, dim3(1), blk, 0, stream, static_cast<const double *>(p->N0),
-                           w.N0d, (int64_t)15);
-        const dim3 gx((unsigned)((c.T_x + 127) / 128));
-        const double *mn = static_cast<const double *>(m_nom);
-        const double *Nn = static_cast<const double *>(N_nom);
-        hipLaunchKernelGGL(k_ift_nominal, gx, dim3(128), 0, stream, c.T_x, mn, Nn, is_factor,
-                           w.nm, w.nP, 0, w.prev, w.stat);
-        if ((rc = hip_check(hipGetLastError(), "ift setup launch")))
-            return rc;
-        for (int it = 0; it < n_iter; ++it) {
-            if ((rc = launch_slr(c, w)) || (rc = launch_felem(c, w)) || (rc = run_fscan(c, w)) ||
-                (rc = run_sscan(c, w)))
-                return rc;
-            // hold the value at the fixed point; keep the new tangents
-            hipLaunchKernelGGL(k_ift_nominal, gx, dim3(128), 0, stream, c.T_x, mn, Nn, is_factor,
-                               w.nm, w.nP, 1, w.prev, w.stat);
-            if ((rc = hip_check(hipGetLastError(), "ift nominal launch")))
-                return rc;
-        }
-        if (delta) {
-            hipLaunchKernelGGL(k_seq_max, dim3((unsigned)c.B), dim3(256), 0, stream, p->y_off,
-                               w.stat, delta);
-            if ((rc = hip_check(hipGetLastError(), "ift delta launch")))
-                return rc;
-        }
-        // log-likelihood of the linearisation at (n*, dn*/dtheta)
-        if ((rc = launch_slr(c, w)) || (rc = launch_felem(c, w)) || (rc = run_fscan(c, w)))
-            return rc;
-        {
-            KTime kt(stream, "ift_loglik_terms", "", 0);
-            hipLaunchKernelGGL(k_loglik_terms_cov_dual, dim3((unsigned)((c.T_y + 127) / 128)),
-                               dim3(128), 0, stream, p->y_off, c.B, c.T_y,
-                               C::gamma_ref(&w.gam, c.T_y), static_cast<const double *>(y),
-                               C::marg_ref2(w.mf, w.Pf, c.T_x), w.ell);
-            if ((rc = hip_check(hipGetLastError(), "ift loglik launch")))
-                return rc;
-        }
-        if ((rc = launch_seq_sum(c, 1, w.ell, c.T_y, ll, w.scan_ws)))
-            return rc;
-        return launch_seq_sum(c, 3, w.ell + c.T_y, c.T_y, grad, w.scan_ws);
-    } catch (const std::exception &ex) {
-        set_error(ex.what());
-        return PSS_EINVAL;
-    } catch (...) {
-        set_error("unknown exception in loglik_grad_ift");
-        return PSS_EINVAL;
-    }
-}

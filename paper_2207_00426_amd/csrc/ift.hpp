@@ -1,5 +1,6 @@
-// Shared pieces of the fixed-point gradient (ift.hip, ift_smoother.hip): the
-// dual-number type of its passes and the workspace buffers of one call.
+// Shared pieces of the fixed-point gradient (ift.hip, ift_smoother.hip,
+// ift_api.hip): the dual-number types of its passes, the workspace buffers of
+// one call, and the per-precision entry points (S = double or float).
 #pragma once
 
 #include "dual.hpp"
@@ -7,15 +8,14 @@
 
 namespace pss {
 
-using D = Dual<double, 3>;
-using C = Core<D, 5, 2>;
-using FSC = FilterScanCov<D, 5>;
-using SSC = SmootherScanCov<D, 5>;
+template <typename S>
+using IftC = Core<Dual<S, 3>, 5, 2>;
 
+template <typename S>
 struct IftBufs {
-    D *nm, *nP, *mf, *Pf, *yd, *m0d, *N0d;
+    Dual<S, 3> *nm, *nP, *mf, *Pf, *yd, *m0d, *N0d;
     pss_gamma gam;
-    FElemRef<D, 5> fel;
+    FElemRef<Dual<S, 3>, 5> fel;
     double *ell;
     double *prev, *stat; // previous tangents [60][T_x]; per-state change [T_x]
     void *scan_ws;
@@ -24,6 +24,16 @@ struct IftBufs {
 
 // covariance-form smoother scan of the dual pass (ift_smoother.hip): reads
 // the dual linearisation and filter marginals, writes the dual nominal
-int run_sscan(const Ctx &c, const IftBufs &w);
+template <typename S>
+int run_sscan(const Ctx &c, const IftBufs<S> &w);
+
+// workspace bytes and the whole computation (ift.hip); the problem has been
+// validated by the caller (ift_api.hip)
+template <typename S>
+size_t ift_ws(const pss_problem *p);
+template <typename S>
+int ift_run(const pss_problem *p, const void *m_nom, const void *N_nom, const void *y,
+            int32_t n_iter, double *ll, double *grad, double *delta, void *ws,
+            hipStream_t stream);
 
 } // namespace pss

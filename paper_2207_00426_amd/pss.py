@@ -517,7 +517,7 @@ class LogLik(torch.autograd.Function):
 def loglik_grad_ift(batch, m_nom, N_nom, y, n_iter=30, ws=None, with_delta=False):
     """(ll [B], grad [3, B][, delta [B]]): the total derivative of the
     pseudo-log-likelihood at the IPLS fixed point (m_nom, N_nom) (Algorithm
-    4), FP64 CT only; delta is the per-sequence tangent change of the last
+    4), CT model; delta is the per-sequence tangent change of the last
     iteration (a convergence check)."""
     _require_gpu()
     dev = batch.device

@@ -197,12 +197,14 @@ def test_ricker_model_and_sigma_point_rules_are_validated(L):
 
 
 def test_fixed_point_gradient_is_validated_before_any_hip_call(L):
+    # (refusals before any HIP call)
     ct = dict(model=pss.MODEL_CT, nx=5, ny=2, m0=np.zeros(5), N0=np.eye(5), dt=0.01)
     b = _cpu_batch(**ct)
     assert pss.workspace_size(b, "loglik_grad_ift") > pss.workspace_size(b, "loglik_grad")
     d = ctypes.c_void_p(8)
-    # FP32 and non-CT models are refused
-    for bad in (_cpu_batch(dtype=torch.float32, **ct), _ricker_cpu(), _cpu_batch()):
+    # FP32 is built too; non-CT models are refused
+    assert pss.workspace_size(_cpu_batch(dtype=torch.float32, **ct), "loglik_grad_ift") > 0
+    for bad in (_ricker_cpu(), _cpu_batch()):
         p = bad.struct()
         assert pss.workspace_size(bad, "loglik_grad_ift") == 0
         rc = L.pss_loglik_grad_ift(ctypes.byref(p), d, d, d, 5, d, d, None, d, 1 << 40, None)

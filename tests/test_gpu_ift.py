@@ -77,3 +77,21 @@ def test_tangent_iteration_reports_a_missing_fixed_point():
     print("tangent change per sequence", d)
     assert np.all(d[[0, 1, 3]] < 1e-8)
     assert d[2] > 1e3 * np.max(d[[0, 1, 3]])
+
+
+def test_fixed_point_gradient_fp32():
+    # the FP32 dual passes at the FP32 nominal, against the FP64 oracle's
+    # total derivative: the FP32 gradient bar
+    w = wl.ct_single(400, seed=3)
+    l0, g_tot, _, _ = orc.ct_score_total(orc.ct_params(), w.model.m0, np.eye(5), w.y)
+    b = pss.Batch.ct(w.y_off, w.model, dtype=torch.float32, device=DEV)
+    yd = pss.to_soa(w.y, torch.float32, DEV)
+    m, N = b.prior_nominal()
+    pss.ipls_iterate(b, yd, 60, m, N)
+    ll, grad, delta = pss.loglik_grad_ift(b, m, N, yd, n_iter=40, with_delta=True)
+    torch.cuda.synchronize()
+    g = grad[:, 0].cpu().numpy()
+    print("FP32 IFT gradient", g, "oracle", g_tot, "delta", float(delta[0]))
+    assert np.all(np.isfinite(g))
+    assert par.ll_err(float(ll[0]), l0) < par.TOL["f32"]["ll"]
+    assert par.grad_err(g, g_tot) < par.TOL["f32"]["g"], (g, g_tot)
