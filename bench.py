@@ -86,9 +86,10 @@ def log(msg):
     print("bench: " + msg, file=sys.stderr, flush=True)
 
 
-def scan_plan(lengths, T0, E0, Tup, Eup):
+def scan_plan(lengths, T0, E0, Tup, Eup, flat0):
     """Mirror of the library's level plan: per level (T, E, elements, tiles,
-    active threads)."""
+    active threads, flat).  With flat0 the finest level is flat (never the
+    top): its threads' aggregates are the next level's elements."""
     cnt = np.asarray(lengths, dtype=np.int64)
     levels = []
     for l in range(8):
@@ -97,30 +98,36 @@ def scan_plan(lengths, T0, E0, Tup, Eup):
         tiles = -(-cnt // TS)
         last = cnt - (tiles - 1) * TS
         threads = (tiles - 1) * T + (-(-last // E))
-        levels.append((T, E, int(cnt.sum()), int(tiles.sum()), int(threads.sum())))
-        if cnt.max() <= TS:
+        flat = flat0 and l == 0
+        top = cnt.max() <= TS and not flat
+        levels.append((T, E, int(cnt.sum()), int(tiles.sum()), int(threads.sum()), flat))
+        if top:
             break
-        cnt = tiles
+        cnt = -(-cnt // E) if flat else tiles
     return levels
 
 
-def scan_kernel_flops(op, lengths, T0, E0, Tup, Eup):
+def scan_kernel_flops(op, lengths, T0, E0, Tup, Eup, flat0):
     """Counted flops of each kernel of one scan, keyed (kernel, level).
 
     Up-sweep (and the first half of the top kernel): the fold and the tile
     tree combine every element but the first of each tile, elems - tiles
     combines.  Down-sweep: the tree applies threads - tiles times and every
-    element is applied once.  The smoother's level-0 up-sweep also builds its
-    elements (one per state)."""
+    element is applied once.  A flat level has no tree: elems - threads
+    combines up, elems applies down.  The smoother's level-0 up-sweep also
+    builds its elements (one per state)."""
     comb, app = FLOPS[op + "_combine"], FLOPS[op + "_apply"]
     # the filter's finest level folds and applies leaf elements (elements -
     # threads fold combines, elements applies); its trees use the general form
     lcomb = FLOPS.get(op + "_combine_leaf", comb)
     lapp = FLOPS.get(op + "_apply_leaf", app)
-    plan = scan_plan(lengths, T0, E0, Tup, Eup)
+    plan = scan_plan(lengths, T0, E0, Tup, Eup, flat0)
     out = {}
-    for l, (T, E, elems, tiles, threads) in enumerate(plan):
-        if l == 0:
+    for l, (T, E, elems, tiles, threads, flat) in enumerate(plan):
+        if flat:
+            up = (elems - threads) * lcomb
+            down = elems * lapp
+        elif l == 0:
             up = (elems - threads) * lcomb + (threads - tiles) * comb
             down = elems * lapp + (threads - tiles) * app
         else:
@@ -186,10 +193,11 @@ def copy_probe(stream, dev, reps=5):
 
 
 def shapes(dtype, T_req, E_req, smoother=False):
-    """Mirror of the library's default launch shapes (T0, E0, Tup, Eup)."""
+    """Mirror of the library's default launch shapes (T0, E0, Tup, Eup, flat
+    finest level)."""
     T0 = T_req or 64
     E0 = E_req or (2 if smoother else 4)
-    return T0, E0, min(T0, 64), 2
+    return T0, E0, min(T0, 64), 2 if smoother else 4, not smoother
 
 
 class Runner:
@@ -593,8 +601,8 @@ def main():
             "loglik_grad": timed(stream, lambda: pss.loglik_grad(b, m, N, yd, ws=R.ws_grad), reps),
         }
         log("stages (ms): " + ", ".join("%s %.3f" % kv for kv in stage.items()))
-        T0, E0, Tup, Eup = shapes(args.dtype, args.scan_threads, args.scan_elems)
-        kflops = scan_kernel_flops("filter", [n], T0, E0, Tup, Eup)
+        T0, E0, Tup, Eup, flat0 = shapes(args.dtype, args.scan_threads, args.scan_elems)
+        kflops = scan_kernel_flops("filter", [n], T0, E0, Tup, Eup, flat0)
         kflops.update(scan_kernel_flops(
             "smoother", [n + 1], *shapes(args.dtype, args.scan_threads, args.scan_elems, True)))
         E0s = shapes(args.dtype, args.scan_threads, args.scan_elems, True)[1]

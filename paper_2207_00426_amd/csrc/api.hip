@@ -109,7 +109,7 @@ KTime::~KTime()
 // ---------------------------------------------------------------------------
 // scan planning (host side mirrors k_plan exactly)
 // ---------------------------------------------------------------------------
-ScanShape plan_scan(const Ctx &c, int extra, int T0, int E0, int Tup, int Eup)
+ScanShape plan_scan(const Ctx &c, int extra, int T0, int E0, int Tup, int Eup, bool flat0)
 {
     ScanShape sh;
     std::vector<int64_t> cnt(c.B);
@@ -126,58 +126,103 @@ ScanShape plan_scan(const Ctx &c, int extra, int T0, int E0, int Tup, int Eup)
         int64_t nt = 0, mx = 0;
         for (int b = 0; b < c.B; ++b) {
             mx = std::max(mx, cnt[b]);
-            cnt[b] = (cnt[b] + TS - 1) / TS;
-            nt += cnt[b];
+            nt += (cnt[b] + TS - 1) / TS;
         }
         sh.ntiles[l] = nt;
-        if (mx <= TS) {
+        // a flat level 0 is never the top, also where one tile would hold
+        // every sequence: a sequence's bracketing must not depend on the
+        // lengths of the others in its batch (a level that holds a sequence
+        // in one tile passes it through bitwise unchanged)
+        sh.flat[l] = l == 0 && flat0;
+        if (mx <= TS && !sh.flat[l]) {
             sh.L = l + 1;
             break;
         }
+        const int64_t D = sh.flat[l] ? sh.E[l] : TS;
+        int64_t ne = 0;
+        for (int b = 0; b < c.B; ++b) {
+            cnt[b] = (cnt[b] + D - 1) / D;
+            ne += cnt[b];
+        }
         if (l + 1 < kMaxLevels)
-            sh.nelem[l + 1] = nt;
+            sh.nelem[l + 1] = ne;
     }
     return sh;
+}
+
+// exclusive block-wide prefix sums of one value per sequence, written to
+// out[0..B] (one block of 1024 threads; the block calls it uniformly)
+template <class F>
+__device__ void plan_offsets(int B, int64_t *out, int64_t *sh, int64_t &carry, F value)
+{
+    if (threadIdx.x == 0) {
+        carry = 0;
+        out[0] = 0;
+    }
+    for (int base = 0; base < B; base += 1024) {
+        const int b = base + threadIdx.x;
+        const int64_t t = b < B ? value(b) : 0;
+        __syncthreads();
+        sh[threadIdx.x] = t;
+        for (int d = 1; d < 1024; d <<= 1) {
+            __syncthreads();
+            const int64_t v = (int)threadIdx.x >= d ? sh[threadIdx.x - d] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += v;
+        }
+        __syncthreads();
+        if (b < B)
+            out[b + 1] = carry + sh[threadIdx.x];
+        __syncthreads();
+        if (threadIdx.x == 0)
+            carry += sh[1023];
+        __syncthreads();
+    }
 }
 
 __global__ __launch_bounds__(1024) void k_plan(PlanArgs a)
 {
     __shared__ int64_t sh[1024];
     __shared__ int64_t carry;
-    for (int l = 0; l < a.L; ++l) {
-        if (threadIdx.x == 0) {
-            carry = 0;
+    if (a.B <= 64) {
+        // few sequences: one thread, no block-wide scans
+        if (threadIdx.x != 0)
+            return;
+        for (int l = 0; l < a.L; ++l) {
+            int64_t t_acc = 0, e_acc = 0;
             a.tile_off[l][0] = 0;
-        }
-        for (int base = 0; base < a.B; base += 1024) {
-            const int b = base + threadIdx.x;
-            int64_t t = 0;
-            if (b < a.B) {
+            if (l > 0 && a.elem_off[l])
+                a.elem_off[l][0] = 0;
+            for (int b = 0; b < a.B; ++b) {
                 int64_t cn = a.y_off[b + 1] - a.y_off[b] + a.extra;
-                for (int q = 0; q <= l; ++q)
-                    cn = (cn + a.TS[q] - 1) / a.TS[q];
-                t = cn;
+                for (int q = 0; q < l; ++q)
+                    cn = (cn + a.D[q] - 1) / a.D[q];
+                t_acc += (cn + a.TS[l] - 1) / a.TS[l];
+                e_acc += cn;
+                a.tile_off[l][b + 1] = t_acc;
+                if (l > 0 && a.elem_off[l])
+                    a.elem_off[l][b + 1] = e_acc;
             }
-            __syncthreads();
-            sh[threadIdx.x] = t;
-            for (int d = 1; d < 1024; d <<= 1) {
-                __syncthreads();
-                const int64_t v = (int)threadIdx.x >= d ? sh[threadIdx.x - d] : 0;
-                __syncthreads();
-                sh[threadIdx.x] += v;
-            }
-            __syncthreads();
-            if (b < a.B)
-                a.tile_off[l][b + 1] = carry + sh[threadIdx.x];
-            __syncthreads();
-            if (threadIdx.x == 0)
-                carry += sh[1023];
-            __syncthreads();
         }
+        return;
+    }
+    for (int l = 0; l < a.L; ++l) {
+        // elements of sequence b at level l
+        auto elems = [&](int b) {
+            int64_t cn = a.y_off[b + 1] - a.y_off[b] + a.extra;
+            for (int q = 0; q < l; ++q)
+                cn = (cn + a.D[q] - 1) / a.D[q];
+            return cn;
+        };
+        plan_offsets(a.B, a.tile_off[l], sh, carry,
+                     [&](int b) { return (elems(b) + a.TS[l] - 1) / a.TS[l]; });
+        if (l > 0 && a.elem_off[l])
+            plan_offsets(a.B, a.elem_off[l], sh, carry, elems);
     }
 }
 
-int launch_plan(const Ctx &c, const ScanShape &sh, int extra, int64_t *const *tile_off)
+int launch_plan(const Ctx &c, const ScanShape &sh, int extra, int64_t *const *tile_off,
+                int64_t *const *elem_off)
 {
     PlanArgs a;
     a.y_off = c.p->y_off;
@@ -185,8 +230,11 @@ int launch_plan(const Ctx &c, const ScanShape &sh, int extra, int64_t *const *ti
     a.extra = extra;
     a.L = sh.L;
     for (int l = 0; l < kMaxLevels; ++l) {
-        a.TS[l] = l < sh.L ? (int64_t)sh.T[l] * sh.E[l] : 1;
-        a.tile_off[l] = l < sh.L ? tile_off[l] : nullptr;
+        const bool in = l < sh.L;
+        a.TS[l] = in ? (int64_t)sh.T[l] * sh.E[l] : 1;
+        a.D[l] = in ? (sh.flat[l] ? sh.E[l] : a.TS[l]) : 1;
+        a.tile_off[l] = in ? tile_off[l] : nullptr;
+        a.elem_off[l] = in && elem_off ? elem_off[l] : nullptr;
     }
     hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, c.s, a);
     return hip_check(hipGetLastError(), "plan launch");

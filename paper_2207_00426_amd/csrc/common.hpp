@@ -66,17 +66,25 @@ struct Ctx {
     hipStream_t s;
 };
 
-// shape of one scan (filter: n_b elements per sequence, smoother: n_b + 1)
+// shape of one scan (filter: n_b elements per sequence, smoother: n_b + 1).
+// Level l has tiles of T[l] * E[l] elements, one block of T[l] threads each.
+// A tree level hands one aggregate per tile to the level above; a flat level
+// (flat[l], never the top) hands up every thread's aggregate and runs no
+// in-tile tree.
 struct ScanShape {
     int L = 0;
-    int T[kMaxLevels];
-    int E[kMaxLevels];
-    int64_t ntiles[kMaxLevels];
-    int64_t nelem[kMaxLevels];
+    int T[kMaxLevels] = {};
+    int E[kMaxLevels] = {};
+    int flat[kMaxLevels] = {};
+    int64_t ntiles[kMaxLevels] = {};
+    int64_t nelem[kMaxLevels] = {};
 };
 
-ScanShape plan_scan(const Ctx &c, int extra, int T0, int E0, int Tup, int Eup);
-int launch_plan(const Ctx &c, const ScanShape &sh, int extra, int64_t *const *tile_off);
+ScanShape plan_scan(const Ctx &c, int extra, int T0, int E0, int Tup, int Eup, bool flat0);
+// device tile offsets of every level and, where elem_off is given, the
+// element offsets of every level >= 1 (both [B + 1] per level)
+int launch_plan(const Ctx &c, const ScanShape &sh, int extra, int64_t *const *tile_off,
+                int64_t *const *elem_off = nullptr);
 // per-sequence sums of step terms (two deterministic stages); the workspace
 // part (seq_sum_bytes) comes from the caller
 size_t seq_sum_bytes(const Ctx &c, int nc);

@@ -321,7 +321,7 @@ static int run_fscan(const Ctx &c, const IftBufs<S> &w)
     FiltDst<D, 5> dst{C::marg_ref2(w.mf, w.Pf, c.T_x), c.p->y_off};
     StartPreCov<D, 5> st{w.m0d, w.N0d};
     RefSrc<FSC, FElemRef<D, 5>, true> src{w.fel};
-    return C::template run_scan<FSC>(c, sh, sw, 0, src, dst, st, &C::felem_ref);
+    return C::template run_scan<FSC, C::kFlatF>(c, sh, sw, 0, src, dst, st, &C::felem_ref);
 }
 
 template <typename S>

@@ -19,7 +19,7 @@ int run_sscan(const Ctx &c, const IftBufs<S> &w)
                                    C::selem_ref(stash, c.T_x), c.p->y_off};
     SmoothDst<D, 5> dst{C::marg_ref2(w.nm, w.nP, c.T_x)};
     StartPre<D, 5> st{nullptr, nullptr};
-    return C::template run_scan<SSC>(c, sh, sw, 1, src, dst, st, &C::selem_ref);
+    return C::template run_scan<SSC, C::kFlatS>(c, sh, sw, 1, src, dst, st, &C::selem_ref);
 }
 
 #if !defined(PSS_IFT_T)

@@ -17,14 +17,23 @@ inline T *mptr(void *p) { return static_cast<T *>(p); }
 // default launch shapes (overridable through pss_problem).  One 64-lane
 // wave per tile; the filter folds 4 elements per thread, the smoother 2 (its
 // operator is cheaper, and with 2 its level-0 reads and stash writes stay
-// closer to whole cache lines); the upper levels fold 2.
+// closer to whole cache lines).  The filter's finest level is flat: its
+// per-thread aggregates are the next level's elements, so no in-tile tree
+// runs there (a tree step keeps the whole wave busy for one operator while
+// half of its lanes or fewer have work); its next level, n/4 elements, folds
+// 4 per thread.  The smoother's operator is cheap next to its element
+// construction, so its finest level keeps the tree and saves a level; its
+// upper levels fold 2.
 template <typename T, int NX>
 struct Defaults {
     static constexpr int T0 = 64;
     static constexpr int E0_filter = 4;
     static constexpr int E0_smoother = 2;
     static constexpr int Tup = 64;
-    static constexpr int Eup = 2;
+    static constexpr int Eup_filter = 4;
+    static constexpr int Eup_smoother = 2;
+    static constexpr bool flat_filter = true;
+    static constexpr bool flat_smoother = false;
 };
 
 template <typename T, int NX, int NY>
@@ -33,6 +42,8 @@ struct Core {
     using SS = SmootherScan<T, NX>;
     static constexpr int P = tri_size(NX);
     static constexpr int PY = tri_size(NY);
+    static constexpr bool kFlatF = Defaults<T, NX>::flat_filter;
+    static constexpr bool kFlatS = Defaults<T, NX>::flat_smoother;
 
     // ------------------------------------------------------------------
     static void shapes(const Ctx &c, bool smoother, int &T0, int &E0, int &Tup, int &Eup)
@@ -42,7 +53,7 @@ struct Core {
                                  : (smoother ? Defaults<T, NX>::E0_smoother
                                              : Defaults<T, NX>::E0_filter);
         Tup = Defaults<T, NX>::Tup;
-        Eup = Defaults<T, NX>::Eup;
+        Eup = smoother ? Defaults<T, NX>::Eup_smoother : Defaults<T, NX>::Eup_filter;
         if (Tup > T0)
             Tup = T0;
     }
@@ -51,9 +62,10 @@ struct Core {
     template <class Op>
     struct ScanWs {
         int64_t *tile_off[kMaxLevels];
+        int64_t *elem_off[kMaxLevels]; // element offsets of level l >= 1
         T *agg[kMaxLevels];  // elements of level l >= 1
         T *pre[kMaxLevels];  // exclusive prefixes of level l >= 1
-        T *tree[kMaxLevels]; // LDS tree of level l < L-1
+        T *tree[kMaxLevels]; // LDS tree of a tree level l < L-1
     };
 
     template <class Op>
@@ -63,11 +75,13 @@ struct Core {
         for (int l = 0; l < sh.L; ++l)
             w.tile_off[l] = cv.template take<int64_t>(c.B + 1);
         for (int l = 1; l < sh.L; ++l) {
+            w.elem_off[l] = cv.template take<int64_t>(c.B + 1);
             w.agg[l] = cv.template take<T>((size_t)Op::NE * sh.nelem[l]);
             w.pre[l] = cv.template take<T>((size_t)Op::NP * sh.nelem[l]);
         }
         for (int l = 0; l + 1 < sh.L; ++l)
-            w.tree[l] = cv.template take<T>((size_t)Op::NE * sh.ntiles[l] * sh.T[l]);
+            if (!sh.flat[l])
+                w.tree[l] = cv.template take<T>((size_t)Op::NE * sh.ntiles[l] * sh.T[l]);
         return w;
     }
 
@@ -149,28 +163,38 @@ struct Core {
                          "hipFuncSetAttribute");
     }
 
-    // generic multi-level scan driver
-    template <class Op, class Src0, class Dst0, class AggRef, class Start>
+    // generic multi-level scan driver; Flat: level 0 may be flat (then it
+    // is, see plan_scan, and level 1 is stored tile-interleaved)
+    template <class Op, bool Flat, class Src0, class Dst0, class AggRef, class Start>
     static int run_scan(const Ctx &c, const ScanShape &sh, const ScanWs<Op> &w, int extra,
                         const Src0 &src0, const Dst0 &dst0, const Start &start,
                         AggRef (*agg_ref)(T *, int64_t))
     {
-        int rc = launch_plan(c, sh, extra, w.tile_off);
+        int rc = launch_plan(c, sh, extra, w.tile_off, w.elem_off);
         if (rc)
             return rc;
         using LvSrc = RefSrc<Op, AggRef>;
+        using LvSrcI = RefSrc<Op, AggRef, true>;
         using LvDst = PreDst<Op, MargRef<T, NX>>;
         auto geom = [&](int l) {
             LevelGeom g;
             g.y_off = c.p->y_off;
-            g.prev_tiles = l > 0 ? w.tile_off[l - 1] : nullptr;
+            g.elem_off = l > 0 ? w.elem_off[l] : nullptr;
             g.tile_off = w.tile_off[l];
             g.level = l;
             g.extra = extra;
             g.B = c.B;
             g.E = sh.E[l];
-            g.stage = l == 0 && scan_stage(Op::NE, Op::NP, sh.T[l], sh.E[l], sizeof(T));
+            g.stage = scan_stage(Op::NE, Op::NP, sh.T[l], sh.E[l], sizeof(T));
             return g;
+        };
+        // calls launch(src) with the element source of level l >= 1
+        auto with_src = [&](int l, auto &&launch) -> int {
+            if constexpr (Flat) {
+                if (l == 1 && sh.flat[0])
+                    return launch(LvSrcI{agg_ref(w.agg[l], sh.nelem[l])});
+            }
+            return launch(LvSrc{agg_ref(w.agg[l], sh.nelem[l])});
         };
         // up-sweeps of the lower levels
         for (int l = 0; l + 1 < sh.L; ++l) {
@@ -180,18 +204,34 @@ struct Core {
             const size_t lb = lds_bytes<Op>(sh.T[l], sh.E[l], g.stage);
             KTime kt(c.s, Op::name, "up", l);
             if (l == 0) {
-                auto k = k_scan_up<Op, Src0, AggRef>;
-                if ((rc = prep_lds(k, lb)))
-                    return rc;
-                hipLaunchKernelGGL(k, dim3((unsigned)sh.ntiles[l]), dim3(sh.T[l]), lb, c.s, g,
-                                   src0, agg, w.tree[l], tree_ld);
+                bool flat = false;
+                if constexpr (Flat) {
+                    if ((flat = sh.flat[0])) {
+                        auto k = k_scan_up_flat<Op, Src0, AggRef>;
+                        if ((rc = prep_lds(k, lb)))
+                            return rc;
+                        hipLaunchKernelGGL(k, dim3((unsigned)sh.ntiles[l]), dim3(sh.T[l]), lb,
+                                           c.s, g, src0, agg, w.elem_off[1], sh.T[1], sh.E[1]);
+                    }
+                }
+                if (!flat) {
+                    auto k = k_scan_up<Op, Src0, AggRef>;
+                    if ((rc = prep_lds(k, lb)))
+                        return rc;
+                    hipLaunchKernelGGL(k, dim3((unsigned)sh.ntiles[l]), dim3(sh.T[l]), lb, c.s,
+                                       g, src0, agg, w.tree[l], tree_ld);
+                }
             } else {
-                LvSrc s{agg_ref(w.agg[l], sh.nelem[l])};
-                auto k = k_scan_up<Op, LvSrc, AggRef>;
-                if ((rc = prep_lds(k, lb)))
+                rc = with_src(l, [&](auto s) -> int {
+                    auto k = k_scan_up<Op, decltype(s), AggRef>;
+                    if (int r = prep_lds(k, lb))
+                        return r;
+                    hipLaunchKernelGGL(k, dim3((unsigned)sh.ntiles[l]), dim3(sh.T[l]), lb, c.s,
+                                       g, s, agg, w.tree[l], tree_ld);
+                    return 0;
+                });
+                if (rc)
                     return rc;
-                hipLaunchKernelGGL(k, dim3((unsigned)sh.ntiles[l]), dim3(sh.T[l]), lb, c.s, g, s,
-                                   agg, w.tree[l], tree_ld);
             }
             if ((rc = hip_check(hipGetLastError(), "scan up launch")))
                 return rc;
@@ -209,13 +249,17 @@ struct Core {
                 hipLaunchKernelGGL(k, dim3((unsigned)sh.ntiles[l]), dim3(sh.T[l]), lb, c.s, g,
                                    src0, dst0, start);
             } else {
-                LvSrc s{agg_ref(w.agg[l], sh.nelem[l])};
                 LvDst d{marg_ref(w.pre[l], sh.nelem[l])};
-                auto k = k_scan_top<Op, LvSrc, LvDst, Start>;
-                if ((rc = prep_lds(k, lb)))
+                rc = with_src(l, [&](auto s) -> int {
+                    auto k = k_scan_top<Op, decltype(s), LvDst, Start>;
+                    if (int r = prep_lds(k, lb))
+                        return r;
+                    hipLaunchKernelGGL(k, dim3((unsigned)sh.ntiles[l]), dim3(sh.T[l]), lb, c.s,
+                                       g, s, d, start);
+                    return 0;
+                });
+                if (rc)
                     return rc;
-                hipLaunchKernelGGL(k, dim3((unsigned)sh.ntiles[l]), dim3(sh.T[l]), lb, c.s, g, s,
-                                   d, start);
             }
             if ((rc = hip_check(hipGetLastError(), "scan top launch")))
                 return rc;
@@ -228,19 +272,35 @@ struct Core {
             MargRef<T, NX> pin = marg_ref(w.pre[l + 1], sh.nelem[l + 1]);
             KTime kt(c.s, Op::name, "down", l);
             if (l == 0) {
-                auto k = k_scan_down<Op, Src0, Dst0, MargRef<T, NX>>;
-                if ((rc = prep_lds(k, lb)))
-                    return rc;
-                hipLaunchKernelGGL(k, dim3((unsigned)sh.ntiles[l]), dim3(sh.T[l]), lb, c.s, g,
-                                   src0, dst0, w.tree[l], tree_ld, pin);
+                bool flat = false;
+                if constexpr (Flat) {
+                    if ((flat = sh.flat[0])) {
+                        auto k = k_scan_down_flat<Op, Src0, Dst0, MargRef<T, NX>>;
+                        if ((rc = prep_lds(k, lb)))
+                            return rc;
+                        hipLaunchKernelGGL(k, dim3((unsigned)sh.ntiles[l]), dim3(sh.T[l]), lb,
+                                           c.s, g, src0, dst0, w.elem_off[1], pin);
+                    }
+                }
+                if (!flat) {
+                    auto k = k_scan_down<Op, Src0, Dst0, MargRef<T, NX>>;
+                    if ((rc = prep_lds(k, lb)))
+                        return rc;
+                    hipLaunchKernelGGL(k, dim3((unsigned)sh.ntiles[l]), dim3(sh.T[l]), lb, c.s,
+                                       g, src0, dst0, w.tree[l], tree_ld, pin);
+                }
             } else {
-                LvSrc s{agg_ref(w.agg[l], sh.nelem[l])};
                 LvDst d{marg_ref(w.pre[l], sh.nelem[l])};
-                auto k = k_scan_down<Op, LvSrc, LvDst, MargRef<T, NX>>;
-                if ((rc = prep_lds(k, lb)))
+                rc = with_src(l, [&](auto s) -> int {
+                    auto k = k_scan_down<Op, decltype(s), LvDst, MargRef<T, NX>>;
+                    if (int r = prep_lds(k, lb))
+                        return r;
+                    hipLaunchKernelGGL(k, dim3((unsigned)sh.ntiles[l]), dim3(sh.T[l]), lb, c.s,
+                                       g, s, d, w.tree[l], tree_ld, pin);
+                    return 0;
+                });
+                if (rc)
                     return rc;
-                hipLaunchKernelGGL(k, dim3((unsigned)sh.ntiles[l]), dim3(sh.T[l]), lb, c.s, g, s,
-                                   d, w.tree[l], tree_ld, pin);
             }
             if ((rc = hip_check(hipGetLastError(), "scan down launch")))
                 return rc;
@@ -254,13 +314,13 @@ struct Core {
     {
         int T0, E0, Tup, Eup;
         shapes(c, false, T0, E0, Tup, Eup);
-        return plan_scan(c, 0, T0, E0, Tup, Eup);
+        return plan_scan(c, 0, T0, E0, Tup, Eup, kFlatF);
     }
     static ScanShape smoother_shape(const Ctx &c)
     {
         int T0, E0, Tup, Eup;
         shapes(c, true, T0, E0, Tup, Eup);
-        return plan_scan(c, 1, T0, E0, Tup, Eup);
+        return plan_scan(c, 1, T0, E0, Tup, Eup, kFlatS);
     }
 
     static size_t fscan_bytes(const Ctx &c)
@@ -304,17 +364,17 @@ struct Core {
             auto wc = carve_scan<FSC>(cc, c, sh);
             if (ilv) {
                 RefSrc<FSC, FElemRef<T, NX>, true> src{er};
-                return run_scan<FSC>(c, sh, wc, 0, src, dst, stc, &felem_ref);
+                return run_scan<FSC, kFlatF>(c, sh, wc, 0, src, dst, stc, &felem_ref);
             }
             RefSrc<FSC, FElemRef<T, NX>> src{er};
-            return run_scan<FSC>(c, sh, wc, 0, src, dst, stc, &felem_ref);
+            return run_scan<FSC, kFlatF>(c, sh, wc, 0, src, dst, stc, &felem_ref);
         }
         if (ilv) {
             RefSrc<FS, FElemRef<T, NX>, true, LZ> src{er};
-            return run_scan<FS>(c, sh, w, 0, src, dst, st, &felem_ref);
+            return run_scan<FS, kFlatF>(c, sh, w, 0, src, dst, st, &felem_ref);
         }
         RefSrc<FS, FElemRef<T, NX>, false, LZ> src{er};
-        return run_scan<FS>(c, sh, w, 0, src, dst, st, &felem_ref);
+        return run_scan<FS, kFlatF>(c, sh, w, 0, src, dst, st, &felem_ref);
     }
 
     static int sscan(const Ctx &c, const pss_gamma *g, const void *mf, const void *Nf, void *ms,
@@ -332,11 +392,11 @@ struct Core {
             auto wc = carve_scan<SSC>(cc, c, sh);
             SmootherSrc<T, NX, NY, true> src{gamma_ref(g, c.T_y), marg_ref2(mf, Nf, c.T_x),
                                              selem_ref(stash, c.T_x), c.p->y_off};
-            return run_scan<SSC>(c, sh, wc, 1, src, dst, st, &selem_ref);
+            return run_scan<SSC, kFlatS>(c, sh, wc, 1, src, dst, st, &selem_ref);
         }
         SmootherSrc<T, NX, NY> src{gamma_ref(g, c.T_y), marg_ref2(mf, Nf, c.T_x),
                                    selem_ref(stash, c.T_x), c.p->y_off};
-        return run_scan<SS>(c, sh, w, 1, src, dst, st, &selem_ref);
+        return run_scan<SS, kFlatS>(c, sh, w, 1, src, dst, st, &selem_ref);
     }
 
     static int felem(const Ctx &c, const pss_gamma *g, const void *y, const pss_felem *out,
@@ -355,7 +415,9 @@ struct Core {
         er.eta = mptr<T>(out->eta);
         er.Z = mptr<T>(out->Z);
         er.ld = c.T_y;
-        const int tb = 128;
+        // a block covers a whole level-0 tile (64 x 4): the strided reads of
+        // its tile-interleaved elements meet the same cache lines in one L2
+        const int tb = 256;
         KTime kt(c.s, cov ? "filter_elements_cov" : "filter_elements", "", 0);
         const dim3 grid((unsigned)((c.T_y + tb - 1) / tb));
         if (cov)

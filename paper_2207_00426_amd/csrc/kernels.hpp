@@ -463,7 +463,7 @@ PSS_INL void tree_down(typename Op::T *lds, int Tb, int nvalid, const typename O
 // geometry of one scan level
 struct LevelGeom {
     const int64_t *y_off;      // level 0: measurement offsets
-    const int64_t *prev_tiles; // level >= 1: tile offsets of the level below
+    const int64_t *elem_off;   // level >= 1: this level's element offsets [B + 1]
     const int64_t *tile_off;   // this level's tile offsets [B + 1]
     int level;
     int extra; // level 0: elements per sequence = n_b + extra, element offset y_off[b] + extra*b
@@ -480,8 +480,8 @@ PSS_INL void seq_range(const LevelGeom &g, int b, int64_t &off, int64_t &cnt)
         off = a + (int64_t)g.extra * b;
         cnt = z - a + g.extra;
     } else {
-        off = g.prev_tiles[b];
-        cnt = g.prev_tiles[b + 1] - off;
+        off = g.elem_off[b];
+        cnt = g.elem_off[b + 1] - off;
     }
 }
 
@@ -598,14 +598,20 @@ struct SmootherSrc {
 // --- output sinks -------------------------------------------------------------
 // put(ti, p, excl, incl) receives the exclusive and inclusive prefix of
 // element p.  A sink with `stageable` also has first(ti, excl), called with
-// the exclusive prefix of a sequence's first element, and store(ti, p, incl):
-// apply_phase may then collect a tile's inclusive prefixes in LDS and store
-// them with consecutive lanes on consecutive elements.
+// the exclusive prefix of a sequence's first element, and store(ti, p, x):
+// apply_phase may then collect a tile's prefixes in LDS (the exclusive ones
+// when `stage_excl`, else the inclusive ones) and store them with
+// consecutive lanes on consecutive elements.
 // levels >= 1: exclusive prefix of each element
 template <class Op, class Ref>
 struct PreDst {
-    static constexpr bool stageable = false;
+    static constexpr bool stageable = true, stage_excl = true;
     Ref ref;
+    PSS_INL void first(const TileInfo &ti, const typename Op::Pre &excl) const {}
+    PSS_INL void store(const TileInfo &ti, int64_t p, const typename Op::Pre &excl) const
+    {
+        ref.store(ti.off + p, excl);
+    }
     PSS_INL void put(const TileInfo &ti, int64_t p, const typename Op::Pre &excl,
                      const typename Op::Pre &incl) const
     {
@@ -618,7 +624,7 @@ struct PreDst {
 // prior)
 template <typename T, int NX>
 struct FiltDst {
-    static constexpr bool stageable = true;
+    static constexpr bool stageable = true, stage_excl = false;
     MargRef<T, NX> out; // ld = T_x
     const int64_t *y_off;
     PSS_INL void first(const TileInfo &ti, const Marg<T, NX> &excl) const
@@ -642,7 +648,7 @@ struct FiltDst {
 // of state n - p
 template <typename T, int NX>
 struct SmoothDst {
-    static constexpr bool stageable = true;
+    static constexpr bool stageable = true, stage_excl = false;
     MargRef<T, NX> out;
     PSS_INL void first(const TileInfo &ti, const Marg<T, NX> &excl) const {}
     PSS_INL void store(const TileInfo &ti, int64_t p, const Marg<T, NX> &incl) const
@@ -808,7 +814,10 @@ PSS_INL void apply_phase(const LevelGeom &g, const TileInfo &ti, const Src &src,
                     src_apply<Op>(src, ti, p, P, Q);
                     if (p == 0)
                         dst.first(ti, P);
-                    lds_put(Q, lds, ld, (int)(p - ti.start));
+                    if constexpr (Dst::stage_excl)
+                        lds_put(P, lds, ld, (int)(p - ti.start));
+                    else
+                        lds_put(Q, lds, ld, (int)(p - ti.start));
                     P = Q;
                 }
             }
@@ -872,6 +881,48 @@ __global__ __launch_bounds__(256) void k_scan_down(LevelGeom g, Src src, Dst dst
     apply_phase<Op>(g, ti, src, dst, lds, Tb);
 }
 
+// flat level, first half: every thread's fold is element v of the next
+// level (v = the thread's rank in its sequence), stored tile-interleaved for
+// that level's tiles of nT threads x nE elements; no tree
+template <class Op, class Src, class AggRef>
+__global__ __launch_bounds__(256) void k_scan_up_flat(LevelGeom g, Src src, AggRef agg,
+                                                      const int64_t *next_off, int nT, int nE)
+{
+    using T = typename Op::T;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *lds = reinterpret_cast<T *>(smem_raw);
+    const int Tb = blockDim.x;
+    const TileInfo ti = tile_info(g);
+    fold_phase<Op>(g, ti, src, lds, Tb);
+    if (threadIdx.x < ti.nvalid) {
+        const int64_t v = ti.start / g.E + threadIdx.x;
+        const int64_t off = next_off[ti.b], cnt = next_off[ti.b + 1] - off;
+        const int64_t TS = (int64_t)nT * nE, start = (v / TS) * TS;
+        const int tcnt = (int)((cnt - start) < TS ? (cnt - start) : TS);
+        const int64_t slot = off + start + ilv((int)(v - start), tcnt, nE);
+        Op::copy_v(Op::slot(lds, Tb, threadIdx.x), view_of(agg, slot));
+    }
+}
+
+// flat level, second half: each thread takes its exclusive prefix from the
+// level above, then applies and emits as a tree level does
+template <class Op, class Src, class Dst, class PreRef>
+__global__ __launch_bounds__(256) void k_scan_down_flat(LevelGeom g, Src src, Dst dst,
+                                                        const int64_t *next_off, PreRef pre_in)
+{
+    using T = typename Op::T;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *lds = reinterpret_cast<T *>(smem_raw);
+    const int Tb = blockDim.x;
+    const TileInfo ti = tile_info(g);
+    if (threadIdx.x < ti.nvalid) {
+        typename Op::Pre P;
+        pre_in.load(next_off[ti.b] + ti.start / g.E + threadIdx.x, P);
+        lds_put(P, lds, Tb, threadIdx.x);
+    }
+    apply_phase<Op>(g, ti, src, dst, lds, Tb);
+}
+
 // top level (one tile per sequence): everything in one kernel
 template <class Op, class Src, class Dst, class Start>
 __global__ __launch_bounds__(256) void k_scan_top(LevelGeom g, Src src, Dst dst, Start start)
@@ -895,8 +946,10 @@ struct PlanArgs {
     int B;
     int extra;
     int L;
-    int64_t TS[kMaxLevels];
+    int64_t TS[kMaxLevels]; // tile size of level l
+    int64_t D[kMaxLevels];  // elements of level l per element of level l + 1
     int64_t *tile_off[kMaxLevels];
+    int64_t *elem_off[kMaxLevels]; // may be null
 };
 
 __global__ __launch_bounds__(1024) void k_plan(PlanArgs a);
@@ -905,7 +958,7 @@ __global__ __launch_bounds__(1024) void k_plan(PlanArgs a);
 // element-wise kernels
 // ---------------------------------------------------------------------------
 template <typename T, int NX, int NY, bool COV = false>
-__global__ __launch_bounds__(128) void k_filter_elements(const int64_t *y_off, int B, int64_t T_y,
+__global__ __launch_bounds__(256) void k_filter_elements(const int64_t *y_off, int B, int64_t T_y,
                                                          GammaRef<T, NX, NY> gam, const T *y,
                                                          const T *m0, const T *N0,
                                                          FElemRef<T, NX> out, int ilv_T,

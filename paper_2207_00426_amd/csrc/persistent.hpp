@@ -323,7 +323,7 @@ PSS_INL void filter_tile(const PArgs<T> &a, const PGroup<T> &G, int64_t gt, T *l
     const int64_t t = gt - G.tile_f[b];
     LevelGeom g;
     g.y_off = G.y_off;
-    g.prev_tiles = nullptr;
+    g.elem_off = nullptr;
     g.tile_off = G.tile_f;
     g.level = 0;
     g.extra = 0;
@@ -377,7 +377,7 @@ PSS_INL void smoother_tile(const PArgs<T> &a, const PGroup<T> &G, int64_t gu, T 
     const int64_t u = gu - G.tile_s[b];
     LevelGeom g;
     g.y_off = G.y_off;
-    g.prev_tiles = nullptr;
+    g.elem_off = nullptr;
     g.tile_off = G.tile_s;
     g.level = 0;
     g.extra = 1;
