@@ -608,6 +608,8 @@ def main():
         E0s = shapes(args.dtype, args.scan_threads, args.scan_elems, True)[1]
         kflops[("slr", 0)] = n * (FLOPS["slr_transition"] + FLOPS["slr_bearings"])
         kflops[("filter_elements", 0)] = n * FLOPS["filter_element"]
+        kflops[("slr_felem", 0)] = n * (FLOPS["slr_transition"] + FLOPS["slr_bearings"] +
+                                         FLOPS["filter_element"])
         kernels = {}
         for key, (calls, tot) in sorted(ktimes.items()):
             avg = tot / calls

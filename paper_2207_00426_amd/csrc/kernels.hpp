@@ -1363,6 +1363,92 @@ __global__ __launch_bounds__(128) void k_slr_ct(const int64_t *y_off, int B, int
     }
 }
 
+// The CT model with cubature (or Taylor, taylor != 0) linearisation fused
+// with the filter elements: one thread per stored element slot i (stored
+// tile-interleaved as k_filter_elements does) linearises its step slot t --
+// the transition at state k and the bearings at state k + 1, as k_slr_ct --
+// and builds the element of that step from the result in registers.  The
+// transition part is stored for the smoother; the measurement part only
+// with store_obs.
+template <typename T, bool COV>
+__global__ __launch_bounds__(256) void k_slr_felem_ct(const int64_t *y_off, int B, int64_t T_y,
+                                                      CTParams<T> P, MargRef<T, 5> nom,
+                                                      const T *y, const T *m0, const T *N0,
+                                                      GammaRef<T, 5, 2> gam, int store_obs,
+                                                      FElemRef<T, 5> out, int ilv_T, int ilv_E,
+                                                      int taylor, int nominal_cov)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= T_y)
+        return;
+    const int b = find_seq(y_off, B, i, 0);
+    int64_t k = i - y_off[b];
+    if (ilv_E > 0) {
+        const int64_t TS = (int64_t)ilv_T * ilv_E, cnt = y_off[b + 1] - y_off[b];
+        const int64_t start = (k / TS) * TS;
+        const int tcnt = (int)((cnt - start) < TS ? (cnt - start) : TS);
+        k = start + ilv_inv((int)(k - start), tcnt, ilv_E);
+    }
+    const int64_t t = y_off[b] + k; // step slot
+    const int64_t s = t + b;        // state slot of state k
+    auto load_nom = [&](int64_t st, Marg<T, 5> &mg) {
+        nom.load(st, mg);
+        if (nominal_cov && !taylor) {
+            T Pm[5][5], L[5][5];
+            sym_full(Pm, [&](int r, int q) { return mg.N[r][q]; });
+            chol_lower(Pm, L);
+#pragma unroll
+            for (int r = 0; r < 5; ++r)
+#pragma unroll
+                for (int q = 0; q <= r; ++q)
+                    mg.N[r][q] = L[r][q];
+        }
+    };
+    T F[5][5], c[5], SL[5][5];
+    {
+        Marg<T, 5> mg;
+        load_nom(s, mg);
+        if (taylor)
+            ct_taylor_transition(P, mg, F, c, SL);
+        else
+            ct_slr_transition(P, mg, F, c, SL);
+    }
+    gam.store_trans(t, F, c, SL);
+    T yy[2] = {y[t], y[T_y + t]};
+    T H[2][5], d[2], SO[2][2];
+    {
+        Marg<T, 5> mg;
+        load_nom(s + 1, mg);
+        if (taylor)
+            ct_taylor_bearings(P, mg, yy, H, d, SO);
+        else
+            ct_slr_bearings(P, mg, yy, H, d, SO);
+    }
+    if (store_obs)
+        gam.store_obs(t, H, d, SO);
+    FElem<T, 5> e;
+    if (k == 0) {
+        T m[5], N[5][5];
+#pragma unroll
+        for (int r = 0; r < 5; ++r) {
+            m[r] = m0[r];
+#pragma unroll
+            for (int q = 0; q <= r; ++q)
+                N[r][q] = N0[tri_idx(r, q)];
+        }
+        if constexpr (COV)
+            filter_element_first_cov(m, N, F, c, SL, H, d, SO, yy, e);
+        else
+            filter_element_first(m, N, F, c, SL, H, d, SO, yy, e);
+    } else {
+        if constexpr (COV)
+            filter_element_cov(F, c, SL, H, d, SO, yy, e);
+        else
+            filter_element(F, c, SL, H, d, SO, yy, e);
+    }
+    out.store(i, e);
+}
+
 // the CT model with the unscented or Gauss-Hermite rule (one thread per
 // state, the slots as k_slr_ct)
 template <typename T>
