@@ -8,6 +8,23 @@
 
 namespace pss {
 
+// launch shapes of the dual-number scans: the tree at every level.  A dual
+// scan kernel runs one tile per CU (4x the registers and LDS of its value
+// type), so the extra level that a flat finest level brings costs more than
+// the tree it saves at the sizes this gradient is used on (n = 1000: 196 ms
+// per call flat, 177 ms with the tree).
+template <typename S, int NX>
+struct Defaults<Dual<S, 3>, NX> {
+    static constexpr int T0 = 64;
+    static constexpr int E0_filter = 4;
+    static constexpr int E0_smoother = 2;
+    static constexpr int Tup = 64;
+    static constexpr int Eup_filter = 2;
+    static constexpr int Eup_smoother = 2;
+    static constexpr bool flat_filter = false;
+    static constexpr bool flat_smoother = false;
+};
+
 template <typename S>
 using IftC = Core<Dual<S, 3>, 5, 2>;
 

@@ -92,6 +92,36 @@ def test_linear_filter_smoother_multilevel(nx, ny, tag):
         assert em < tol["m"] and eP < tol["P"], ("smoother", bi, em, eP)
 
 
+def test_linear_many_sequences_default_shapes():
+    """150 ragged sequences (more than 64, so the level planner takes its
+    block-wide path) at the default launch shapes: the filter's flat finest
+    level, its interleaved next level and the smoother's tree, per sequence
+    against the oracle."""
+    rng = np.random.default_rng(77)
+    lengths = rng.integers(1, 700, size=150)
+    lengths[:3] = [1, 256, 257]
+    G, m0, N0, y, y_off = _linear_case(4, 2, lengths, 4242)
+    ref = _oracle_linear(G, m0, N0, y, y_off)
+    b = pss.Batch(pss.MODEL_LINEAR, torch.float64, 4, 2, y_off, m0, N0, device=DEV)
+    g = b.gamma_from_numpy(G)
+    yd = pss.to_soa(y, torch.float64, DEV)
+    el = pss.sqrt_filter_elements(b, g, yd)
+    mf, Nf = pss.sqrt_filter_scan(b, el)
+    ms, Ns = pss.sqrt_smoother_scan(b, g, mf, Nf)
+    torch.cuda.synchronize()
+    tol = par.TOL["f64"]
+    mfa, Nfa = pss.marg_from_soa(mf, Nf, 4)
+    msa, Nsa = pss.marg_from_soa(ms, Ns, 4)
+    for bi, (r, a1, a2, a3, a4) in enumerate(zip(ref, _split_states(mfa, y_off),
+                                                 _split_states(Nfa, y_off),
+                                                 _split_states(msa, y_off),
+                                                 _split_states(Nsa, y_off))):
+        em, eP = par.marg_errs(a1, a2, r["mf"], r["Nf"])
+        assert em < tol["m"] and eP < tol["P"], ("filter", bi, em, eP)
+        em, eP = par.marg_errs(a3, a4, r["ms"], r["Ns"])
+        assert em < tol["m"] and eP < tol["P"], ("smoother", bi, em, eP)
+
+
 @pytest.mark.parametrize("nx,ny", [(5, 2), (2, 3), (3, 3)])
 def test_filter_elements_match_tables_1_2(nx, ny):
     lengths = np.array([7, 1, 4])
