@@ -216,3 +216,41 @@ def test_fixed_point_gradient_is_validated_before_any_hip_call(L):
                                  None) == -1
     assert L.pss_loglik_grad_ift(ctypes.byref(p), d, d, d, 5, d, d, None, d, 16, None) == -3
     assert "workspace" in pss.last_error()
+
+
+def _scan_ws_bytes(plan, B, NE, NP, esz):
+    """Workspace of one scan as the library carves it: tile offsets of every
+    level; element offsets, elements and exclusive prefixes of every level
+    above the finest; the LDS-tree copies of the lower tree levels (each
+    piece 256-byte aligned)."""
+    al = lambda x: (x + 255) // 256 * 256
+    used = 0
+    for l, (T, E, elems, tiles, threads, flat) in enumerate(plan):
+        used += al((B + 1) * 8)
+        if l > 0:
+            used += al((B + 1) * 8) + al(NE * elems * esz) + al(NP * elems * esz)
+        if l + 1 < len(plan) and not flat:
+            used += al(NE * tiles * T * esz)
+    return used
+
+
+@pytest.mark.parametrize("lengths", [[1], [255], [256], [257], [10 ** 6], [150, 37, 400, 1],
+                                     [3000] * 70])
+@pytest.mark.parametrize("T,E", [(0, 0), (128, 1), (256, 8)])
+def test_bench_scan_plan_mirrors_the_library(L, lengths, T, E):
+    """bench.py prices every scan kernel from its own mirror of the level plan
+    (flat finest filter level, tree levels above, the smoother's tree): the
+    workspace that mirror implies is exactly what the library asks for."""
+    import bench
+    y_off = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+    b = _cpu_batch(nx=5, ny=2, m0=np.zeros(5), N0=np.eye(5), y_off=y_off, scan_threads=T,
+                   scan_elems=E)
+    B = len(lengths)
+    fplan = bench.scan_plan(lengths, *bench.shapes("f64", T, E, False))
+    assert fplan[0][5] and not any(lv[5] for lv in fplan[1:])
+    assert pss.workspace_size(b, "filter_scan") == _scan_ws_bytes(fplan, B, 65, 20, 8)
+    splan = bench.scan_plan([n + 1 for n in lengths], *bench.shapes("f64", T, E, True))
+    assert not any(lv[5] for lv in splan)
+    T_x = int(y_off[-1]) + B
+    stash = (45 * T_x * 8 + 255) // 256 * 256
+    assert pss.workspace_size(b, "smoother_scan") == _scan_ws_bytes(splan, B, 45, 20, 8) + stash
