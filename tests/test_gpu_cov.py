@@ -67,6 +67,35 @@ def test_cov_form_ct_every_pass():
     assert par.ll_err(float(ll.item()), ll_ref) < par.TOL["f64"]["ll"]
 
 
+@pytest.mark.parametrize("lin", ["cubature", "taylor"])
+def test_cov_form_ct_fp32_each_pass_from_its_own_nominal(lin):
+    """FP32 covariance form (in FP32 the linearisation and the filter
+    elements run as one kernel): every pass against one oracle pass taken
+    from the GPU's own nominal before it, so FP32 error does not compound,
+    within the FP32 bar; then the log-likelihood at the final nominal."""
+    w = wl.ct_single(1000, seed=1)
+    prm = orc.ct_params()
+    b = pss.Batch.ct(w.y_off, w.model, dtype=torch.float32, device=DEV, form="cov",
+                     linearization=lin)
+    yd = pss.to_soa(w.y, torch.float32, DEV)
+    m, N = b.prior_nominal()
+    tol = par.TOL["f32"]
+    for i in range(5):
+        m_in, P_in = _cov_from_soa(m, N, 5)
+        ref = orc.ct_ipls(prm, w.model.m0, np.eye(5), w.y, 1, ms_init=m_in,
+                          Ns_init=np.linalg.cholesky(P_in.astype(np.float64)), method=lin)
+        pss.ipls_iterate(b, yd, 1, m, N)
+        torch.cuda.synchronize()
+        ma, Pa = _cov_from_soa(m, N, 5)
+        em, eP = _errs(ma, Pa, ref["ms"], ref["Ns"])
+        assert em < tol["m"] and eP < tol["P"], (lin, i, em, eP)
+    ma, Pa = _cov_from_soa(m, N, 5)
+    ll = pss.loglik(b, yd, m, N)
+    ll_ref = orc.ct_loglik(prm, w.model.m0, np.eye(5), w.y, ma,
+                           np.linalg.cholesky(Pa.astype(np.float64)), method=lin)
+    assert par.ll_err(float(ll.item()), ll_ref) < tol["ll"]
+
+
 def test_fp32_square_root_form_does_not_diverge_where_covariance_form_does():
     # informative bearings (sigma 5e-4) and slow dynamics (q 1e-3): the
     # setting of the robustness comparison where the covariance form loses
