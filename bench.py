@@ -86,14 +86,14 @@ def log(msg):
     print("bench: " + msg, file=sys.stderr, flush=True)
 
 
-def scan_plan(lengths, T0, E0, Tup, Eup, flat0):
+def scan_plan(lengths, T0, E0, Tup, E1, Eup, flat0):
     """Mirror of the library's level plan: per level (T, E, elements, tiles,
     active threads, flat).  With flat0 the finest level is flat (never the
     top): its threads' aggregates are the next level's elements."""
     cnt = np.asarray(lengths, dtype=np.int64)
     levels = []
     for l in range(8):
-        T, E = (T0, E0) if l == 0 else (Tup, Eup)
+        T, E = (T0, E0) if l == 0 else (Tup, E1 if l == 1 else Eup)
         TS = T * E
         tiles = -(-cnt // TS)
         last = cnt - (tiles - 1) * TS
@@ -107,7 +107,7 @@ def scan_plan(lengths, T0, E0, Tup, Eup, flat0):
     return levels
 
 
-def scan_kernel_flops(op, lengths, T0, E0, Tup, Eup, flat0):
+def scan_kernel_flops(op, lengths, T0, E0, Tup, E1, Eup, flat0):
     """Counted flops of each kernel of one scan, keyed (kernel, level).
 
     Up-sweep (and the first half of the top kernel): the fold and the tile
@@ -121,7 +121,7 @@ def scan_kernel_flops(op, lengths, T0, E0, Tup, Eup, flat0):
     # threads fold combines, elements applies); its trees use the general form
     lcomb = FLOPS.get(op + "_combine_leaf", comb)
     lapp = FLOPS.get(op + "_apply_leaf", app)
-    plan = scan_plan(lengths, T0, E0, Tup, Eup, flat0)
+    plan = scan_plan(lengths, T0, E0, Tup, E1, Eup, flat0)
     out = {}
     for l, (T, E, elems, tiles, threads, flat) in enumerate(plan):
         if flat:
@@ -193,11 +193,11 @@ def copy_probe(stream, dev, reps=5):
 
 
 def shapes(dtype, T_req, E_req, smoother=False):
-    """Mirror of the library's default launch shapes (T0, E0, Tup, Eup, flat
-    finest level)."""
+    """Mirror of the library's default launch shapes (T0, E0, Tup, E1 of level
+    1, Eup of the levels above, flat finest level)."""
     T0 = T_req or 64
     E0 = E_req or (2 if smoother else 4)
-    return T0, E0, min(T0, 64), 2 if smoother else 4, not smoother
+    return T0, E0, min(T0, 64), 2 if smoother else 4, 2, not smoother
 
 
 class Runner:
@@ -601,8 +601,9 @@ def main():
             "loglik_grad": timed(stream, lambda: pss.loglik_grad(b, m, N, yd, ws=R.ws_grad), reps),
         }
         log("stages (ms): " + ", ".join("%s %.3f" % kv for kv in stage.items()))
-        T0, E0, Tup, Eup, flat0 = shapes(args.dtype, args.scan_threads, args.scan_elems)
-        kflops = scan_kernel_flops("filter", [n], T0, E0, Tup, Eup, flat0)
+        fshape = shapes(args.dtype, args.scan_threads, args.scan_elems)
+        T0, E0 = fshape[0], fshape[1]
+        kflops = scan_kernel_flops("filter", [n], *fshape)
         kflops.update(scan_kernel_flops(
             "smoother", [n + 1], *shapes(args.dtype, args.scan_threads, args.scan_elems, True)))
         E0s = shapes(args.dtype, args.scan_threads, args.scan_elems, True)[1]

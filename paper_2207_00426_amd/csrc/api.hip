@@ -109,7 +109,8 @@ KTime::~KTime()
 // ---------------------------------------------------------------------------
 // scan planning (host side mirrors k_plan exactly)
 // ---------------------------------------------------------------------------
-ScanShape plan_scan(const Ctx &c, int extra, int T0, int E0, int Tup, int Eup, bool flat0)
+ScanShape plan_scan(const Ctx &c, int extra, int T0, int E0, int Tup, int E1, int Eup,
+                    bool flat0)
 {
     ScanShape sh;
     std::vector<int64_t> cnt(c.B);
@@ -121,7 +122,7 @@ ScanShape plan_scan(const Ctx &c, int extra, int T0, int E0, int Tup, int Eup, b
     sh.nelem[0] = total;
     for (int l = 0; l < kMaxLevels; ++l) {
         sh.T[l] = l == 0 ? T0 : Tup;
-        sh.E[l] = l == 0 ? E0 : Eup;
+        sh.E[l] = l == 0 ? E0 : (l == 1 ? E1 : Eup);
         const int64_t TS = (int64_t)sh.T[l] * sh.E[l];
         int64_t nt = 0, mx = 0;
         for (int b = 0; b < c.B; ++b) {

@@ -80,7 +80,9 @@ struct ScanShape {
     int64_t nelem[kMaxLevels] = {};
 };
 
-ScanShape plan_scan(const Ctx &c, int extra, int T0, int E0, int Tup, int Eup, bool flat0);
+// level 0 takes (T0, E0), level 1 (Tup, E1), the levels above (Tup, Eup)
+ScanShape plan_scan(const Ctx &c, int extra, int T0, int E0, int Tup, int E1, int Eup,
+                    bool flat0);
 // device tile offsets of every level and, where elem_off is given, the
 // element offsets of every level >= 1 (both [B + 1] per level)
 int launch_plan(const Ctx &c, const ScanShape &sh, int extra, int64_t *const *tile_off,

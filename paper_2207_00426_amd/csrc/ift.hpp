@@ -19,6 +19,8 @@ struct Defaults<Dual<S, 3>, NX> {
     static constexpr int E0_filter = 4;
     static constexpr int E0_smoother = 2;
     static constexpr int Tup = 64;
+    static constexpr int E1_filter = 2;
+    static constexpr int E1_smoother = 2;
     static constexpr int Eup_filter = 2;
     static constexpr int Eup_smoother = 2;
     static constexpr bool flat_filter = false;

@@ -22,16 +22,18 @@ inline T *mptr(void *p) { return static_cast<T *>(p); }
 // per-thread aggregates are the next level's elements, so no in-tile tree
 // runs there (a tree step keeps the whole wave busy for one operator while
 // half of its lanes or fewer have work); its next level, n/4 elements, folds
-// 4 per thread.  The smoother's operator is cheap next to its element
-// construction, so its finest level keeps the tree and saves a level; its
-// upper levels fold 2.
+// 4 per thread, the levels above it 2.  The smoother's operator is cheap
+// next to its element construction, so its finest level keeps the tree and
+// saves a level; its upper levels fold 2.
 template <typename T, int NX>
 struct Defaults {
     static constexpr int T0 = 64;
     static constexpr int E0_filter = 4;
     static constexpr int E0_smoother = 2;
     static constexpr int Tup = 64;
-    static constexpr int Eup_filter = 4;
+    static constexpr int E1_filter = 4;
+    static constexpr int E1_smoother = 2;
+    static constexpr int Eup_filter = 2;
     static constexpr int Eup_smoother = 2;
     static constexpr bool flat_filter = true;
     static constexpr bool flat_smoother = false;
@@ -47,13 +49,15 @@ struct Core {
     static constexpr bool kFlatS = Defaults<T, NX>::flat_smoother;
 
     // ------------------------------------------------------------------
-    static void shapes(const Ctx &c, bool smoother, int &T0, int &E0, int &Tup, int &Eup)
+    static void shapes(const Ctx &c, bool smoother, int &T0, int &E0, int &Tup, int &E1,
+                       int &Eup)
     {
         T0 = c.p->scan_threads > 0 ? c.p->scan_threads : Defaults<T, NX>::T0;
         E0 = c.p->scan_elems > 0 ? c.p->scan_elems
                                  : (smoother ? Defaults<T, NX>::E0_smoother
                                              : Defaults<T, NX>::E0_filter);
         Tup = Defaults<T, NX>::Tup;
+        E1 = smoother ? Defaults<T, NX>::E1_smoother : Defaults<T, NX>::E1_filter;
         Eup = smoother ? Defaults<T, NX>::Eup_smoother : Defaults<T, NX>::Eup_filter;
         if (Tup > T0)
             Tup = T0;
@@ -313,15 +317,15 @@ struct Core {
     // filter scan (elements read from `el`)
     static ScanShape filter_shape(const Ctx &c)
     {
-        int T0, E0, Tup, Eup;
-        shapes(c, false, T0, E0, Tup, Eup);
-        return plan_scan(c, 0, T0, E0, Tup, Eup, kFlatF);
+        int T0, E0, Tup, E1, Eup;
+        shapes(c, false, T0, E0, Tup, E1, Eup);
+        return plan_scan(c, 0, T0, E0, Tup, E1, Eup, kFlatF);
     }
     static ScanShape smoother_shape(const Ctx &c)
     {
-        int T0, E0, Tup, Eup;
-        shapes(c, true, T0, E0, Tup, Eup);
-        return plan_scan(c, 1, T0, E0, Tup, Eup, kFlatS);
+        int T0, E0, Tup, E1, Eup;
+        shapes(c, true, T0, E0, Tup, E1, Eup);
+        return plan_scan(c, 1, T0, E0, Tup, E1, Eup, kFlatS);
     }
 
     static size_t fscan_bytes(const Ctx &c)
