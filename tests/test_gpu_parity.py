@@ -200,7 +200,7 @@ def test_ct_slr_matches_oracle(tag):
     g = pss.slr_linearize(b, m, N, pss.to_soa(w.y, dt, DEV))
     torch.cuda.synchronize()
     tol = 1e-9 if tag == "f64" else 2e-4
-    # offsets are differences zbar - G m of O(|x|) terms: judge them on that scale
+    # offsets are differences zbar - G m of O(|x|) terms: compare them on that scale
     Fm = np.abs(np.einsum("kij,kj->ki", ref["F"], nom["ms"][:-1])).max(axis=1, keepdims=True)
     Hm = np.abs(np.einsum("kij,kj->ki", ref["H"], nom["ms"][1:])).max(axis=1, keepdims=True)
     for key, shape, extra in (("F", (5, 5), 0.0), ("c", (5,), Fm), ("H", (2, 5), 0.0),
