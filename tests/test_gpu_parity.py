@@ -92,7 +92,8 @@ def test_linear_filter_smoother_multilevel(nx, ny, tag):
         assert em < tol["m"] and eP < tol["P"], ("smoother", bi, em, eP)
 
 
-def test_linear_many_sequences_default_shapes():
+@pytest.mark.parametrize("tag", ["f64", "f32"])
+def test_linear_many_sequences_default_shapes(tag):
     """150 ragged sequences (more than 64, so the level planner takes its
     block-wide path) at the default launch shapes: the filter's flat finest
     level, its interleaved next level and the smoother's tree, per sequence
@@ -102,14 +103,15 @@ def test_linear_many_sequences_default_shapes():
     lengths[:3] = [1, 256, 257]
     G, m0, N0, y, y_off = _linear_case(4, 2, lengths, 4242)
     ref = _oracle_linear(G, m0, N0, y, y_off)
-    b = pss.Batch(pss.MODEL_LINEAR, torch.float64, 4, 2, y_off, m0, N0, device=DEV)
+    dt = _tdtype(tag)
+    b = pss.Batch(pss.MODEL_LINEAR, dt, 4, 2, y_off, m0, N0, device=DEV)
     g = b.gamma_from_numpy(G)
-    yd = pss.to_soa(y, torch.float64, DEV)
+    yd = pss.to_soa(y, dt, DEV)
     el = pss.sqrt_filter_elements(b, g, yd)
     mf, Nf = pss.sqrt_filter_scan(b, el)
     ms, Ns = pss.sqrt_smoother_scan(b, g, mf, Nf)
     torch.cuda.synchronize()
-    tol = par.TOL["f64"]
+    tol = par.TOL[tag]
     mfa, Nfa = pss.marg_from_soa(mf, Nf, 4)
     msa, Nsa = pss.marg_from_soa(ms, Ns, 4)
     for bi, (r, a1, a2, a3, a4) in enumerate(zip(ref, _split_states(mfa, y_off),
