@@ -132,7 +132,9 @@ typedef enum {
     PSS_OP_LOGLIK = 5,
     PSS_OP_LOGLIK_GRAD = 6,
     PSS_OP_SEQUENTIAL = 7,
-    PSS_OP_LOGLIK_GRAD_IFT = 8
+    PSS_OP_LOGLIK_GRAD_IFT = 8,
+    PSS_OP_LOGLIK_VJP = 9,
+    PSS_OP_SCORE_FISHER = 10
 } pss_op;
 
 /* ---- problem description (host struct, read during the call only) ----- */
@@ -185,6 +187,29 @@ typedef struct pss_gamma {
 typedef struct pss_felem {
     void *A, *b, *U, *eta, *Z;
 } pss_felem;
+
+/* Checkpoint of the log-likelihood's filter pass, kept between pss_loglik
+   (which fills it) and the gradient calls (which consume it) so that the
+   backward pass does not repeat the forward filter scan.  Caller-owned
+   device memory of pss_ckpt_size(p, level) bytes.  level chooses what is
+   stored (level checkpointing of the scan of Algorithm 1):
+     0       every filtering marginal (nx + nx(nx+1)/2 numbers per state);
+     l >= 1  the exclusive prefixes of the filter scan's level-l elements
+             (the filtering marginal before each level-l element: one per
+             4 states at level 1, one per 1024 at level 2 with the default
+             shapes); the backward pass re-runs only the levels below l;
+   a level at or above the scan's top keeps nothing but the per-sequence
+   log-likelihoods, and the backward pass re-runs the whole filter scan.
+   `tag` is written by pss_loglik and identifies the problem (sizes, model,
+   theta, launch shape, level); a gradient call with another problem is
+   refused.  The nominal, y and (linear models) Gamma of the gradient call
+   must be those of the pss_loglik call that filled it. */
+typedef struct pss_ckpt {
+    int32_t level;
+    void *buf;
+    size_t bytes;
+    uint64_t tag;
+} pss_ckpt;
 
 /* ---- entry points --------------------------------------------------------- */
 
@@ -241,29 +266,75 @@ int pss_ipls_iterate(const pss_problem *p, const pss_gamma *g, const void *y, in
                      void *m_nom, void *N_nom, void *m_f, void *N_f, void *ws, size_t ws_bytes,
                      hipStream_t stream);
 
+/* Bytes of a checkpoint of this level for this problem (0 and the last
+   error set for an invalid problem or a negative level). */
+size_t pss_ckpt_size(const pss_problem *p, int32_t level);
+
 /* Pseudo-log-likelihood of Section 5.1: the model is linearised at the
    nominal (nonlinear models; for LINEAR `g` is used), filtered with
    Algorithm 1, and
    ll[b] = sum_k log N(y_k; H_k m^-_k + d_k, Y_k Y_k^T) with the predicted
    factor Y_k = Tria([H_k Tria([F_{k-1} N^f_{k-1}, S_Lambda]), S_Omega]).
-   ll: device double [B] (FP64 accumulation for both dtypes).
-   ws: pss_workspace_size(PSS_OP_LOGLIK). */
+   ll: device double [B] (FP64 accumulation for both dtypes).  ckpt
+   (nullable; square-root form): filled for a later gradient call (see
+   pss_ckpt).  ws: pss_workspace_size(PSS_OP_LOGLIK). */
 int pss_loglik(const pss_problem *p, const pss_gamma *g, const void *m_nom, const void *N_nom,
-               const void *y, double *ll, void *ws, size_t ws_bytes, hipStream_t stream);
+               const void *y, double *ll, pss_ckpt *ckpt, void *ws, size_t ws_bytes,
+               hipStream_t stream);
 
 /* Gradient of the pseudo-log-likelihood with respect to theta = (log q1,
    log q2, log sigma) at a FROZEN nominal (the partial derivative term of
-   eq. gradient; PSS_MODEL_CT_BEARINGS only, any linearisation).  With the
-   nominal fixed, theta enters only through S_Lambda and S_Omega.  The sensitivities dl/dLambda_k
-   and dl/dOmega_k are the posterior expectations of the complete-data score
-   (Fisher's identity), computed from the parallel square-root smoother of
-   the linearised model; they are contracted with dQ/dtheta and dR/dtheta.
-   Outputs (device double): ll [B]; grad [3][B] per sequence, component-major
-   (nullable); theta_bar [3] = sum_b ll_bar[b] grad[.][b] (nullable; ll_bar
-   nullable means all ones).  ws: pss_workspace_size(PSS_OP_LOGLIK_GRAD). */
+   eq. gradient; PSS_MODEL_CT_BEARINGS only, any linearisation), by a
+   hand-written reverse-mode adjoint of the square-root filter pass.  With
+   the nominal fixed, theta enters only through S_Lambda and S_Omega.  The
+   cotangents of the filtering marginals (Gram cotangents dl/dP, never
+   factor cotangents) obey lambda_{k-1} = T_k(lambda_k), an affine map per
+   step built from the step's Kalman gain; the maps compose associatively,
+   so the VJP of the filter scan runs as a reverse associative scan over the
+   same tile levels.  Each step's VJP then gives the Gram cotangents of
+   Lambda_k and Omega_k, contracted with dQ/dtheta and dR/dtheta.
+   ckpt (nullable): a checkpoint filled by pss_loglik for this problem and
+   nominal -- the forward filter pass is then not repeated (level 0) or
+   only its levels under the checkpoint are re-run; NULL runs the forward
+   pass first.  Outputs (device double): ll [B]; grad [3][B] per sequence,
+   component-major (nullable); theta_bar [3] = sum_b ll_bar[b] grad[.][b]
+   (nullable; ll_bar nullable means all ones).
+   ws: pss_workspace_size(PSS_OP_LOGLIK_GRAD). */
 int pss_loglik_grad(const pss_problem *p, const void *m_nom, const void *N_nom, const void *y,
-                    const double *ll_bar, double *ll, double *grad, double *theta_bar, void *ws,
-                    size_t ws_bytes, hipStream_t stream);
+                    const double *ll_bar, const pss_ckpt *ckpt, double *ll, double *grad,
+                    double *theta_bar, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Vector-Jacobian product of the pseudo-log-likelihood (Section 5.1) with
+   respect to the linearisation and the prior, at a frozen nominal, by the
+   same reverse-mode adjoint as pss_loglik_grad; any model, square-root
+   form.  Outputs, each step's cotangent scaled by its sequence's ll_bar[b]
+   (ll_bar nullable: ones):
+     g_bar   (stride 1, [.][T_y] in the dtype): the cotangent of every
+             field of Gamma at every step slot in the library's
+             representation -- F, c, H, d entrywise, S_L and S_O as the
+             lower triangles of 2 Lambda_bar S_L and 2 Omega_bar S_O (the
+             factor cotangents of the Gram cotangents);
+     m0_bar  [nx][B], N0_bar [nx(nx+1)/2][B] (both nullable, together):
+             per sequence, the cotangent of the prior mean and of its
+             factor (lower triangle of 2 P0_bar N0);
+     ll [B]  the log-likelihoods.
+   For a linear model with a shared Gamma (stride 0) the gradient is the
+   sum of g_bar over the step slots.  ckpt as for pss_loglik_grad.
+   ws: pss_workspace_size(PSS_OP_LOGLIK_VJP). */
+int pss_loglik_vjp(const pss_problem *p, const pss_gamma *g, const void *m_nom,
+                   const void *N_nom, const void *y, const double *ll_bar, const pss_ckpt *ckpt,
+                   double *ll, const pss_gamma *g_bar, void *m0_bar, void *N0_bar, void *ws,
+                   size_t ws_bytes, hipStream_t stream);
+
+/* The same theta gradient as pss_loglik_grad by another route, kept as a
+   cross-check: the sensitivities dl/dLambda_k and dl/dOmega_k as posterior
+   expectations of the complete-data score (Fisher's identity), from the
+   parallel square-root smoother of the linearised model.  Same outputs as
+   pss_loglik_grad without a checkpoint.
+   ws: pss_workspace_size(PSS_OP_SCORE_FISHER). */
+int pss_score_fisher(const pss_problem *p, const void *m_nom, const void *N_nom, const void *y,
+                     const double *ll_bar, double *ll, double *grad, double *theta_bar,
+                     void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* Gradient of the pseudo-log-likelihood at the IPLS fixed point (Section
    5.2, eq. implicity_function_theorem, Algorithm 4): the total derivative of

@@ -37,7 +37,30 @@ def _run(cmd):
     return r.stdout
 
 
-def build(jobs: int | None = None, verbose: bool = False, extra_flags=()) -> str:
+def _deps(src: str, seen=None) -> set:
+    """The source and every file it reaches through #include "..." lines."""
+    import re
+    seen = set() if seen is None else seen
+    if src in seen or not os.path.exists(src):
+        return seen
+    seen.add(src)
+    for inc in re.findall(r'^#include "([^"]+)"', open(src).read(), flags=re.M):
+        _deps(os.path.normpath(os.path.join(os.path.dirname(src), inc)), seen)
+    return seen
+
+
+def _stale(src: str, obj: str) -> bool:
+    # a unit is rebuilt when its source or a header it includes is newer
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(f) > t for f in _deps(src))
+
+
+def build(jobs: int | None = None, verbose: bool = False, extra_flags=(),
+          incremental: bool = False) -> str:
+    """Compile every unit (incremental: only units older than a source) and
+    link libpss.so."""
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or min(8, os.cpu_count() or 4)
     units = [(os.path.join(CSRC, "api.hip"), os.path.join(BUILD, "api.o"), []),
@@ -57,6 +80,8 @@ def build(jobs: int | None = None, verbose: bool = False, extra_flags=()) -> str
 
     def compile_one(u):
         src, obj, defs = u
+        if incremental and not _stale(src, obj):
+            return obj
         out = _run([HIPCC, *FLAGS, *extra_flags, *defs, "-c", src, "-o", obj])
         if verbose and out.strip():
             print(out)
@@ -75,4 +100,4 @@ def clean():
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="-i" in sys.argv))

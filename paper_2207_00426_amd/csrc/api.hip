@@ -545,6 +545,65 @@ static int check_ws(const Ctx &c, int op, const void *ws, size_t ws_bytes)
     return PSS_OK;
 }
 
+// identity of a checkpoint: FNV-1a over what fixes the filter pass it
+// stores (model, dimensions, dtype, batch offsets, model constants, the
+// linearisation, launch shape, level)
+static uint64_t ckpt_tag(const pss_problem *p, int32_t level)
+{
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](const void *d, size_t n) {
+        const unsigned char *b = static_cast<const unsigned char *>(d);
+        for (size_t i = 0; i < n; ++i) {
+            h ^= b[i];
+            h *= 1099511628211ull;
+        }
+    };
+    const int32_t ints[] = {p->model, p->dtype, p->nx, p->ny, p->B, p->scan_threads,
+                            p->scan_elems, p->linearization, p->form, p->gh_order, level};
+    mix(ints, sizeof ints);
+    mix(p->y_off_host, sizeof(int64_t) * ((size_t)p->B + 1));
+    const double dbl[] = {p->dt, p->theta[0], p->theta[1], p->theta[2], p->sensors[0],
+                          p->sensors[1], p->sensors[2], p->sensors[3], p->ut_kappa};
+    mix(dbl, sizeof dbl);
+    return h;
+}
+
+static size_t ckpt_need(const Ctx &c, int level)
+{
+    size_t need = 0;
+    dispatch(c.p, [&](auto tag) {
+        using I = typename decltype(tag)::I;
+        need = I::ckpt_bytes(c, level);
+        return 0;
+    });
+    return need;
+}
+
+// a checkpoint about to be filled (for_fill) or consumed
+static int check_ckpt(const Ctx &c, const pss_ckpt *ck, bool for_fill)
+{
+    if (!ck)
+        return PSS_OK;
+    if (c.p->form != PSS_FORM_SQRT) {
+        set_error("checkpoints are defined for the square-root form only");
+        return PSS_EUNSUPPORTED;
+    }
+    if (ck->level < 0 || !ck->buf) {
+        set_error("checkpoint: negative level or null buffer");
+        return PSS_EINVAL;
+    }
+    const size_t need = ckpt_need(c, ck->level);
+    if (ck->bytes < need) {
+        set_error("checkpoint buffer too small: need " + std::to_string(need) + " bytes");
+        return PSS_EWORKSPACE;
+    }
+    if (!for_fill && ck->tag != ckpt_tag(c.p, ck->level)) {
+        set_error("checkpoint was filled for another problem, level or launch shape");
+        return PSS_EINVAL;
+    }
+    return PSS_OK;
+}
+
 } // namespace pss
 
 using namespace pss;
@@ -777,8 +836,25 @@ int pss_ipls_iterate(const pss_problem *p, const pss_gamma *g, const void *y, in
     }()));
 }
 
+size_t pss_ckpt_size(const pss_problem *p, int32_t level)
+{
+    try {
+        if (validate(p) != PSS_OK)
+            return 0;
+        if (level < 0) {
+            set_error("checkpoint level must be >= 0");
+            return 0;
+        }
+        return ckpt_need(make_ctx(p, nullptr), level);
+    } catch (...) {
+        set_error("exception in pss_ckpt_size");
+        return 0;
+    }
+}
+
 int pss_loglik(const pss_problem *p, const pss_gamma *g, const void *m_nom, const void *N_nom,
-               const void *y, double *ll, void *ws, size_t ws_bytes, hipStream_t stream)
+               const void *y, double *ll, pss_ckpt *ckpt, void *ws, size_t ws_bytes,
+               hipStream_t stream)
 {
     PSS_GUARD(([&]() -> int {
         int rc = validate(p);
@@ -795,16 +871,21 @@ int pss_loglik(const pss_problem *p, const pss_gamma *g, const void *m_nom, cons
         const Ctx c = make_ctx(p, stream);
         if ((rc = check_ws(c, PSS_OP_LOGLIK, ws, ws_bytes)))
             return rc;
-        return dispatch(p, [&](auto tag) {
+        if ((rc = check_ckpt(c, ckpt, true)))
+            return rc;
+        rc = dispatch(p, [&](auto tag) {
             using I = typename decltype(tag)::I;
-            return I::loglik(c, g, m_nom, N_nom, y, ll, ws);
+            return I::loglik(c, g, m_nom, N_nom, y, ll, ckpt, ws);
         });
+        if (rc == PSS_OK && ckpt)
+            ckpt->tag = ckpt_tag(p, ckpt->level);
+        return rc;
     }()));
 }
 
 int pss_loglik_grad(const pss_problem *p, const void *m_nom, const void *N_nom, const void *y,
-                    const double *ll_bar, double *ll, double *grad, double *theta_bar, void *ws,
-                    size_t ws_bytes, hipStream_t stream)
+                    const double *ll_bar, const pss_ckpt *ckpt, double *ll, double *grad,
+                    double *theta_bar, void *ws, size_t ws_bytes, hipStream_t stream)
 {
     PSS_GUARD(([&]() -> int {
         int rc = validate(p);
@@ -823,9 +904,74 @@ int pss_loglik_grad(const pss_problem *p, const void *m_nom, const void *N_nom, 
         const Ctx c = make_ctx(p, stream);
         if ((rc = check_ws(c, PSS_OP_LOGLIK_GRAD, ws, ws_bytes)))
             return rc;
+        if ((rc = check_ckpt(c, ckpt, false)))
+            return rc;
         return dispatch(p, [&](auto tag) {
             using I = typename decltype(tag)::I;
-            return I::loglik_grad(c, m_nom, N_nom, y, ll_bar, ll, grad, theta_bar, ws);
+            return I::loglik_grad(c, m_nom, N_nom, y, ll_bar, ckpt, ll, grad, theta_bar, ws);
+        });
+    }()));
+}
+
+int pss_loglik_vjp(const pss_problem *p, const pss_gamma *g, const void *m_nom,
+                   const void *N_nom, const void *y, const double *ll_bar, const pss_ckpt *ckpt,
+                   double *ll, const pss_gamma *g_bar, void *m0_bar, void *N0_bar, void *ws,
+                   size_t ws_bytes, hipStream_t stream)
+{
+    PSS_GUARD(([&]() -> int {
+        int rc = validate(p);
+        if (rc)
+            return rc;
+        if ((rc = need_sqrt(p, "loglik_vjp")))
+            return rc;
+        if (!y || !ll || !gamma_ok(g_bar) || g_bar->stride != 1 ||
+            ((m0_bar == nullptr) != (N0_bar == nullptr))) {
+            set_error("loglik_vjp: null buffer, g_bar stride != 1, or only one of m0_bar, "
+                      "N0_bar");
+            return PSS_EINVAL;
+        }
+        if (p->model == PSS_MODEL_LINEAR ? !gamma_ok(g) : (!m_nom || !N_nom || g != nullptr)) {
+            set_error("loglik_vjp: a linear model needs g, a nonlinear model the nominal and "
+                      "g = NULL");
+            return PSS_EINVAL;
+        }
+        const Ctx c = make_ctx(p, stream);
+        if ((rc = check_ws(c, PSS_OP_LOGLIK_VJP, ws, ws_bytes)))
+            return rc;
+        if ((rc = check_ckpt(c, ckpt, false)))
+            return rc;
+        return dispatch(p, [&](auto tag) {
+            using I = typename decltype(tag)::I;
+            return I::loglik_vjp(c, g, m_nom, N_nom, y, ll_bar, ckpt, ll, g_bar, m0_bar, N0_bar,
+                                 ws);
+        });
+    }()));
+}
+
+int pss_score_fisher(const pss_problem *p, const void *m_nom, const void *N_nom, const void *y,
+                     const double *ll_bar, double *ll, double *grad, double *theta_bar,
+                     void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    PSS_GUARD(([&]() -> int {
+        int rc = validate(p);
+        if (rc)
+            return rc;
+        if ((rc = need_sqrt(p, "score_fisher")))
+            return rc;
+        if (p->model != PSS_MODEL_CT_BEARINGS) {
+            set_error("score_fisher: theta is defined for the coordinated-turn model");
+            return PSS_EUNSUPPORTED;
+        }
+        if (!m_nom || !N_nom || !y || !ll) {
+            set_error("score_fisher: null buffer");
+            return PSS_EINVAL;
+        }
+        const Ctx c = make_ctx(p, stream);
+        if ((rc = check_ws(c, PSS_OP_SCORE_FISHER, ws, ws_bytes)))
+            return rc;
+        return dispatch(p, [&](auto tag) {
+            using I = typename decltype(tag)::I;
+            return I::score_fisher(c, m_nom, N_nom, y, ll_bar, ll, grad, theta_bar, ws);
         });
     }()));
 }

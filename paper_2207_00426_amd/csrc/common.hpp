@@ -136,10 +136,18 @@ struct Impl {
     static int ipls(const Ctx &c, const pss_gamma *g, const void *y, int n_iter, void *m_nom,
                     void *N_nom, void *mf_out, void *Nf_out, void *ws);
     static int loglik(const Ctx &c, const pss_gamma *g, const void *m_nom, const void *N_nom,
-                      const void *y, double *ll, void *ws);
+                      const void *y, double *ll, const pss_ckpt *ckpt, void *ws);
     static int loglik_grad(const Ctx &c, const void *m_nom, const void *N_nom, const void *y,
-                           const double *ll_bar, double *ll, double *grad, double *theta_bar,
-                           void *ws);
+                           const double *ll_bar, const pss_ckpt *ckpt, double *ll, double *grad,
+                           double *theta_bar, void *ws);
+    static int loglik_vjp(const Ctx &c, const pss_gamma *g, const void *m_nom, const void *N_nom,
+                          const void *y, const double *ll_bar, const pss_ckpt *ckpt, double *ll,
+                          const pss_gamma *gbar, void *m0_bar, void *N0_bar, void *ws);
+    static int score_fisher(const Ctx &c, const void *m_nom, const void *N_nom, const void *y,
+                            const double *ll_bar, double *ll, double *grad, double *theta_bar,
+                            void *ws);
+    static size_t ckpt_bytes(const Ctx &c, int level);
+    static int filter_levels(const Ctx &c);
     static int sequential(const Ctx &c, const pss_gamma *g, const void *y, int n_iter,
                           void *m_nom, void *N_nom, void *mf_out, void *Nf_out, void *ws);
 };

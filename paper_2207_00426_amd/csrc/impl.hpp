@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <type_traits>
 
+#include "adjoint.hpp"
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -170,11 +171,17 @@ struct Core {
 
     // generic multi-level scan driver; Flat: level 0 may be flat (then it
     // is, see plan_scan, and level 1 is stored tile-interleaved)
+    // stop > 0 (and < sh.L): run only the levels below `stop`, whose
+    // exclusive prefixes w.pre[stop] the caller provides (a checkpoint):
+    // the up-sweeps that rebuild those levels' trees and elements, then their
+    // down-sweeps; the levels from `stop` up are not run.
     template <class Op, bool Flat, class Src0, class Dst0, class AggRef, class Start>
     static int run_scan(const Ctx &c, const ScanShape &sh, const ScanWs<Op> &w, int extra,
                         const Src0 &src0, const Dst0 &dst0, const Start &start,
-                        AggRef (*agg_ref)(T *, int64_t))
+                        AggRef (*agg_ref)(T *, int64_t), int stop = 0)
     {
+        const int top = (stop > 0 && stop < sh.L) ? stop : sh.L;
+        const bool partial = top < sh.L;
         int rc = launch_plan(c, sh, extra, w.tile_off, w.elem_off);
         if (rc)
             return rc;
@@ -201,8 +208,12 @@ struct Core {
             }
             return launch(LvSrc{agg_ref(w.agg[l], sh.nelem[l])});
         };
-        // up-sweeps of the lower levels
-        for (int l = 0; l + 1 < sh.L; ++l) {
+        // up-sweeps of the lower levels (below a checkpoint: all levels
+        // under it; a flat level right under it needs no up-sweep, its
+        // down-sweep reads the stored prefixes per thread)
+        for (int l = 0; l + 1 < sh.L && l < top; ++l) {
+            if (partial && l == top - 1 && sh.flat[l])
+                continue;
             const LevelGeom g = geom(l);
             const int64_t tree_ld = sh.ntiles[l] * sh.T[l];
             AggRef agg = agg_ref(w.agg[l + 1], sh.nelem[l + 1]);
@@ -242,7 +253,7 @@ struct Core {
                 return rc;
         }
         // top level
-        {
+        if (!partial) {
             const int l = sh.L - 1;
             const LevelGeom g = geom(l);
             const size_t lb = lds_bytes<Op>(sh.T[l], sh.E[l], g.stage);
@@ -270,7 +281,7 @@ struct Core {
                 return rc;
         }
         // down-sweeps of the lower levels
-        for (int l = sh.L - 2; l >= 0; --l) {
+        for (int l = top - (partial ? 1 : 2); l >= 0; --l) {
             const LevelGeom g = geom(l);
             const int64_t tree_ld = sh.ntiles[l] * sh.T[l];
             const size_t lb = lds_bytes<Op>(sh.T[l], sh.E[l], g.stage);
@@ -328,6 +339,22 @@ struct Core {
         return plan_scan(c, 1, T0, E0, Tup, E1, Eup, kFlatS);
     }
 
+    // the adjoint scan (reverse time, one element per step): tree level 0
+    // with 2 elements per thread, as the smoother (its element -- a Kalman
+    // step from the filtering marginal -- dominates the operator)
+    static ScanShape adj_shape(const Ctx &c)
+    {
+        const int T0 = c.p->scan_threads > 0 ? c.p->scan_threads : Defaults<T, NX>::T0;
+        const int Tup = std::min(T0, (int)Defaults<T, NX>::Tup);
+        return plan_scan(c, 0, T0, 2, Tup, 2, 2, false);
+    }
+    static size_t ascan_bytes(const Ctx &c)
+    {
+        Carver cv{nullptr};
+        carve_scan<AdjScan<T, NX>>(cv, c, adj_shape(c));
+        return cv.used;
+    }
+
     static size_t fscan_bytes(const Ctx &c)
     {
         Carver cv{nullptr};
@@ -345,12 +372,21 @@ struct Core {
     // ilv: the elements are stored tile-interleaved for this scan's level 0
     // (as written by felem(..., true)); the library's own passes use that
     // cov: the standard (covariance-form) scan of the same storage layout
+    // ck_pre (square-root form only): the exclusive prefixes of the filter
+    // scan's level ck_level (1 <= ck_level < levels) -- written there by a
+    // full scan, or, with resume, read from there and only the levels below
+    // re-run (the backward pass of a checkpointed log-likelihood)
     static int fscan(const Ctx &c, const pss_felem *el, void *mf, void *Nf, void *ws,
-                     bool ilv = false, bool cov = false)
+                     bool ilv = false, bool cov = false, int ck_level = 0, T *ck_pre = nullptr,
+                     bool resume = false)
     {
         const ScanShape sh = filter_shape(c);
         Carver cv{static_cast<char *>(ws)};
         auto w = carve_scan<FS>(cv, c, sh);
+        const bool ck = ck_pre && ck_level >= 1 && ck_level < sh.L;
+        if (ck)
+            w.pre[ck_level] = ck_pre;
+        const int stop = (ck && resume) ? ck_level : 0;
         FElemRef<T, NX> er;
         er.A = mptr<T>(el->A);
         er.b = mptr<T>(el->b);
@@ -376,10 +412,10 @@ struct Core {
         }
         if (ilv) {
             RefSrc<FS, FElemRef<T, NX>, true, LZ> src{er};
-            return run_scan<FS, kFlatF>(c, sh, w, 0, src, dst, st, &felem_ref);
+            return run_scan<FS, kFlatF>(c, sh, w, 0, src, dst, st, &felem_ref, stop);
         }
         RefSrc<FS, FElemRef<T, NX>, false, LZ> src{er};
-        return run_scan<FS, kFlatF>(c, sh, w, 0, src, dst, st, &felem_ref);
+        return run_scan<FS, kFlatF>(c, sh, w, 0, src, dst, st, &felem_ref, stop);
     }
 
     static int sscan(const Ctx &c, const pss_gamma *g, const void *mf, const void *Nf, void *ms,
@@ -402,6 +438,23 @@ struct Core {
         SmootherSrc<T, NX, NY> src{gamma_ref(g, c.T_y), marg_ref2(mf, Nf, c.T_x),
                                    selem_ref(stash, c.T_x), c.p->y_off};
         return run_scan<SS, kFlatS>(c, sh, w, 1, src, dst, st, &selem_ref);
+    }
+
+    // the adjoint scan: the reverse scan of the cotangent maps T_k from the
+    // filtering marginals (mf, Nf) and the linearisation, emitting through
+    // `out` the step cotangents and through `dst` the prior's
+    template <class Out>
+    static int ascan(const Ctx &c, const pss_gamma *g, const void *y, const void *mf,
+                     const void *Nf, const Out &out, const AdjDst<T, NX> &dst, void *ws)
+    {
+        using AS = AdjScan<T, NX>;
+        const ScanShape sh = adj_shape(c);
+        Carver cv{static_cast<char *>(ws)};
+        auto w = carve_scan<AS>(cv, c, sh);
+        AdjSrc<T, NX, NY, Out> src{gamma_ref(g, c.T_y), marg_ref2(mf, Nf, c.T_x), cptr<T>(y),
+                                   c.T_y, out};
+        StartPre<T, NX> st{nullptr, nullptr};
+        return run_scan<AS, false>(c, sh, w, 0, src, dst, st, &selem_ref);
     }
 
     static int felem(const Ctx &c, const pss_gamma *g, const void *y, const pss_felem *out,
@@ -473,6 +526,8 @@ struct Core {
     static size_t ws_size(const Ctx &c, int op)
     {
         const size_t scans = fscan_bytes(c) > sscan_bytes(c) ? fscan_bytes(c) : sscan_bytes(c);
+        const size_t fwd = gamma_bytes(c) + felem_bytes(c) + marg_bytes(c) +
+                           align256(c.T_y * sizeof(double));
         switch (op) {
         case PSS_OP_SLR:
         case PSS_OP_FILTER_ELEMENTS:
@@ -484,10 +539,13 @@ struct Core {
         case PSS_OP_IPLS:
             return gamma_bytes(c) + felem_bytes(c) + marg_bytes(c) + scans;
         case PSS_OP_LOGLIK:
-            return gamma_bytes(c) + felem_bytes(c) + marg_bytes(c) +
-                   align256(c.T_y * sizeof(double)) +
-                   std::max(fscan_bytes(c), seq_sum_bytes(c, 1));
+            return fwd + std::max(fscan_bytes(c), seq_sum_bytes(c, 1));
         case PSS_OP_LOGLIK_GRAD:
+            return fwd + std::max({fscan_bytes(c), ascan_bytes(c), seq_sum_bytes(c, 3)}) +
+                   align256(3 * c.T_y * sizeof(double)) + align256(3 * c.B * sizeof(double));
+        case PSS_OP_LOGLIK_VJP:
+            return fwd + std::max({fscan_bytes(c), ascan_bytes(c), seq_sum_bytes(c, 1)});
+        case PSS_OP_SCORE_FISHER:
             return gamma_bytes(c) + felem_bytes(c) + marg_bytes(c) +
                    align256(c.T_y * sizeof(double)) + std::max(scans, seq_sum_bytes(c, 3)) +
                    marg_bytes(c) + align256(3 * c.T_y * sizeof(double)) +
@@ -498,6 +556,51 @@ struct Core {
             return 0;
         }
     }
+
+    // ------------------------------------------------------------------
+    // checkpoints of the log-likelihood's filter pass (pss_ckpt): the
+    // per-sequence log-likelihoods, then what the level keeps -- level 0
+    // every filtering marginal, level l in [1, levels) the exclusive
+    // prefixes of the filter scan's level-l elements, higher levels nothing
+    struct CkView {
+        int level = 0;
+        double *ll = nullptr;
+        T *marg = nullptr; // level 0: [Sizes::marg][T_x]
+        T *pre = nullptr;  // level l: [Sizes::marg][nelem_l]
+    };
+    static size_t ckpt_bytes(const Ctx &c, int level)
+    {
+        Carver cv{nullptr};
+        cv.template take<double>((size_t)c.B);
+        if (level == 0) {
+            cv.template take<T>((size_t)Sizes<NX>::marg * c.T_x);
+        } else {
+            const ScanShape sh = filter_shape(c);
+            if (level < sh.L)
+                cv.template take<T>((size_t)Sizes<NX>::marg * sh.nelem[level]);
+        }
+        return cv.used;
+    }
+    static CkView ckpt_view(const Ctx &c, const pss_ckpt *ck)
+    {
+        CkView v;
+        if (!ck)
+            return v;
+        v.level = ck->level;
+        Carver cv{static_cast<char *>(ck->buf)};
+        v.ll = cv.template take<double>((size_t)c.B);
+        if (ck->level == 0) {
+            v.marg = cv.template take<T>((size_t)Sizes<NX>::marg * c.T_x);
+        } else {
+            const ScanShape sh = filter_shape(c);
+            if (ck->level < sh.L)
+                v.pre = cv.template take<T>((size_t)Sizes<NX>::marg * sh.nelem[ck->level]);
+        }
+        return v;
+    }
+    // the filter scan's level count for this problem (checkpoint levels
+    // from it up keep nothing but the log-likelihoods)
+    static int filter_levels(const Ctx &c) { return filter_shape(c).L; }
 
     static int ipls(const Ctx &c, const pss_gamma *gin, const void *y, int n_iter, void *m_nom,
                     void *N_nom, void *mf_out, void *Nf_out, void *ws)
@@ -533,65 +636,214 @@ struct Core {
         return rc;
     }
 
-    // filter pass shared by loglik and loglik_grad; returns the carved state
+    // linearisation (nonlinear models) and level-0 filter elements
+    // (tile-interleaved) at the nominal; the transition and measurement
+    // parts of Gamma are both stored
+    static int lin_elements(const Ctx &c, const pss_gamma *gin, const void *m_nom,
+                            const void *N_nom, const void *y, const pss_gamma &gw,
+                            const pss_felem *el)
+    {
+        int rc;
+        const bool cov = c.p->form == PSS_FORM_COV;
+        const int fused = nonlinear(c) ? slr_felem(c, m_nom, N_nom, y, &gw, el, cov, true) : 1;
+        if (fused < 0)
+            return fused;
+        if (fused) {
+            if (nonlinear(c) && (rc = slr(c, m_nom, N_nom, y, &gw)))
+                return rc;
+            if ((rc = felem(c, nonlinear(c) ? &gw : gin, y, el, true, cov)))
+                return rc;
+        }
+        return PSS_OK;
+    }
+
+    // filter pass shared by loglik and the gradients; returns the carved
+    // state.  With a checkpoint (square-root form) the filtering marginals
+    // go to it (level 0) or the scan's level-`level` prefixes do, and the
+    // log-likelihoods are copied into it.
     static int loglik_core(const Ctx &c, const pss_gamma *gin, const void *m_nom,
                            const void *N_nom, const void *y, double *ll, Carver &cv,
-                           pss_gamma &gw, T *&mfb, void *&scan_ws)
+                           pss_gamma &gw, T *&mfb, void *&scan_ws, const CkView &ck = CkView{},
+                           bool use_ck = false)
     {
         gw = carve_gamma(cv, c.T_y);
         T *fel = cv.template take<T>((size_t)Sizes<NX>::felem * c.T_y);
         mfb = cv.template take<T>((size_t)Sizes<NX>::marg * c.T_x);
         double *ell = cv.template take<double>((size_t)c.T_y);
         scan_ws = cv.base + cv.used;
-        const pss_gamma *g = nonlinear(c) ? &gw : gin;
         if (!nonlinear(c))
             gw = *gin;
+        const pss_gamma *g = &gw;
+        if (use_ck && ck.level == 0)
+            mfb = ck.marg;
         FElemRef<T, NX> fr = felem_ref(fel, c.T_y);
         pss_felem el{fr.A, fr.b, fr.U, fr.eta, fr.Z};
         int rc;
         const bool cov = c.p->form == PSS_FORM_COV;
-        const int fused = nonlinear(c) ? slr_felem(c, m_nom, N_nom, y, &gw, &el, cov, true) : 1;
-        if (fused < 0)
-            return fused;
-        if (fused) {
-            if (nonlinear(c) && (rc = slr(c, m_nom, N_nom, y, &gw)))
-                return rc;
-            if ((rc = felem(c, g, y, &el, true, cov)))
-                return rc;
-        }
-        if ((rc = fscan(c, &el, mfb, mfb + (size_t)NX * c.T_x, scan_ws, true, cov)))
+        if ((rc = lin_elements(c, gin, m_nom, N_nom, y, gw, &el)))
+            return rc;
+        if ((rc = fscan(c, &el, mfb, mfb + (size_t)NX * c.T_x, scan_ws, true, cov,
+                        use_ck ? ck.level : 0, use_ck ? ck.pre : nullptr, false)))
             return rc;
         const int tb = 128;
-        KTime kt(c.s, "loglik_terms", "", 0);
-        const dim3 grid((unsigned)((c.T_y + tb - 1) / tb));
-        if (cov)
-            hipLaunchKernelGGL((k_loglik_terms_cov<T, NX, NY>), grid, dim3(tb), 0, c.s, c.p->y_off,
-                               c.B, c.T_y, c.T_x, gamma_ref(g, c.T_y), cptr<T>(y),
-                               marg_ref(mfb, c.T_x), ell);
-        else
-            hipLaunchKernelGGL((k_loglik_terms<T, NX, NY>), grid, dim3(tb), 0, c.s, c.p->y_off,
-                               c.B, c.T_y, c.T_x, gamma_ref(g, c.T_y), cptr<T>(y),
-                               marg_ref(mfb, c.T_x), ell);
-        if ((rc = hip_check(hipGetLastError(), "loglik launch")))
+        {
+            KTime kt(c.s, "loglik_terms", "", 0);
+            const dim3 grid((unsigned)((c.T_y + tb - 1) / tb));
+            if (cov)
+                hipLaunchKernelGGL((k_loglik_terms_cov<T, NX, NY>), grid, dim3(tb), 0, c.s,
+                                   c.p->y_off, c.B, c.T_y, c.T_x, gamma_ref(g, c.T_y), cptr<T>(y),
+                                   marg_ref(mfb, c.T_x), ell);
+            else
+                hipLaunchKernelGGL((k_loglik_terms<T, NX, NY>), grid, dim3(tb), 0, c.s,
+                                   c.p->y_off, c.B, c.T_y, c.T_x, gamma_ref(g, c.T_y), cptr<T>(y),
+                                   marg_ref(mfb, c.T_x), ell);
+            if ((rc = hip_check(hipGetLastError(), "loglik launch")))
+                return rc;
+        }
+        if ((rc = launch_seq_sum(c, 1, ell, c.T_y, ll, scan_ws)))
             return rc;
-        return launch_seq_sum(c, 1, ell, c.T_y, ll, scan_ws);
+        if (use_ck)
+            rc = hip_check(hipMemcpyAsync(ck.ll, ll, (size_t)c.B * sizeof(double),
+                                          hipMemcpyDeviceToDevice, c.s),
+                           "checkpoint log-likelihood copy");
+        return rc;
     }
 
     static int loglik(const Ctx &c, const pss_gamma *gin, const void *m_nom, const void *N_nom,
-                      const void *y, double *ll, void *ws)
+                      const void *y, double *ll, const pss_ckpt *ckpt, void *ws)
     {
         Carver cv{static_cast<char *>(ws)};
         pss_gamma gw;
         T *mfb;
         void *scan_ws;
-        return loglik_core(c, gin, m_nom, N_nom, y, ll, cv, gw, mfb, scan_ws);
+        return loglik_core(c, gin, m_nom, N_nom, y, ll, cv, gw, mfb, scan_ws, ckpt_view(c, ckpt),
+                           ckpt != nullptr);
     }
 
-    static int loglik_grad(const Ctx &c, const void *m_nom, const void *N_nom, const void *y,
-                           const double *ll_bar, double *ll, double *grad, double *theta_bar,
-                           void *ws)
+    // forward state of a gradient pass: the linearisation and the filtering
+    // marginals at the nominal, from a checkpoint (re-running the filter
+    // scan's levels under it) or from a full filter pass; ll receives the
+    // log-likelihoods
+    static int grad_forward(const Ctx &c, const pss_gamma *gin, const void *m_nom,
+                            const void *N_nom, const void *y, const pss_ckpt *ckpt, double *ll,
+                            Carver &cv, pss_gamma &gw, T *&mf, void *&scan_ws)
     {
-        // layout: [gamma | felem | mf | ell | scan ws ...] then the grad part
+        if (!ckpt) {
+            T *mfb;
+            int rc = loglik_core(c, gin, m_nom, N_nom, y, ll, cv, gw, mfb, scan_ws);
+            mf = mfb;
+            return rc;
+        }
+        const CkView ck = ckpt_view(c, ckpt);
+        gw = carve_gamma(cv, c.T_y);
+        T *fel = cv.template take<T>((size_t)Sizes<NX>::felem * c.T_y);
+        T *mfb = cv.template take<T>((size_t)Sizes<NX>::marg * c.T_x);
+        cv.template take<double>((size_t)c.T_y);
+        scan_ws = cv.base + cv.used;
+        if (!nonlinear(c))
+            gw = *gin;
+        int rc;
+        if (ck.level == 0) {
+            // every marginal is stored: only the linearisation is redone
+            if (nonlinear(c) && (rc = slr(c, m_nom, N_nom, y, &gw)))
+                return rc;
+            mf = ck.marg;
+        } else {
+            FElemRef<T, NX> fr = felem_ref(fel, c.T_y);
+            pss_felem el{fr.A, fr.b, fr.U, fr.eta, fr.Z};
+            if ((rc = lin_elements(c, gin, m_nom, N_nom, y, gw, &el)))
+                return rc;
+            // levels under the checkpoint re-run from its prefixes; without
+            // stored prefixes (a level at or above the top) the whole scan
+            if ((rc = fscan(c, &el, mfb, mfb + (size_t)NX * c.T_x, scan_ws, true, false,
+                            ck.level, ck.pre, true)))
+                return rc;
+            mf = mfb;
+        }
+        return hip_check(hipMemcpyAsync(ll, ck.ll, (size_t)c.B * sizeof(double),
+                                        hipMemcpyDeviceToDevice, c.s),
+                         "checkpoint log-likelihood copy");
+    }
+
+    // gradient with respect to theta (coordinated-turn model) by the
+    // reverse-mode adjoint: the cotangent scan from the filtering marginals,
+    // the step VJP contracted with dQ/dtheta and dR/dtheta, fixed-order
+    // per-sequence sums
+    static int loglik_grad(const Ctx &c, const void *m_nom, const void *N_nom, const void *y,
+                           const double *ll_bar, const pss_ckpt *ckpt, double *ll, double *grad,
+                           double *theta_bar, void *ws)
+    {
+        if constexpr (NX == 5 && NY == 2) {
+            const size_t scans = std::max({fscan_bytes(c), ascan_bytes(c), seq_sum_bytes(c, 3)});
+            Carver tail{static_cast<char *>(ws) + gamma_bytes(c) + felem_bytes(c) +
+                        marg_bytes(c) + align256(c.T_y * sizeof(double)) + scans};
+            double *gterms = tail.template take<double>((size_t)3 * c.T_y);
+            double *gseq = tail.template take<double>((size_t)3 * c.B);
+            Carver cv{static_cast<char *>(ws)};
+            pss_gamma gw;
+            T *mf;
+            void *scan_ws;
+            int rc = grad_forward(c, nullptr, m_nom, N_nom, y, ckpt, ll, cv, gw, mf, scan_ws);
+            if (rc)
+                return rc;
+            const CTHost h = ct_host(c.p);
+            ThetaOut<T, NX, NY> out;
+            for (int i = 0; i < 5; ++i)
+                for (int j = 0; j < 5; ++j) {
+                    double a1 = 0.0, a2 = 0.0;
+                    for (int q = 0; q < 5; ++q) {
+                        a1 += h.L1[i][q] * h.L1[j][q];
+                        a2 += h.L2[i][q] * h.L2[j][q];
+                    }
+                    out.th.dQ1[i][j] = (T)a1;
+                    out.th.dQ2[i][j] = (T)a2;
+                }
+            out.th.dR = (T)(2.0 * h.sigma * h.sigma);
+            out.terms = gterms;
+            out.T_y = c.T_y;
+            AdjDst<T, NX> dst{nullptr, nullptr, nullptr, nullptr, c.B};
+            if ((rc = ascan(c, &gw, y, mf, mf + (size_t)NX * c.T_x, out, dst, scan_ws)))
+                return rc;
+            double *gout = grad ? grad : gseq;
+            if ((rc = launch_seq_sum(c, 3, gterms, c.T_y, gout, scan_ws)))
+                return rc;
+            if (theta_bar)
+                rc = launch_weighted_grad(c, gout, ll_bar, theta_bar);
+            return rc;
+        } else {
+            set_error("the theta gradient needs the coordinated-turn model");
+            return PSS_EUNSUPPORTED;
+        }
+    }
+
+    // VJP of the log-likelihood with respect to the linearisation (every
+    // step's Gamma in the library's representation) and the prior
+    static int loglik_vjp(const Ctx &c, const pss_gamma *gin, const void *m_nom,
+                          const void *N_nom, const void *y, const double *ll_bar,
+                          const pss_ckpt *ckpt, double *ll, const pss_gamma *gbar, void *m0_bar,
+                          void *N0_bar, void *ws)
+    {
+        Carver cv{static_cast<char *>(ws)};
+        pss_gamma gw;
+        T *mf;
+        void *scan_ws;
+        int rc = grad_forward(c, gin, m_nom, N_nom, y, ckpt, ll, cv, gw, mf, scan_ws);
+        if (rc)
+            return rc;
+        GammaOut<T, NX, NY> out;
+        out.bar = gamma_ref(gbar, c.T_y);
+        out.w = ll_bar;
+        AdjDst<T, NX> dst{mptr<T>(m0_bar), mptr<T>(N0_bar), cptr<T>(c.p->N0), ll_bar, c.B};
+        return ascan(c, &gw, y, mf, mf + (size_t)NX * c.T_x, out, dst, scan_ws);
+    }
+
+    // the frozen-nominal score by Fisher's identity from the parallel
+    // smoother (a cross-check of the adjoint)
+    static int score_fisher(const Ctx &c, const void *m_nom, const void *N_nom, const void *y,
+                            const double *ll_bar, double *ll, double *grad, double *theta_bar,
+                            void *ws)
+    {
+        // layout: [gamma | felem | mf | ell | scan ws ...] then the score part
         // after the largest scan workspace
         Carver cv{static_cast<char *>(ws)};
         pss_gamma gw;
@@ -836,16 +1088,44 @@ int Impl<T, NX, NY>::ipls(const Ctx &c, const pss_gamma *g, const void *y, int n
 }
 template <typename T, int NX, int NY>
 int Impl<T, NX, NY>::loglik(const Ctx &c, const pss_gamma *g, const void *m_nom,
-                            const void *N_nom, const void *y, double *ll, void *ws)
+                            const void *N_nom, const void *y, double *ll, const pss_ckpt *ckpt,
+                            void *ws)
 {
-    return Core<T, NX, NY>::loglik(c, g, m_nom, N_nom, y, ll, ws);
+    return Core<T, NX, NY>::loglik(c, g, m_nom, N_nom, y, ll, ckpt, ws);
 }
 template <typename T, int NX, int NY>
 int Impl<T, NX, NY>::loglik_grad(const Ctx &c, const void *m_nom, const void *N_nom,
-                                 const void *y, const double *ll_bar, double *ll, double *grad,
-                                 double *theta_bar, void *ws)
+                                 const void *y, const double *ll_bar, const pss_ckpt *ckpt,
+                                 double *ll, double *grad, double *theta_bar, void *ws)
 {
-    return Core<T, NX, NY>::loglik_grad(c, m_nom, N_nom, y, ll_bar, ll, grad, theta_bar, ws);
+    return Core<T, NX, NY>::loglik_grad(c, m_nom, N_nom, y, ll_bar, ckpt, ll, grad, theta_bar,
+                                        ws);
+}
+template <typename T, int NX, int NY>
+int Impl<T, NX, NY>::loglik_vjp(const Ctx &c, const pss_gamma *g, const void *m_nom,
+                                const void *N_nom, const void *y, const double *ll_bar,
+                                const pss_ckpt *ckpt, double *ll, const pss_gamma *gbar,
+                                void *m0_bar, void *N0_bar, void *ws)
+{
+    return Core<T, NX, NY>::loglik_vjp(c, g, m_nom, N_nom, y, ll_bar, ckpt, ll, gbar, m0_bar,
+                                       N0_bar, ws);
+}
+template <typename T, int NX, int NY>
+int Impl<T, NX, NY>::score_fisher(const Ctx &c, const void *m_nom, const void *N_nom,
+                                  const void *y, const double *ll_bar, double *ll, double *grad,
+                                  double *theta_bar, void *ws)
+{
+    return Core<T, NX, NY>::score_fisher(c, m_nom, N_nom, y, ll_bar, ll, grad, theta_bar, ws);
+}
+template <typename T, int NX, int NY>
+size_t Impl<T, NX, NY>::ckpt_bytes(const Ctx &c, int level)
+{
+    return Core<T, NX, NY>::ckpt_bytes(c, level);
+}
+template <typename T, int NX, int NY>
+int Impl<T, NX, NY>::filter_levels(const Ctx &c)
+{
+    return Core<T, NX, NY>::filter_levels(c);
 }
 template <typename T, int NX, int NY>
 int Impl<T, NX, NY>::sequential(const Ctx &c, const pss_gamma *g, const void *y, int n_iter,

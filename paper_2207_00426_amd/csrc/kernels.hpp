@@ -19,6 +19,8 @@
 // consecutive lanes touch consecutive words.
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 #include "device_cov.hpp"
 #include "device_ops.hpp"
@@ -736,12 +738,22 @@ PSS_INL void src_fold(const Src &src, const TileInfo &ti, int64_t p, const V &ac
     }
 }
 
+// A source with fused_down (the adjoint's finest level) applies element p to
+// the prefix itself and may emit per-element results from both.
+template <class S, class = void>
+struct fused_down_of : std::false_type {};
+template <class S>
+struct fused_down_of<S, std::void_t<decltype(S::fused_down)>>
+    : std::integral_constant<bool, S::fused_down> {};
+
 template <class Op, class Src>
 PSS_INL void src_apply(const Src &src, const TileInfo &ti, int64_t p, const typename Op::Pre &P,
                        typename Op::Pre &Q)
 {
     constexpr int nz = leaf_cols<Src, Op::NX>();
-    if constexpr (Src::lazy_down) {
+    if constexpr (fused_down_of<Src>::value) {
+        src.down_apply(ti, p, P, Q);
+    } else if constexpr (Src::lazy_down) {
         Op::template apply_v<nz>(P, src.dview(ti, p), Q);
     } else {
         typename Op::Elem e;

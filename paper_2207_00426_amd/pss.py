@@ -31,7 +31,7 @@ LINEARIZATIONS = {"cubature": LIN_CUBATURE, "taylor": LIN_TAYLOR, "unscented": L
 FORM_SQRT, FORM_COV = 0, 1
 FORMS = {"sqrt": FORM_SQRT, "cov": FORM_COV}
 OPS = dict(slr=0, filter_elements=1, filter_scan=2, smoother_scan=3, ipls=4, loglik=5,
-           loglik_grad=6, sequential=7, loglik_grad_ift=8)
+           loglik_grad=6, sequential=7, loglik_grad_ift=8, loglik_vjp=9, score_fisher=10)
 STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported", -3: "workspace too small",
           -4: "HIP error"}
 EXPORTS = ["pss_workspace_size", "pss_slr_linearize", "pss_sqrt_filter_elements",
@@ -39,7 +39,8 @@ EXPORTS = ["pss_workspace_size", "pss_slr_linearize", "pss_sqrt_filter_elements"
            "pss_loglik_grad", "pss_sequential_smoother", "pss_validate", "pss_last_error",
            "pss_version", "pss_batched_workspace_size", "pss_ipls_batched",
            "pss_autotune_workspace_size", "pss_autotune", "pss_kernel_timing",
-           "pss_kernel_times", "pss_loglik_grad_ift"]
+           "pss_kernel_times", "pss_loglik_grad_ift", "pss_ckpt_size", "pss_loglik_vjp",
+           "pss_score_fisher"]
 
 
 class PssError(RuntimeError):
@@ -76,6 +77,11 @@ class FElemC(ctypes.Structure):
                 ("eta", ctypes.c_void_p), ("Z", ctypes.c_void_p)]
 
 
+class CkptC(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int32), ("buf", ctypes.c_void_p), ("bytes", ctypes.c_size_t),
+                ("tag", ctypes.c_uint64)]
+
+
 _lib = None
 
 
@@ -102,8 +108,14 @@ def lib():
                                              vp]
         L.pss_ipls_iterate.argtypes = [P, ctypes.POINTER(GammaC), vp, i32, vp, vp, vp, vp, vp,
                                        sz, vp]
-        L.pss_loglik.argtypes = [P, ctypes.POINTER(GammaC), vp, vp, vp, vp, vp, sz, vp]
-        L.pss_loglik_grad.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+        CK = ctypes.POINTER(CkptC)
+        L.pss_ckpt_size.restype = sz
+        L.pss_ckpt_size.argtypes = [P, i32]
+        L.pss_loglik.argtypes = [P, ctypes.POINTER(GammaC), vp, vp, vp, vp, CK, vp, sz, vp]
+        L.pss_loglik_grad.argtypes = [P, vp, vp, vp, vp, CK, vp, vp, vp, vp, sz, vp]
+        L.pss_loglik_vjp.argtypes = [P, ctypes.POINTER(GammaC), vp, vp, vp, vp, CK, vp,
+                                     ctypes.POINTER(GammaC), vp, vp, vp, sz, vp]
+        L.pss_score_fisher.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
         L.pss_sequential_smoother.argtypes = [P, ctypes.POINTER(GammaC), vp, i32, vp, vp, vp, vp,
                                               vp, sz, vp]
         L.pss_loglik_grad_ift.argtypes = [P, vp, vp, vp, i32, vp, vp, vp, vp, sz, vp]
@@ -123,7 +135,7 @@ def lib():
         for name in ("pss_slr_linearize", "pss_sqrt_filter_elements", "pss_sqrt_filter_scan",
                      "pss_sqrt_smoother_scan", "pss_ipls_iterate", "pss_loglik",
                      "pss_loglik_grad", "pss_sequential_smoother", "pss_validate",
-                     "pss_loglik_grad_ift"):
+                     "pss_loglik_grad_ift", "pss_loglik_vjp", "pss_score_fisher"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -456,8 +468,37 @@ def sequential_smoother(batch, y, n_iter, m_nom=None, N_nom=None, gamma=None, wa
     return (m_nom, N_nom, m_f, N_f) if want_filter else (m_nom, N_nom)
 
 
-def loglik(batch, y, m_nom=None, N_nom=None, gamma=None, ws=None):
-    """Pseudo-log-likelihood per sequence (float64 [B])."""
+class Checkpoint:
+    """A pss_ckpt: device buffer (torch uint8) plus the C struct.  level 0
+    keeps every filtering marginal, level l >= 1 the filter scan's level-l
+    prefixes (the gradient re-runs the levels below), a level at or above the
+    scan's top only the log-likelihoods."""
+
+    def __init__(self, batch, level=0):
+        self.level = int(level)
+        self.bytes = ckpt_size(batch, self.level)
+        self.buf = torch.empty(max(self.bytes, 1), dtype=torch.uint8, device=batch.device)
+        self.c = CkptC()
+        self.c.level = self.level
+        self.c.buf = self.buf.data_ptr()
+        self.c.bytes = self.bytes
+        self.c.tag = 0
+
+    def ref(self):
+        return ctypes.byref(self.c)
+
+
+def ckpt_size(batch, level) -> int:
+    p = batch.struct()
+    return int(lib().pss_ckpt_size(ctypes.byref(p), int(level)))
+
+
+def _ckpt_ref(ckpt):
+    return None if ckpt is None else ckpt.ref()
+
+
+def loglik(batch, y, m_nom=None, N_nom=None, gamma=None, ws=None, ckpt=None):
+    """Pseudo-log-likelihood per sequence (float64 [B]); fills ckpt if given."""
     _require_gpu()
     ll = torch.empty(batch.B, dtype=torch.float64, device=batch.device)
     if ws is None:
@@ -466,12 +507,13 @@ def loglik(batch, y, m_nom=None, N_nom=None, gamma=None, ws=None):
         n = ws.numel()
     p = batch.struct()
     _check(lib().pss_loglik(ctypes.byref(p), _gamma_c(gamma), _ptr(m_nom), _ptr(N_nom), _ptr(y),
-                            _ptr(ll), _ptr(ws), n, _stream()))
+                            _ptr(ll), _ckpt_ref(ckpt), _ptr(ws), n, _stream()))
     return ll
 
 
-def loglik_grad(batch, m_nom, N_nom, y, ll_bar=None, ws=None):
-    """(ll [B], grad [3, B], theta_bar [3]) at the frozen nominal."""
+def loglik_grad(batch, m_nom, N_nom, y, ll_bar=None, ws=None, ckpt=None):
+    """(ll [B], grad [3, B], theta_bar [3]) at the frozen nominal, by the
+    reverse-mode adjoint (from ckpt when given)."""
     _require_gpu()
     dev = batch.device
     ll = torch.empty(batch.B, dtype=torch.float64, device=dev)
@@ -485,33 +527,81 @@ def loglik_grad(batch, m_nom, N_nom, y, ll_bar=None, ws=None):
         ll_bar = ll_bar.to(device=dev, dtype=torch.float64).contiguous()
     p = batch.struct()
     _check(lib().pss_loglik_grad(ctypes.byref(p), _ptr(m_nom), _ptr(N_nom), _ptr(y),
-                                 _ptr(ll_bar), _ptr(ll), _ptr(grad), _ptr(tb), _ptr(ws), n,
-                                 _stream()))
+                                 _ptr(ll_bar), _ckpt_ref(ckpt), _ptr(ll), _ptr(grad), _ptr(tb),
+                                 _ptr(ws), n, _stream()))
     return ll, grad, tb
+
+
+def score_fisher(batch, m_nom, N_nom, y, ll_bar=None, ws=None):
+    """The same gradient by Fisher's identity from the smoother (cross-check)."""
+    _require_gpu()
+    dev = batch.device
+    ll = torch.empty(batch.B, dtype=torch.float64, device=dev)
+    grad = torch.empty((3, batch.B), dtype=torch.float64, device=dev)
+    tb = torch.empty(3, dtype=torch.float64, device=dev)
+    if ws is None:
+        ws, n = batch.workspace("score_fisher")
+    else:
+        n = ws.numel()
+    if ll_bar is not None:
+        ll_bar = ll_bar.to(device=dev, dtype=torch.float64).contiguous()
+    p = batch.struct()
+    _check(lib().pss_score_fisher(ctypes.byref(p), _ptr(m_nom), _ptr(N_nom), _ptr(y),
+                                  _ptr(ll_bar), _ptr(ll), _ptr(grad), _ptr(tb), _ptr(ws), n,
+                                  _stream()))
+    return ll, grad, tb
+
+
+def loglik_vjp(batch, y, m_nom=None, N_nom=None, gamma=None, ll_bar=None, ws=None, ckpt=None,
+               prior=True):
+    """VJP of the log-likelihood with respect to every step's linearisation
+    and the prior: (ll [B], g_bar (stride-1 Gamma dict of cotangents),
+    m0_bar [nx, B], N0_bar [P, B]) -- the prior parts None if not prior."""
+    _require_gpu()
+    dev = batch.device
+    ll = torch.empty(batch.B, dtype=torch.float64, device=dev)
+    gbar = batch.new_gamma(1)
+    m0b = N0b = None
+    if prior:
+        m0b = batch.empty(batch.nx, batch.B)
+        N0b = batch.empty(tri(batch.nx), batch.B)
+    if ws is None:
+        ws, n = batch.workspace("loglik_vjp")
+    else:
+        n = ws.numel()
+    if ll_bar is not None:
+        ll_bar = ll_bar.to(device=dev, dtype=torch.float64).contiguous()
+    p = batch.struct()
+    _check(lib().pss_loglik_vjp(ctypes.byref(p), _gamma_c(gamma), _ptr(m_nom), _ptr(N_nom),
+                                _ptr(y), _ptr(ll_bar), _ckpt_ref(ckpt), _ptr(ll), _gamma_c(gbar),
+                                _ptr(m0b), _ptr(N0b), _ptr(ws), n, _stream()))
+    return ll, gbar, m0b, N0b
 
 
 class LogLik(torch.autograd.Function):
     """Pseudo-log-likelihood summed over the batch as a function of theta =
-    (log q1, log q2, log sigma) at a frozen nominal; backward runs the
-    library's gradient pass with the incoming cotangent."""
+    (log q1, log q2, log sigma) at a frozen nominal.  The forward pass keeps
+    a checkpoint of its filter pass (level ckpt_level); backward runs the
+    library's reverse-mode adjoint from it with the incoming cotangent."""
 
     @staticmethod
-    def forward(ctx, theta, batch, y, m_nom, N_nom):
+    def forward(ctx, theta, batch, y, m_nom, N_nom, ckpt_level=0):
         th = tuple(float(v) for v in theta.detach().cpu().tolist())
         b2 = _with_theta(batch, th)
-        ll = loglik(b2, y, m_nom, N_nom)
+        ck = Checkpoint(b2, ckpt_level)
+        ll = loglik(b2, y, m_nom, N_nom, ckpt=ck)
         ctx.save_for_backward(theta)
-        ctx.stuff = (b2, y, m_nom, N_nom)
+        ctx.stuff = (b2, y, m_nom, N_nom, ck)
         return ll.sum().to(theta.dtype)
 
     @staticmethod
     def backward(ctx, g):
         (theta,) = ctx.saved_tensors
-        b2, y, m_nom, N_nom = ctx.stuff
+        b2, y, m_nom, N_nom, ck = ctx.stuff
         w = torch.full((b2.B,), 1.0, dtype=torch.float64, device=b2.device) * g.to(
             device=b2.device, dtype=torch.float64)
-        _, _, tb = loglik_grad(b2, m_nom, N_nom, y, ll_bar=w)
-        return tb.to(device=theta.device, dtype=theta.dtype), None, None, None, None
+        _, _, tb = loglik_grad(b2, m_nom, N_nom, y, ll_bar=w, ckpt=ck)
+        return tb.to(device=theta.device, dtype=theta.dtype), None, None, None, None, None
 
 
 def loglik_grad_ift(batch, m_nom, N_nom, y, n_iter=30, ws=None, with_delta=False):

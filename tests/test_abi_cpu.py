@@ -73,9 +73,15 @@ def test_null_arguments_rejected_before_any_hip_call(L):
     assert rc == -1
     rc = L.pss_slr_linearize(ctypes.byref(p), None, None, None, None, None)
     assert rc == -2  # a linear model has no SLR
-    rc = L.pss_loglik_grad(ctypes.byref(p), None, None, None, None, None, None, None, None, 0,
-                           None)
+    rc = L.pss_loglik_grad(ctypes.byref(p), None, None, None, None, None, None, None, None,
+                           None, 0, None)
     assert rc == -2
+    rc = L.pss_score_fisher(ctypes.byref(p), None, None, None, None, None, None, None, None, 0,
+                            None)
+    assert rc == -2
+    rc = L.pss_loglik_vjp(ctypes.byref(p), None, None, None, None, None, None, None, None, None,
+                          None, None, 0, None)
+    assert rc == -1
     assert L.pss_validate(None) == -1
 
 
@@ -183,9 +189,15 @@ def test_ricker_model_and_sigma_point_rules_are_validated(L):
     assert "1024" in pss.last_error()
     # the gradient is defined for the CT model only; refused before any HIP call
     p = _ricker_cpu().struct()
-    rc = L.pss_loglik_grad(ctypes.byref(p), None, None, None, None, None, None, None, None, 0,
-                           None)
+    rc = L.pss_loglik_grad(ctypes.byref(p), None, None, None, None, None, None, None, None,
+                           None, 0, None)
     assert rc == -2
+    rc = L.pss_score_fisher(ctypes.byref(p), None, None, None, None, None, None, None, None, 0,
+                            None)
+    assert rc == -2
+    rc = L.pss_loglik_vjp(ctypes.byref(p), None, None, None, None, None, None, None, None, None,
+                          None, None, 0, None)
+    assert rc == -1
     # the persistent pass fuses the cubature / Taylor CT SLR only
     y = ctypes.c_void_p(8)
     for bad in (_ricker_cpu(), _cpu_batch(linearization="unscented", **ct)):
@@ -254,3 +266,42 @@ def test_bench_scan_plan_mirrors_the_library(L, lengths, T, E):
     T_x = int(y_off[-1]) + B
     stash = (45 * T_x * 8 + 255) // 256 * 256
     assert pss.workspace_size(b, "smoother_scan") == _scan_ws_bytes(splan, B, 45, 20, 8) + stash
+
+
+def test_checkpoint_sizes_and_validation(L):
+    """pss_ckpt_size follows the level plan: level 0 keeps every filtering
+    marginal, level l the filter scan's level-l prefixes, levels at or above
+    the top only the log-likelihoods; a wrong tag, a short buffer or the
+    covariance form are refused before any HIP call."""
+    n = 10 ** 5
+    b = pss.Batch(pss.MODEL_CT, torch.float64, 5, 2, np.array([0, n]), np.zeros(5), np.eye(5),
+                  device="cpu", dt=0.01, theta=(0.0, 0.0, 0.0))
+    s0, s1, s2, s9 = (pss.ckpt_size(b, lv) for lv in (0, 1, 2, 9))
+    al = lambda x: (x + 255) // 256 * 256  # noqa: E731
+    assert s0 == al(8) + al(20 * 8 * (n + 1))
+    # flat level 0 folds 4 per thread: n / 4 prefixes at level 1
+    assert s1 == al(8) + al(20 * 8 * (n // 4))
+    assert s2 == al(8) + al(20 * 8 * -(-n // (4 * 256)))
+    assert s9 == al(8)
+    assert s0 > s1 > s2 > s9
+    assert pss.ckpt_size(b, -1) == 0
+    p = b.struct()
+    ck = pss.CkptC()
+    ck.level = 0
+    ck.buf = 1
+    ck.bytes = s0 - 1
+    ck.tag = 0
+    ws = ctypes.c_void_p(1)
+    big = 1 << 40
+    # consuming: short buffer, then a tag of another problem
+    rc = L.pss_loglik_grad(ctypes.byref(p), ws, ws, ws, None, ctypes.byref(ck), ws, ws, ws, ws,
+                           big, None)
+    assert rc == -3 and "checkpoint" in pss.last_error()
+    ck.bytes = s0
+    rc = L.pss_loglik_grad(ctypes.byref(p), ws, ws, ws, None, ctypes.byref(ck), ws, ws, ws, ws,
+                           big, None)
+    assert rc == -1 and "another problem" in pss.last_error()
+    b.form = pss.FORM_COV
+    p = b.struct()
+    rc = L.pss_loglik(ctypes.byref(p), None, ws, ws, ws, ws, ctypes.byref(ck), ws, big, None)
+    assert rc == -2
