@@ -270,6 +270,23 @@ int pss_ipls_iterate(const pss_problem *p, const pss_gamma *g, const void *y, in
    error set for an invalid problem or a negative level). */
 size_t pss_ckpt_size(const pss_problem *p, int32_t level);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the same
+   n_iter passes as pss_ipls_iterate, same arguments and outputs, with the
+   workspace taken from a file-scope device array of the library instead of
+   a caller buffer.  Makes no allocation.  The array holds
+   pss_noalloc_max_bytes() bytes (64 MiB: about 4 * 10^4 coordinated-turn
+   steps in FP64); a problem whose PSS_OP_IPLS workspace is larger is refused
+   with PSS_EWORKSPACE before anything is enqueued.  Each GPU the library
+   runs on holds its own copy until the process ends.  Every call on one GPU
+   shares that GPU's copy: calls that overlap in time on one GPU (several
+   streams or threads) race and give undefined results.  The array keeps the
+   last call's contents; nothing in it needs to start at zero. */
+size_t pss_noalloc_max_bytes(void);
+int pss_ipls_iterate_noalloc(const pss_problem *p, const pss_gamma *g, const void *y,
+                             int32_t n_iter, void *m_nom, void *N_nom, void *m_f, void *N_f,
+                             hipStream_t stream);
+
 /* Pseudo-log-likelihood of Section 5.1: the model is linearised at the
    nominal (nonlinear models; for LINEAR `g` is used), filtered with
    Algorithm 1, and

@@ -65,7 +65,8 @@ def build(jobs: int | None = None, verbose: bool = False, extra_flags=(),
     jobs = jobs or min(8, os.cpu_count() or 4)
     units = [(os.path.join(CSRC, "api.hip"), os.path.join(BUILD, "api.o"), []),
              (os.path.join(CSRC, "persistent.hip"), os.path.join(BUILD, "persistent.o"), []),
-             (os.path.join(CSRC, "ift_api.hip"), os.path.join(BUILD, "ift_api.o"), [])]
+             (os.path.join(CSRC, "ift_api.hip"), os.path.join(BUILD, "ift_api.o"), []),
+             (os.path.join(CSRC, "noalloc.hip"), os.path.join(BUILD, "noalloc.o"), [])]
     # the fixed-point gradient's dual-number passes: one unit per precision
     # and half (they are the slowest units to compile)
     for t in DTYPES:

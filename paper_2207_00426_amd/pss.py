@@ -40,7 +40,7 @@ EXPORTS = ["pss_workspace_size", "pss_slr_linearize", "pss_sqrt_filter_elements"
            "pss_version", "pss_batched_workspace_size", "pss_ipls_batched",
            "pss_autotune_workspace_size", "pss_autotune", "pss_kernel_timing",
            "pss_kernel_times", "pss_loglik_grad_ift", "pss_ckpt_size", "pss_loglik_vjp",
-           "pss_score_fisher"]
+           "pss_score_fisher", "pss_noalloc_max_bytes", "pss_ipls_iterate_noalloc"]
 
 
 class PssError(RuntimeError):
@@ -116,6 +116,10 @@ def lib():
         L.pss_loglik_vjp.argtypes = [P, ctypes.POINTER(GammaC), vp, vp, vp, vp, CK, vp,
                                      ctypes.POINTER(GammaC), vp, vp, vp, sz, vp]
         L.pss_score_fisher.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.pss_noalloc_max_bytes.restype = sz
+        L.pss_noalloc_max_bytes.argtypes = []
+        L.pss_ipls_iterate_noalloc.argtypes = [P, ctypes.POINTER(GammaC), vp, i32, vp, vp, vp,
+                                               vp, vp]
         L.pss_sequential_smoother.argtypes = [P, ctypes.POINTER(GammaC), vp, i32, vp, vp, vp, vp,
                                               vp, sz, vp]
         L.pss_loglik_grad_ift.argtypes = [P, vp, vp, vp, i32, vp, vp, vp, vp, sz, vp]
@@ -135,7 +139,8 @@ def lib():
         for name in ("pss_slr_linearize", "pss_sqrt_filter_elements", "pss_sqrt_filter_scan",
                      "pss_sqrt_smoother_scan", "pss_ipls_iterate", "pss_loglik",
                      "pss_loglik_grad", "pss_sequential_smoother", "pss_validate",
-                     "pss_loglik_grad_ift", "pss_loglik_vjp", "pss_score_fisher"):
+                     "pss_loglik_grad_ift", "pss_loglik_vjp", "pss_score_fisher",
+                     "pss_ipls_iterate_noalloc"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
