@@ -17,17 +17,25 @@ Also in the line (same run):
   sequential      time per IPLS pass of the parallel scans vs the sequential
                   square-root kernel (one thread walks the sequence) at
                   n = 10^4 and 10^5 (prefixes of the same sequence)
-  loglik_grad_ms  one loglik + gradient evaluation on 64 CT sequences of
-                  10^4 steps (the parameter-estimation configuration), and 50
+  loglik_grad_ms  one loglik + gradient evaluation (the reverse-mode
+                  adjoint) on 64 CT sequences of 10^4 steps (the parameter-
+                  estimation configuration), with the checkpointed split
+                  (forward with a checkpoint of each level, backward from it,
+                  bytes kept) and the Fisher-identity route beside it, and 50
                   L-BFGS steps on theta from theta* + 0.5 on that batch (IPLS
                   re-run at every evaluation)
   kernels         every scan kernel of one filter and one smoother scan,
                   timed per launch with HIP events on its stream, with the
                   counted flops it executes
-  roofline        the kernel with the largest time among those; bound =
-                  vector ALU; traffic = counter HBM bytes per launch from the
-                  committed rocprofv3 summary, when it was taken on these
-                  kernels
+  roofline        the kernel with the largest time among those: its counted
+                  flops and algorithmic bytes per launch over its time, against
+                  78.6 TFLOP/s (vector ALU) and 8 TB/s (HBM); bound = the larger
+                  of the two lower bounds; traffic = counter HBM bytes per
+                  launch from the committed rocprofv3 summary, when it was
+                  taken on these kernels
+  pass            one IPLS pass (its kernels once each): time, flops, the
+                  algorithmic bytes and the counter bytes against the fused
+                  minimum (the nominal and y in, the nominal out)
   fp32_divergence share of FP32 runs whose log-likelihood is NaN, square-root
                   vs standard covariance form (15 CT sequences per length,
                   20 passes; FP64 as a control)
@@ -55,14 +63,20 @@ from paper_2207_00426_amd import pss  # noqa: E402
 from paper_2207_00426_amd import workloads as wl  # noqa: E402
 
 # Counted floating-point operations of the nx = 5, ny = 2 operators (add,
-# multiply, reciprocal, square root = 1; fused multiply-add = 2), obtained by
-# instantiating the register code on a counting number type.  "_leaf": the
-# filter operator with a finest-level element on the right, whose Z has only
-# ny non-zero columns.
-FLOPS = dict(filter_combine=3363, filter_apply=2300, filter_combine_leaf=2492,
-             filter_apply_leaf=1805, smoother_combine=740, smoother_apply=515,
-             filter_element=1261, smoother_element=1514, slr_transition=938, slr_bearings=488)
+# multiply, divide, reciprocal, square root = 1; fused multiply-add = 2;
+# transcendentals apart), from tests/flop_count.cpp, which instantiates the
+# library's register code on a counting number type
+# (tests/test_flop_counts_cpu.py keeps these equal to its output).  "_leaf":
+# the filter operator with a finest-level element on the right, whose Z has
+# only ny non-zero columns.  adjoint_element: the Kalman step and its map
+# T_k; adjoint_cotangents: the Gram cotangents and the theta contraction.
+FLOPS = dict(filter_combine=3331, filter_combine_leaf=2476, filter_apply=2292,
+             filter_apply_leaf=1797, smoother_combine=732, smoother_apply=503,
+             filter_element=1248, smoother_element=1510, slr_transition=942, slr_bearings=470,
+             adjoint_element=1469, adjoint_combine=740, adjoint_apply=515,
+             adjoint_cotangents=966)
 PEAK = {"f64": 78.6, "f32": 78.6}  # TFLOP/s vector ALU (FP32 without packed instructions)
+HBM_GBPS = 8000.0  # MI355X HBM3E peak
 
 
 def parse():
@@ -117,6 +131,8 @@ def scan_kernel_flops(op, lengths, T0, E0, Tup, E1, Eup, flat0):
     combines up, elems applies down.  The smoother's level-0 up-sweep also
     builds its elements (one per state)."""
     comb, app = FLOPS[op + "_combine"], FLOPS[op + "_apply"]
+    if op == "adjoint":
+        comb, app = FLOPS["adjoint_combine"], FLOPS["adjoint_apply"]
     # the filter's finest level folds and applies leaf elements (elements -
     # threads fold combines, elements applies); its trees use the general form
     lcomb = FLOPS.get(op + "_combine_leaf", comb)
@@ -135,11 +151,57 @@ def scan_kernel_flops(op, lengths, T0, E0, Tup, E1, Eup, flat0):
             down = (elems + threads - tiles) * app
         if op == "smoother" and l == 0:
             up += elems * FLOPS["smoother_element"]
+        if op == "adjoint" and l == 0:
+            # the map of every step is built in the up-sweep and again in the
+            # down-sweep, which also forms the step's cotangents
+            up += elems * FLOPS["adjoint_element"]
+            down += elems * (FLOPS["adjoint_element"] + FLOPS["adjoint_cotangents"])
         if l == len(plan) - 1:
             out[(op + "_top", l)] = up + down
         else:
             out[(op + "_up", l)] = up
             out[(op + "_down", l)] = down
+    return out
+
+
+# numbers per object (CT, nx = 5, ny = 2): marginal (m, packed N), filter
+# element, smoother element / adjoint map, linearisation parts
+NUM = dict(marg=20, felem=65, selem=45, gam_trans=45, gam_obs=15, y=2)
+
+
+def scan_kernel_bytes(op, lengths, T0, E0, Tup, E1, Eup, flat0, esz, B=1):
+    """Algorithmic HBM bytes of each kernel of one scan, keyed (kernel,
+    level): every input the kernel's contract needs read once and every
+    output written once, in the library's storage design (elements of the
+    level, the tile's saved LDS tree, tile aggregates, exclusive prefixes).
+    Level-0 inputs: filter elements (filter); the filtering marginal and the
+    transition part of Gamma per state, plus the element stash written in
+    the up-sweep and read in the down-sweep (smoother); the marginal, Gamma
+    and y per step, and 3 FP64 theta terms written per step (adjoint)."""
+    plan = scan_plan(lengths, T0, E0, Tup, E1, Eup, flat0)
+    ne = NUM["felem"] if op == "filter" else NUM["selem"]
+    npre = NUM["marg"]
+    out = {}
+    for l, (T, E, elems, tiles, threads, flat) in enumerate(plan):
+        top = l == len(plan) - 1
+        tree = 0 if (flat or top) else tiles * T * ne
+        if l == 0 and op == "smoother":
+            src_up = elems * npre + (elems - B) * NUM["gam_trans"] + elems * NUM["selem"]
+            src_down = elems * NUM["selem"]
+        elif l == 0 and op == "adjoint":
+            src_up = src_down = elems * (npre + NUM["gam_trans"] + NUM["gam_obs"] + NUM["y"])
+        else:
+            src_up = src_down = elems * ne
+        agg = threads * ne if flat else tiles * ne
+        pre_in = threads * npre if flat else tiles * npre
+        outs = elems * npre * esz
+        if l == 0 and op == "adjoint":
+            outs = elems * 3 * 8
+        if top:
+            out[(op + "_top", l)] = src_up * esz + outs
+        else:
+            out[(op + "_up", l)] = (src_up + tree + agg) * esz
+            out[(op + "_down", l)] = (src_down + tree + pre_in) * esz + outs
     return out
 
 
@@ -602,30 +664,71 @@ def main():
         }
         log("stages (ms): " + ", ".join("%s %.3f" % kv for kv in stage.items()))
         fshape = shapes(args.dtype, args.scan_threads, args.scan_elems)
+        sshape = shapes(args.dtype, args.scan_threads, args.scan_elems, True)
+        ashape = (fshape[0], 2, min(fshape[0], 64), 2, 2, False)  # adjoint scan
         T0, E0 = fshape[0], fshape[1]
+        esz = 8 if args.dtype == "f64" else 4
         kflops = scan_kernel_flops("filter", [n], *fshape)
-        kflops.update(scan_kernel_flops(
-            "smoother", [n + 1], *shapes(args.dtype, args.scan_threads, args.scan_elems, True)))
-        E0s = shapes(args.dtype, args.scan_threads, args.scan_elems, True)[1]
+        kflops.update(scan_kernel_flops("smoother", [n + 1], *sshape))
+        kflops.update(scan_kernel_flops("adjoint", [n], *ashape))
+        kbytes = scan_kernel_bytes("filter", [n], *fshape, esz)
+        kbytes.update(scan_kernel_bytes("smoother", [n + 1], *sshape, esz))
+        kbytes.update(scan_kernel_bytes("adjoint", [n], *ashape, esz))
+        E0s = sshape[1]
         kflops[("slr", 0)] = n * (FLOPS["slr_transition"] + FLOPS["slr_bearings"])
         kflops[("filter_elements", 0)] = n * FLOPS["filter_element"]
         kflops[("slr_felem", 0)] = n * (FLOPS["slr_transition"] + FLOPS["slr_bearings"] +
                                          FLOPS["filter_element"])
+        gam = NUM["gam_trans"] + NUM["gam_obs"]
+        kbytes[("slr", 0)] = ((n + 1) * NUM["marg"] + n * (NUM["y"] + gam)) * esz
+        kbytes[("filter_elements", 0)] = n * (gam + NUM["y"] + NUM["felem"]) * esz
+        kbytes[("slr_felem", 0)] = ((n + 1) * NUM["marg"] +
+                                    n * (NUM["y"] + NUM["gam_trans"] + NUM["felem"])) * esz
+        kbytes[("loglik_terms", 0)] = n * (NUM["marg"] + gam + NUM["y"]) * esz + n * 8
         kernels = {}
         for key, (calls, tot) in sorted(ktimes.items()):
             avg = tot / calls
-            fl_k = kflops.get(key)
+            fl_k, by_k = kflops.get(key), kbytes.get(key)
             kernels["%s_L%d" % key] = {
                 "launches": calls, "avg_ms": round(avg, 5),
-                "flops_per_launch": fl_k,
-                "tflops": None if fl_k is None else round(fl_k / (avg * 1e-3) / 1e12, 4)}
-        dom = max((k for k in ktimes if k in kflops), key=lambda k: ktimes[k][1])
+                "flops_per_launch": fl_k, "alg_bytes_per_launch": by_k,
+                "tflops": None if fl_k is None else round(fl_k / (avg * 1e-3) / 1e12, 4),
+                "alg_GBps": None if by_k is None else round(by_k / (avg * 1e-3) / 1e9, 1)}
+        dom = max((k for k in ktimes if k in kflops and k in kbytes),
+                  key=lambda k: ktimes[k][1])
         dom_ms = ktimes[dom][1] / ktimes[dom][0]
-        fl = kflops[dom]
-        achieved = fl / (dom_ms * 1e-3) / 1e12
+        fl, by = kflops[dom], kbytes[dom]
+        t_dom = dom_ms * 1e-3
+        alu_frac = fl / t_dom / 1e12 / PEAK[args.dtype]
+        hbm_frac = by / t_dom / 1e9 / HBM_GBPS
+        # the bound is the larger of the two lower bounds on the launch time
+        bound = "hbm" if by / (HBM_GBPS * 1e9) >= fl / (PEAK[args.dtype] * 1e12) else "alu"
         traffic = counter_traffic(dom[0], dom[1], args.dtype, n)
-        log("dominant kernel %s level %d: %.4f ms, %.3f TFLOP/s" % (dom[0], dom[1], dom_ms,
-                                                                    achieved))
+        log("dominant kernel %s level %d: %.4f ms, %.3f TFLOP/s (ALU %.3f), %.0f GB/s "
+            "algorithmic (HBM %.3f) -> %s bound" % (dom[0], dom[1], dom_ms, fl / t_dom / 1e12,
+                                                   alu_frac, by / t_dom / 1e9, hbm_frac, bound))
+        # one IPLS pass as a whole: its kernels once each
+        pass_keys = [k for k in ktimes if k[0] in ("slr", "filter_elements", "slr_felem") or
+                     k[0].startswith(("filter_up", "filter_down", "filter_top", "smoother_up",
+                                      "smoother_down", "smoother_top"))]
+        pass_ms = sum(ktimes[k][1] / ktimes[k][0] for k in pass_keys)
+        pass_fl = sum(kflops.get(k, 0) for k in pass_keys)
+        pass_by = sum(kbytes.get(k, 0) for k in pass_keys)
+        pass_tr = [counter_traffic(k[0], k[1], args.dtype, n) for k in pass_keys]
+        pass_tr = None if any(v is None for v in pass_tr) else sum(pass_tr)
+        fused_min = n * 102 * esz  # nominal + y in, nominal + filter marginals out
+        pass_info = {
+            "kernels": ["%s_L%d" % k for k in sorted(pass_keys)],
+            "ms": round(pass_ms, 4), "steps_per_s": round(n / (pass_ms * 1e-3), 1),
+            "flops": int(pass_fl), "tflops": round(pass_fl / (pass_ms * 1e-3) / 1e12, 3),
+            "alu_frac": round(pass_fl / (pass_ms * 1e-3) / 1e12 / PEAK[args.dtype], 4),
+            "alg_bytes": int(pass_by), "fused_min_bytes": fused_min,
+            "counter_bytes": pass_tr,
+            "counter_hbm_frac": None if pass_tr is None else round(
+                pass_tr / (pass_ms * 1e-3) / 1e9 / HBM_GBPS, 4),
+            "counter_over_fused_min": None if pass_tr is None else round(pass_tr / fused_min, 2)}
+        log("pass: %.3f ms, %.2f TFLOP/s, counter bytes %s" % (pass_ms, pass_info["tflops"],
+                                                               pass_tr))
         del R, gam, fel, mf, Nf, ms_, Ns_, ws_f, ws_s
         torch.cuda.empty_cache()
 
@@ -693,12 +796,31 @@ def main():
                 mm, NN = pss.ipls_iterate(bb, yy, M)
                 wg, _ = bb.workspace("loglik_grad")
                 t_g = timed(stream, lambda: pss.loglik_grad(bb, mm, NN, yy, ws=wg), 10)
+                wf, _ = bb.workspace("score_fisher")
+                t_f = timed(stream, lambda: pss.score_fisher(bb, mm, NN, yy, ws=wf), 10)
+                wl_, _ = bb.workspace("loglik")
+                t_l = timed(stream, lambda: pss.loglik(bb, yy, mm, NN, ws=wl_), 10)
+                # checkpoint depth: bytes kept between the forward and the
+                # backward call, and the backward's time from it
+                ck = {}
+                for level in (0, 1, 2, 9):
+                    cp = pss.Checkpoint(bb, level)
+                    t_fw = timed(stream, lambda: pss.loglik(bb, yy, mm, NN, ws=wl_, ckpt=cp), 5)
+                    t_bw = timed(stream, lambda: pss.loglik_grad(bb, mm, NN, yy, ws=wg, ckpt=cp),
+                                 5)
+                    ck["level%d" % level] = {"bytes": cp.bytes, "forward_ms": round(t_fw, 4),
+                                             "backward_ms": round(t_bw, 4)}
+                    del cp
                 wi, _ = bb.workspace("ipls")
                 m0, N0 = bb.prior_nominal()
                 t_i = timed(stream, lambda: (mm.copy_(m0), NN.copy_(N0),
                                              pss.ipls_iterate(bb, yy, M, mm, NN, ws=wi)), 3)
-                lg[dt] = {"loglik_plus_grad_ms": round(t_g, 4), "ipls_ms": round(t_i, 4)}
-                log("64x1e4 %s: loglik+grad %.3f ms, IPLS %.3f ms" % (dt, t_g, t_i))
+                lg[dt] = {"loglik_plus_grad_ms": round(t_g, 4), "loglik_ms": round(t_l, 4),
+                          "fisher_route_ms": round(t_f, 4), "ipls_ms": round(t_i, 4),
+                          "checkpoints": ck, "workspace_bytes_grad": pss.workspace_size(
+                              bb, "loglik_grad")}
+                log("64x1e4 %s: loglik+grad %.3f ms (loglik %.3f, Fisher route %.3f), IPLS %.3f "
+                    "ms, checkpoints %s" % (dt, t_g, t_l, t_f, t_i, ck))
                 # 50 L-BFGS steps from theta* + 0.5 (IPLS re-run at every
                 # evaluation, frozen-nominal gradient)
                 th_star = [float(v) for v in wb.model.theta]
@@ -733,7 +855,11 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        oracle.build(force=False)
+        try:  # a copy tuned for this host's CPU; the portable build otherwise
+            oracle.build(force=True, native=True)
+        except Exception as ex:  # noqa: BLE001
+            log("native oracle build failed (%s); portable build" % ex)
+            oracle.build(force=False)
         prm = oracle.ct_params()
         ns = min(n, 100000)
         log("cpu baseline: oracle on the first %d steps" % ns)
@@ -751,7 +877,8 @@ def main():
                "kind": "oracle",
                "sample": "first %d steps of the same sequence, %d repeat(s) of the whole step "
                          "(IPLS %d passes + loglik + score), FP64, sequential in k, one core"
-                         % (ns, reps, M)}
+                         % (ns, reps, M),
+               "build": oracle.build_flags(), **oracle.host_info()}
 
     peak = PEAK[args.dtype]
     line = {
@@ -774,10 +901,18 @@ def main():
             "loglik_plus_grad_ms"),
         "nan_loglik": nan,
         "stage_ms": {k: round(v, 4) for k, v in stage.items()},
-        "roofline": {"bound": "alu", "kernel": "%s level %d" % dom,
-                     "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 6), "traffic": traffic,
-                     "flops_per_launch": int(fl), "avg_launch_ms": round(dom_ms, 5)},
+        "roofline": {"bound": bound, "kernel": "%s level %d" % dom,
+                     "achieved": round(by / t_dom / 1e9, 1) if bound == "hbm"
+                     else round(fl / t_dom / 1e12, 4),
+                     "peak": HBM_GBPS if bound == "hbm" else peak,
+                     "unit": "GB/s" if bound == "hbm" else "TFLOP/s",
+                     "frac": round(max(hbm_frac, alu_frac), 6), "traffic": traffic,
+                     "hbm_frac": round(hbm_frac, 6), "alu_frac": round(alu_frac, 6),
+                     "counter_hbm_frac": None if traffic is None else round(
+                         traffic / t_dom / 1e9 / HBM_GBPS, 6),
+                     "alg_bytes_per_launch": int(by), "flops_per_launch": int(fl),
+                     "avg_launch_ms": round(dom_ms, 5)},
+        "pass": pass_info,
         "kernels": kernels,
         "copy_probe_GBps": round(copy_gbps, 1),
         "cpu_baseline": cpu,

@@ -388,6 +388,22 @@ int pss_sequential_smoother(const pss_problem *p, const pss_gamma *g, const void
                             int32_t n_iter, void *m_nom, void *N_nom, void *m_f, void *N_f,
                             void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* Per-sequence divergence record (the breakdown Section 6.3 counts: a
+   non-finite result).  Numerical breakdown is not a status code of the
+   entry points -- NaN and infinity propagate into that sequence's outputs
+   only, never into another sequence's (no tile spans two sequences).  This
+   call ORs marg_bit into status[b] (device int32 [B], caller-cleared) if
+   any component of sequence b's marginals (m [nx][T_x], N packed [T_x]:
+   filtering or smoothing, the caller says which through its bit, e.g.
+   PSS_STATUS_FILTER / PSS_STATUS_SMOOTHER) is NaN or infinite, and ll_bit
+   if ll[b] (device double [B]) is.  m, N nullable together; ll nullable;
+   not both. */
+#define PSS_STATUS_FILTER 1
+#define PSS_STATUS_SMOOTHER 2
+#define PSS_STATUS_LOGLIK 4
+int pss_nan_status(const pss_problem *p, const void *m, const void *N, int32_t marg_bit,
+                   const double *ll, int32_t ll_bit, int32_t *status, hipStream_t stream);
+
 /* ---- ragged batches of several model groups in one persistent launch ---- */
 
 /* One model group of a batched call: a ragged batch of sequences of one

@@ -27,18 +27,47 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_LIB_NATIVE = os.path.join(_HERE, "liboracle_native.so")
 
 _lib = None
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain C, OpenMP over sequences)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-fopenmp",
-               _SRC, "-o", _LIB + ".tmp", "-lm"]
+def build(force: bool = True, native: bool = False) -> str:
+    """Compile the oracle with gcc (plain C, OpenMP over sequences), -O3.
+    native=True builds a separate copy with -march=native for the machine it
+    runs on (the CPU-baseline timing) and makes it the library this module
+    calls."""
+    global _LIB, _lib
+    target = _LIB_NATIVE if native else _LIB
+    if force or not os.path.exists(target) or os.path.getmtime(target) < os.path.getmtime(_SRC):
+        cmd = ["gcc", "-O3", *(["-march=native"] if native else []), "-std=c11",
+               "-D_GNU_SOURCE", "-fPIC", "-shared", "-fopenmp", _SRC, "-o", target + ".tmp",
+               "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(_LIB + ".tmp", _LIB)
-    return _LIB
+        os.replace(target + ".tmp", target)
+    if native and _LIB != _LIB_NATIVE:
+        _LIB = _LIB_NATIVE
+        _lib = None
+    return target
+
+
+def build_flags() -> str:
+    """The compiler flags of the library this module calls."""
+    return "gcc -O3%s -fopenmp" % (" -march=native" if _LIB == _LIB_NATIVE else "")
+
+
+def host_info() -> dict:
+    """Core count and CPU model of the host (for the baseline record)."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
 
 
 def _load():

@@ -295,6 +295,46 @@ __global__ __launch_bounds__(256) void k_weighted_grad(const double *grad, const
     }
 }
 
+// per-sequence non-finite check: one thread per state (or per sequence for
+// the log-likelihood); a thread that sees a NaN or infinity ORs `bit` into
+// its sequence's status word (a vector atomic; none in the common case)
+template <typename T>
+__global__ __launch_bounds__(256) void k_nan_status(const int64_t *y_off, int B, int64_t T_x,
+                                                    const T *m, const T *N, int nx, int np,
+                                                    const double *ll, int32_t bit_marg,
+                                                    int32_t bit_ll, int32_t *status)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m && s < T_x) {
+        bool bad = false;
+        for (int c = 0; c < nx; ++c)
+            bad |= !isfinite(m[c * T_x + s]);
+        for (int c = 0; c < np; ++c)
+            bad |= !isfinite(N[c * T_x + s]);
+        if (bad)
+            atomicOr(status + find_seq(y_off, B, s, 1), bit_marg);
+    }
+    if (ll && s < B && !isfinite(ll[s]))
+        atomicOr(status + s, bit_ll);
+}
+
+int launch_nan_status(const Ctx &c, const void *m, const void *N, const double *ll, int bit_marg,
+                      int bit_ll, int32_t *status)
+{
+    const int nx = c.p->nx, np = nx * (nx + 1) / 2;
+    const int64_t work = m ? std::max<int64_t>(c.T_x, c.B) : c.B;
+    const dim3 grid((unsigned)((work + 255) / 256));
+    if (c.p->dtype == PSS_F64)
+        hipLaunchKernelGGL(k_nan_status<double>, grid, dim3(256), 0, c.s, c.p->y_off, c.B, c.T_x,
+                           static_cast<const double *>(m), static_cast<const double *>(N), nx, np,
+                           ll, bit_marg, bit_ll, status);
+    else
+        hipLaunchKernelGGL(k_nan_status<float>, grid, dim3(256), 0, c.s, c.p->y_off, c.B, c.T_x,
+                           static_cast<const float *>(m), static_cast<const float *>(N), nx, np,
+                           ll, bit_marg, bit_ll, status);
+    return hip_check(hipGetLastError(), "nan status launch");
+}
+
 int launch_weighted_grad(const Ctx &c, const double *grad, const double *w, double *theta_bar)
 {
     hipLaunchKernelGGL(k_weighted_grad, dim3(1), dim3(64), 0, c.s, grad, w, c.B, theta_bar);
@@ -945,6 +985,22 @@ int pss_loglik_vjp(const pss_problem *p, const pss_gamma *g, const void *m_nom,
             return I::loglik_vjp(c, g, m_nom, N_nom, y, ll_bar, ckpt, ll, g_bar, m0_bar, N0_bar,
                                  ws);
         });
+    }()));
+}
+
+int pss_nan_status(const pss_problem *p, const void *m, const void *N, int32_t marg_bit,
+                   const double *ll, int32_t ll_bit, int32_t *status, hipStream_t stream)
+{
+    PSS_GUARD(([&]() -> int {
+        int rc = validate(p);
+        if (rc)
+            return rc;
+        if (!status || ((m == nullptr) != (N == nullptr)) || (!m && !ll)) {
+            set_error("nan_status: null status, only one of m, N, or nothing to check");
+            return PSS_EINVAL;
+        }
+        const Ctx c = make_ctx(p, stream);
+        return launch_nan_status(c, m, N, ll, marg_bit, ll_bit, status);
     }()));
 }
 

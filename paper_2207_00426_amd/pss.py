@@ -40,7 +40,8 @@ EXPORTS = ["pss_workspace_size", "pss_slr_linearize", "pss_sqrt_filter_elements"
            "pss_version", "pss_batched_workspace_size", "pss_ipls_batched",
            "pss_autotune_workspace_size", "pss_autotune", "pss_kernel_timing",
            "pss_kernel_times", "pss_loglik_grad_ift", "pss_ckpt_size", "pss_loglik_vjp",
-           "pss_score_fisher", "pss_noalloc_max_bytes", "pss_ipls_iterate_noalloc"]
+           "pss_score_fisher", "pss_noalloc_max_bytes", "pss_ipls_iterate_noalloc",
+           "pss_nan_status"]
 
 
 class PssError(RuntimeError):
@@ -116,6 +117,8 @@ def lib():
         L.pss_loglik_vjp.argtypes = [P, ctypes.POINTER(GammaC), vp, vp, vp, vp, CK, vp,
                                      ctypes.POINTER(GammaC), vp, vp, vp, sz, vp]
         L.pss_score_fisher.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.pss_nan_status.argtypes = [P, vp, vp, i32, vp, i32, vp, vp]
+        L.pss_nan_status.restype = ctypes.c_int
         L.pss_noalloc_max_bytes.restype = sz
         L.pss_noalloc_max_bytes.argtypes = []
         L.pss_ipls_iterate_noalloc.argtypes = [P, ctypes.POINTER(GammaC), vp, i32, vp, vp, vp,
@@ -581,6 +584,21 @@ def loglik_vjp(batch, y, m_nom=None, N_nom=None, gamma=None, ll_bar=None, ws=Non
                                 _ptr(y), _ptr(ll_bar), _ckpt_ref(ckpt), _ptr(ll), _gamma_c(gbar),
                                 _ptr(m0b), _ptr(N0b), _ptr(ws), n, _stream()))
     return ll, gbar, m0b, N0b
+
+
+STATUS_FILTER, STATUS_SMOOTHER, STATUS_LOGLIK = 1, 2, 4
+
+
+def nan_status(batch, m=None, N=None, marg_bit=STATUS_SMOOTHER, ll=None,
+               ll_bit=STATUS_LOGLIK, status=None):
+    """Per-sequence int32 bitmask of non-finite results (ORed into status)."""
+    _require_gpu()
+    if status is None:
+        status = torch.zeros(batch.B, dtype=torch.int32, device=batch.device)
+    p = batch.struct()
+    _check(lib().pss_nan_status(ctypes.byref(p), _ptr(m), _ptr(N), int(marg_bit), _ptr(ll),
+                                int(ll_bit), _ptr(status), _stream()))
+    return status
 
 
 class LogLik(torch.autograd.Function):
