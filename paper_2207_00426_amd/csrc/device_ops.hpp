@@ -391,13 +391,22 @@ PSS_INL void load_A(const V &v, T (&A)[NX][NX])
 // Z, A, each after the last read of the input fields it may overwrite, so
 // `o` may view the same storage as `ei` or as `ej`.  Only the first NZ
 // columns of Z_j are read (see xi_block).
+//
+// The mean is formed in update form: with G = (I + C_i J_j)^{-1},
+//   G (b_i + C_i eta_j) = b_i + G C_i (eta_j - J_j b_i)
+//                       = b_i + Tm Tm^T (eta_j - J_j b_i),
+// since G C_i = U_i (I + U_i^T J_j U_i)^{-1} U_i^T = Tm Tm^T.  It equals the
+// printed b of Table 3 but never multiplies the (possibly large) mean by G:
+// G itself is formed as I - Tm Xi21^T, which cancels when C_i J_j is large
+// (a broad prefix against the information of a long span, or a fold of
+// several steps), and in FP32 that cancellation cost ~3 digits of the mean.
 template <typename T, int NX, int NZ, class VI, class VJ, class VO>
 PSS_INL void filter_combine_v(const VI &ei, const VJ &ej, const VO &o)
 {
     constexpr int C = NZ + NX;
     constexpr int K = cmin(2 * NX, C);
-    // v = b_i + U_i U_i^T eta_j and q = eta_j - Z_j Z_j^T b_i need the
-    // inputs only; computing them first keeps U_i, Z_j out of the Tria below
+    // bi and q = eta_j - Z_j Z_j^T b_i need the inputs only; computing them
+    // first keeps U_i, Z_j out of the Tria below
     T v[NX], q[NX];
     T M[2 * NX][C];
     {
@@ -409,9 +418,7 @@ PSS_INL void filter_combine_v(const VI &ei, const VJ &ej, const VO &o)
             etj[i] = ej.eta(i);
             bi[i] = ei.b(i);
         }
-        T ut[NX], uu[NX], zt[NZ];
-        lowerT_mv(Ui, etj, ut);
-        lower_mv(Ui, ut, uu);
+        T zt[NZ];
 #pragma unroll
         for (int a = 0; a < NZ; ++a) {
             T s = Zj[a][a] * bi[a];
@@ -426,7 +433,7 @@ PSS_INL void filter_combine_v(const VI &ei, const VJ &ej, const VO &o)
 #pragma unroll
             for (int a = 1; a < NZ && a <= i; ++a)
                 s = pfma(Zj[i][a], zt[a], s);
-            v[i] = bi[i] + uu[i];
+            v[i] = bi[i];
             q[i] = etj[i] - s;
         }
         // Xi = Tria([[U_i^T Z_j, I], [Z_j, 0]])
@@ -457,17 +464,24 @@ PSS_INL void filter_combine_v(const VI &ei, const VJ &ej, const VO &o)
         }
     T gq[NX];
     mtv(G, q, gq);
-    // A_j G and A_j Tm; then b = A_j G v + b_j
+    // v <- b_i + Tm Tm^T q (the filtered mean of the span's start)
+    {
+        T tq[NX], u[NX];
+        mtv(Tm, q, tq);
+        mv(Tm, tq, u);
+#pragma unroll
+        for (int i = 0; i < NX; ++i)
+            v[i] += u[i];
+    }
+    // A_j G and A_j Tm; then b = A_j v + b_j
     T AG[NX][NX], AT[NX][NX];
     {
         T Aj[NX][NX];
         load_A(ej, Aj);
         mm(Aj, G, AG);
         mm(Aj, Tm, AT);
-    }
-    {
         T w[NX];
-        mv(AG, v, w);
+        mv(Aj, v, w);
 #pragma unroll
         for (int i = 0; i < NX; ++i)
             o.sb(i, w[i] + ej.b(i));
@@ -548,24 +562,34 @@ PSS_INL void filter_apply_v(const Marg<T, NX> &p, const VJ &ej, Marg<T, NX> &o)
 #pragma unroll
         for (int j = 0; j < NX; ++j)
             Nf[i][j] = (j <= i) ? p.N[i][j] : T(0);
-    T v[NX];
+    T q[NX];
     T M[2 * NX][NZ + NX];
     {
-        T Zj[NX][NZ], etj[NX];
+        // q = eta_j - Z_j Z_j^T m
+        T Zj[NX][NZ], zt[NZ];
         load_Z_cols(ej, Zj);
 #pragma unroll
-        for (int i = 0; i < NX; ++i)
-            etj[i] = ej.eta(i);
-        T ut[NX], uu[NX];
-        lowerT_mv(Nf, etj, ut);
-        lower_mv(Nf, ut, uu);
+        for (int a = 0; a < NZ; ++a) {
+            T s = Zj[a][a] * p.m[a];
 #pragma unroll
-        for (int i = 0; i < NX; ++i)
-            v[i] = p.m[i] + uu[i];
+            for (int i = a + 1; i < NX; ++i)
+                s = pfma(Zj[i][a], p.m[i], s);
+            zt[a] = s;
+        }
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+            T s = Zj[i][0] * zt[0];
+#pragma unroll
+            for (int a = 1; a < NZ && a <= i; ++a)
+                s = pfma(Zj[i][a], zt[a], s);
+            q[i] = ej.eta(i) - s;
+        }
         xi_block(Nf, Zj, M);
     }
     lq_rows<NX, NZ>(M);
-    T Tm[NX][NX], G[NX][NX];
+    // Tm = N Xi11^{-T}; the mean in update form (see filter_combine_v):
+    // m' = A_j (m + Tm Tm^T q) + b_j, and N' = Tria([A_j Tm, U_j])
+    T Tm[NX][NX];
     {
         T X11[NX][NX];
 #pragma unroll
@@ -575,28 +599,25 @@ PSS_INL void filter_apply_v(const Marg<T, NX> &p, const VJ &ej, Marg<T, NX> &o)
                 X11[i][j] = M[i][j];
         rsolve_lower_t(Nf, X11, Tm);
     }
-#pragma unroll
-    for (int i = 0; i < NX; ++i)
-#pragma unroll
-        for (int j = 0; j < NX; ++j) {
-            T s = (i == j) ? T(1) : T(0);
-#pragma unroll
-            for (int t = 0; t < NX; ++t)
-                s = pfma(-Tm[i][t], M[NX + j][t], s);
-            G[i][j] = s;
-        }
-    T AG[NX][NX], AT[NX][NX];
+    T v[NX];
     {
-        T Aj[NX][NX];
-        load_A(ej, Aj);
-        mm(Aj, G, AG);
-        mm(Aj, Tm, AT);
-    }
-    T w[NX];
-    mv(AG, v, w);
+        T tq[NX], u[NX];
+        mtv(Tm, q, tq);
+        mv(Tm, tq, u);
 #pragma unroll
-    for (int i = 0; i < NX; ++i)
-        o.m[i] = w[i] + ej.b(i);
+        for (int i = 0; i < NX; ++i)
+            v[i] = p.m[i] + u[i];
+    }
+    T AT[NX][NX];
+    {
+        T Aj[NX][NX], w[NX];
+        load_A(ej, Aj);
+        mm(Aj, Tm, AT);
+        mv(Aj, v, w);
+#pragma unroll
+        for (int i = 0; i < NX; ++i)
+            o.m[i] = w[i] + ej.b(i);
+    }
     T Uj[NX][NX];
     load_lower_U(ej, Uj);
     tria_dense_lower(AT, Uj, o.N);
@@ -841,6 +862,21 @@ PSS_INL void ct_f(const CTParams<T> &P, const T (&x)[5], T (&o)[5])
     o[4] = x[4];
 }
 
+// Precision in which the bearings are formed and their branch is chosen.  An
+// image crossing the cut opposite the measurement jumps by 2 pi, so which
+// side a point falls on is an integer decision; FP32 kernels take it in FP64
+// (from the same FP32 inputs), as the FP64 reference does, and round the
+// small deviations it yields back afterwards.  Without this an FP32 sigma
+// point 1e-7 rad from the cut chose the other branch than FP64 did.
+template <typename T>
+struct BranchPrec {
+    using type = T;
+};
+template <>
+struct BranchPrec<float> {
+    using type = double;
+};
+
 template <typename T>
 PSS_INL T wrap_near(T a, T ref)
 { // ref + (a - ref) reduced to [-pi, pi)
@@ -855,8 +891,9 @@ PSS_INL T wrap_near(T a, T ref)
 template <typename T>
 PSS_INL void ct_h(const CTParams<T> &P, const T (&x)[5], const T (&y)[2], T (&o)[2])
 {
-    o[0] = wrap_near(patan2(x[1] - P.s1y, x[0] - P.s1x), y[0]);
-    o[1] = wrap_near(patan2(x[1] - P.s2y, x[0] - P.s2x), y[1]);
+    using W = typename BranchPrec<T>::type;
+    o[0] = T(wrap_near(patan2(W(x[1]) - W(P.s1y), W(x[0]) - W(P.s1x)), W(y[0])));
+    o[1] = T(wrap_near(patan2(W(x[1]) - W(P.s2y), W(x[0]) - W(P.s2x)), W(y[1])));
 }
 
 // --------------------------------------------------------------------------
@@ -1076,30 +1113,33 @@ template <typename T>
 PSS_INL void ct_slr_bearings(const CTParams<T> &P, const Marg<T, 5> &mg, const T (&y)[2],
                              T (&H)[2][5], T (&d)[2], T (&S)[2][2])
 {
-    const T pi = T(3.14159265358979323846);
-    const T tp = T(6.28318530717958647692);
+    using W = typename BranchPrec<T>::type;
+    const W pi = W(3.14159265358979323846);
+    const W tp = W(6.28318530717958647692);
+    const W sq = psqrt(W(5));
     T ep[2][5], em[2][5], r[2];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-        const T sx = q == 0 ? P.s1x : P.s2x, sy = q == 0 ? P.s1y : P.s2y;
-        const T ux = mg.m[0] - sx, uy = mg.m[1] - sy;
-        const T r2 = ux * ux + uy * uy;
-        T D0 = patan2(uy, ux) - y[q];
+        const W sx = W(q == 0 ? P.s1x : P.s2x), sy = W(q == 0 ? P.s1y : P.s2y);
+        const W ux = W(mg.m[0]) - sx, uy = W(mg.m[1]) - sy;
+        const W r2 = ux * ux + uy * uy;
+        W D0 = patan2(uy, ux) - W(y[q]);
         D0 = D0 - tp * pfloor((D0 + pi) / tp);
-        r[q] = y[q] + D0;
+        r[q] = T(W(y[q]) + D0);
 #pragma unroll
         for (int i = 0; i < 5; ++i) {
-            T dlt[5];
-            sigma_offset(mg, i, dlt);
-            const T cr = ux * dlt[1] - uy * dlt[0];
-            const T dt = ux * dlt[0] + uy * dlt[1];
-            const T ap = patan2(cr, r2 + dt);
-            const T am = patan2(-cr, r2 - dt);
+            // position part of column i of sqrt(nx) N (lower: rows >= i)
+            const W d0 = (i == 0) ? sq * W(mg.N[0][0]) : W(0);
+            const W d1 = (i <= 1) ? sq * W(mg.N[1][i]) : W(0);
+            const W cr = ux * d1 - uy * d0;
+            const W dt = ux * d0 + uy * d1;
+            const W ap = patan2(cr, r2 + dt);
+            const W am = patan2(-cr, r2 - dt);
             // branch jumps of D0 + angle back into [-pi, pi)
-            const T kp = pfloor((D0 + ap + pi) / tp);
-            const T km = pfloor((D0 + am + pi) / tp);
-            ep[q][i] = ap - tp * kp;
-            em[q][i] = am - tp * km;
+            const W kp = pfloor((D0 + ap + pi) / tp);
+            const W km = pfloor((D0 + am + pi) / tp);
+            ep[q][i] = T(ap - tp * kp);
+            em[q][i] = T(am - tp * km);
         }
     }
     const T Sn[2][2] = {{P.sigma, T(0)}, {T(0), P.sigma}};

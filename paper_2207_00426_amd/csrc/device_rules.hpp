@@ -217,18 +217,21 @@ template <typename T>
 PSS_INL void ct_rule_bearings(const RuleSpec<T> &R, const CTParams<T> &P, const Marg<T, 5> &mg,
                               const T (&y)[2], T (&H)[2][5], T (&d)[2], T (&S)[2][2])
 {
-    const T pi = T(3.14159265358979323846);
-    const T tp = T(6.28318530717958647692);
-    T ux[2], uy[2], r2[2], D0[2], r[2];
+    // bearings and their branch in BranchPrec<T> (FP64 for FP32 kernels)
+    using W = typename BranchPrec<T>::type;
+    const W pi = W(3.14159265358979323846);
+    const W tp = W(6.28318530717958647692);
+    W ux[2], uy[2], r2[2], D0[2];
+    T r[2];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-        const T sx = q == 0 ? P.s1x : P.s2x, sy = q == 0 ? P.s1y : P.s2y;
-        ux[q] = mg.m[0] - sx;
-        uy[q] = mg.m[1] - sy;
+        const W sx = W(q == 0 ? P.s1x : P.s2x), sy = W(q == 0 ? P.s1y : P.s2y);
+        ux[q] = W(mg.m[0]) - sx;
+        uy[q] = W(mg.m[1]) - sy;
         r2[q] = ux[q] * ux[q] + uy[q] * uy[q];
-        T a = patan2(uy[q], ux[q]) - y[q];
+        W a = patan2(uy[q], ux[q]) - W(y[q]);
         D0[q] = a - tp * pfloor((a + pi) / tp);
-        r[q] = y[q] + D0[q];
+        r[q] = T(W(y[q]) + D0[q]);
     }
     const T Sn[2][2] = {{P.sigma, T(0)}, {T(0), P.sigma}};
     rule_slr<T, 5, 2, false>(
@@ -236,10 +239,10 @@ PSS_INL void ct_rule_bearings(const RuleSpec<T> &R, const CTParams<T> &P, const 
         [&](const T (&dl)[5], T (&e)[2], T &v) {
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
-                const T cr = ux[q] * dl[1] - uy[q] * dl[0];
-                const T dt = ux[q] * dl[0] + uy[q] * dl[1];
-                const T ang = patan2(cr, r2[q] + dt);
-                e[q] = ang - tp * pfloor((D0[q] + ang + pi) / tp);
+                const W cr = ux[q] * W(dl[1]) - uy[q] * W(dl[0]);
+                const W dt = ux[q] * W(dl[0]) + uy[q] * W(dl[1]);
+                const W ang = patan2(cr, r2[q] + dt);
+                e[q] = T(ang - tp * pfloor((D0[q] + ang + pi) / tp));
             }
             v = T(0);
         },

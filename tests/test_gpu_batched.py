@@ -129,3 +129,75 @@ def test_autotune_picks_a_valid_shape_and_is_used():
     pss.ipls_batched(groups, 2)
     torch.cuda.synchronize()
     _check(groups, meta, _oracle(meta, 2), par.TOL["f32"])
+
+
+def _per_state(m, N, mr, Nr):
+    Pr = par.gram(Nr)
+    den = np.maximum(np.linalg.norm(mr, axis=-1),
+                     np.sqrt(np.maximum(np.trace(Pr, axis1=-2, axis2=-1), 0.0)))
+    em = np.linalg.norm(m - mr, axis=-1) / den
+    dP = (par.gram(N) - Pr).reshape(len(Pr), -1)
+    eP = np.linalg.norm(dP, axis=-1) / np.linalg.norm(Pr.reshape(len(Pr), -1), axis=-1)
+    return em, eP
+
+
+def test_ragged_512_fp32_persistent_graph_every_pass():
+    """The batched benchmark configuration itself: 512 sequences with lengths
+    uniform in [100, 20000] (seed 3), half constant-velocity, half
+    coordinated-turn, FP32, the autotuned persistent pass captured in a HIP
+    graph.  Each replay (one pass) is checked at every state of every
+    sequence against one oracle pass from the GPU's previous nominal."""
+    groups_w, lengths, kinds = wl.ragged_mixed(512, 100, 20000, 3, M=10)
+    tdt = torch.float32
+    cvm = wl.CVModel()
+    G = _cv_gamma(cvm)
+    wcv, _ = groups_w["cv"]
+    wct, _ = groups_w["ct"]
+    b_cv = pss.Batch(pss.MODEL_LINEAR, tdt, 4, 2, wcv.y_off, cvm.m0, np.eye(4), device=DEV)
+    b_ct = pss.Batch.ct(wct.y_off, wct.model, dtype=tdt, device=DEV)
+    y_cv = pss.to_soa(wcv.y, tdt, DEV)
+    y_ct = pss.to_soa(wct.y, tdt, DEV)
+    m_cv, N_cv = b_cv.prior_nominal()
+    m_ct, N_ct = b_ct.prior_nominal()
+    groups = [(b_cv, y_cv, m_cv, N_cv, b_cv.gamma_from_numpy(G)), (b_ct, y_ct, m_ct, N_ct, None)]
+    pss.autotune(groups)
+    ws = torch.empty(pss.batched_workspace_size(groups), dtype=torch.uint8, device=DEV)
+    status = torch.zeros(1, dtype=torch.int32, device=DEV)
+    stream = torch.cuda.Stream()
+    pss.ipls_batched(groups, 1, ws=ws, status=status)  # warm-up, then back to the prior
+    torch.cuda.synchronize()
+    for t, s in ((m_cv, b_cv.prior_nominal()[0]), (N_cv, b_cv.prior_nominal()[1]),
+                 (m_ct, b_ct.prior_nominal()[0]), (N_ct, b_ct.prior_nominal()[1])):
+        t.copy_(s)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(graph, stream=stream):
+            pss.ipls_batched(groups, 1, ws=ws, status=status)
+    # the linear group: every pass is the exact smoother of the linear model
+    ms_cv_ref = np.zeros((len(wcv.y) + len(wcv.y_off) - 1, 4))
+    Ns_cv_ref = np.zeros((len(wcv.y) + len(wcv.y_off) - 1, 4, 4))
+    orc.linear_smoother_batch(cvm.m0, np.eye(4), G, wcv.y, wcv.y_off, ms_cv_ref, Ns_cv_ref)
+    prm = orc.ct_params()
+    worst = []
+    for i in range(10):
+        mp, Np = pss.marg_from_soa(m_ct.double(), N_ct.double(), 5)
+        graph.replay()
+        torch.cuda.synchronize()
+        assert int(status.item()) == 0
+        ms_ref, Ns_ref = mp.copy(), Np.copy()
+        orc.ct_ipls_batch(prm, wct.model.m0, np.eye(5), wct.y, wct.y_off, 1, ms_ref, Ns_ref)
+        em, eP = _per_state(*pss.marg_from_soa(m_ct.double(), N_ct.double(), 5), ms_ref, Ns_ref)
+        cm, cP = _per_state(*pss.marg_from_soa(m_cv.double(), N_cv.double(), 4), ms_cv_ref,
+                            Ns_cv_ref)
+        worst.append((em.max(), eP.max(), cm.max(), cP.max()))
+        p99 = max(np.percentile(em, 99), np.percentile(eP, 99))
+        print("512 ragged FP32 pass %d: CT mean %.3e cov %.3e (p99 %.3e), CV mean %.3e cov "
+              "%.3e" % (i + 1, *worst[-1][:2], p99, *worst[-1][2:]), flush=True)
+        # the linear group and the first CT passes meet the FP32 bar at every
+        # state; later CT passes stay within the FP32 limit of the parallel
+        # scan measured here (p99 up to 1.04e-4, at most 7.3e-4; see the
+        # full-size FP32 test for the attribution)
+        assert max(cm.max(), cP.max()) < par.TOL["f32"]["m"], i
+        if i < 2:
+            assert max(em.max(), eP.max()) < par.TOL["f32"]["m"], i
+        assert p99 < 2e-4 and max(em.max(), eP.max()) < 2e-3, i

@@ -1,19 +1,29 @@
 """GPU parity at the benchmark's full size (one sequence of 10^6 steps) in the
 launch configuration bench.py times (the library's default shapes).
 
-* coordinated-turn bearings model: one IPLS pass from the prior, every
-  smoothed state of the million against the oracle's pass, then the
-  log-likelihood and the frozen-nominal gradient at that nominal;
+* coordinated-turn bearings model, FP64, the benchmark's 10 IPLS passes:
+  every pass, started from the GPU's own previous nominal, against one
+  oracle pass from that nominal at every one of the 10^6 + 1 states (the
+  FP64 bar); the log-likelihood and the adjoint gradient at the final
+  nominal against the oracle's; and the whole chain of passes from the
+  prior against the oracle's own chain, within the chain's sensitivity to
+  round-off (the oracle's chain, perturbed by one part in 10^15 after its
+  first pass, moves by about 1e-7 after ten: the iteration amplifies
+  round-off where bearings-only triangulation is ill-conditioned);
 * linear constant-velocity model: filter and smoother at every state
   against the oracle's sequential square-root recursions;
-* FP32 at full size: one pass within the FP32 bar of the FP64 run at every
-  state (each later pass linearises at the previous FP32 result, so the
-  difference compounds: 1.0e-4 after two); after the 10 passes of the
-  benchmark finite, with the bulk
-  close (median) and the deviation percentiles reported: the fixed-count
-  iteration amplifies FP32 round-off where bearings-only triangulation is
-  ill-conditioned, so a few percent of the states separate by more than
-  1e-2 (measured: 2.6%, steps 8e3 to 2.8e5).
+* FP32 at full size: every pass from the GPU's own FP32 nominal against one
+  oracle pass from it.  Measured limit, not the FP32 bar: passes 1 and 2
+  meet 1e-4 at every state; from pass 3 on (a nominal concentrated on the
+  track) the parallel FP32 scan's errors grow to 2e-4 .. 1.1e-3 at p99 (mean
+  and covariance, largest at pass 9) and 1.2e-3 at most, a few times the
+  error of the sequential
+  FP32 square-root recursion on the same pass (~1e-4, itself above the bar
+  at some states).  Attribution (one pass from a fixed FP64 nominal): not
+  the linearisation (FP64 Gamma cast to FP32 gives the same), the
+  information-form elements' eta ~ J m at |m| ~ 100 (deviation coordinates
+  relative to the nominal cut the mean error 5x) and the FP32 composition
+  of the covariance factors (unchanged by coordinates).
 """
 import numpy as np
 import pytest
@@ -34,24 +44,59 @@ def ct_long():
     return wl.ct_long(N, 2, M=10)
 
 
-def test_ct_one_pass_and_gradient_full_size(ct_long):
+def test_ct_ten_passes_fp64_every_pass_and_gradient(ct_long):
     w = ct_long
+    prm = orc.ct_params()
     b = pss.Batch.ct(w.y_off, w.model, dtype=torch.float64, device=DEV)
     yd = pss.to_soa(w.y, torch.float64, DEV)
-    m, Nn = pss.ipls_iterate(b, yd, 1)
+    m, Nn = b.prior_nominal()
+    for i in range(w.M):
+        mp, Np = pss.marg_from_soa(m, Nn, 5)
+        pss.ipls_iterate(b, yd, 1, m, Nn)
+        torch.cuda.synchronize()
+        r = orc.ct_ipls(prm, w.model.m0, np.eye(5), w.y, 1, ms_init=mp, Ns_init=Np)
+        em, eP = par.marg_errs(*pss.marg_from_soa(m, Nn, 5), r["ms"], r["Ns"])
+        print("full-size FP64 pass %d: mean err %.3e, cov err %.3e" % (i + 1, em, eP), flush=True)
+        assert em < par.TOL["f64"]["m"] and eP < par.TOL["f64"]["P"], i
     ll, grad, _ = pss.loglik_grad(b, m, Nn, yd)
     torch.cuda.synchronize()
-    ma, Na = pss.marg_from_soa(m, Nn, 5)
-    prm = orc.ct_params()
-    r = orc.ct_ipls(prm, w.model.m0, np.eye(5), w.y, 1)
-    em, eP = par.marg_errs(ma, Na, r["ms"], r["Ns"])
-    print("full-size CT pass: mean err %.3e, cov err %.3e" % (em, eP))
-    assert em < par.TOL["f64"]["m"] and eP < par.TOL["f64"]["P"]
-    ll_ref, g_ref = orc.ct_score(prm, w.model.m0, np.eye(5), w.y, r["ms"], r["Ns"])
+    ll_ref, g_ref = orc.ct_score(prm, w.model.m0, np.eye(5), w.y, *pss.marg_from_soa(m, Nn, 5))
     el = par.ll_err(float(ll.item()), ll_ref)
     eg = par.grad_err(grad[:, 0].cpu().numpy(), g_ref)
     print("full-size CT loglik err %.3e, gradient err %.3e" % (el, eg))
     assert el < par.TOL["f64"]["ll"] and eg < par.TOL["f64"]["g"]
+
+
+def test_ct_ten_pass_chain_within_the_iterations_round_off_sensitivity(ct_long):
+    w = ct_long
+    prm = orc.ct_params()
+    b = pss.Batch.ct(w.y_off, w.model, dtype=torch.float64, device=DEV)
+    yd = pss.to_soa(w.y, torch.float64, DEV)
+    hist = []
+    m, Nn = b.prior_nominal()
+    for i in range(w.M):
+        pss.ipls_iterate(b, yd, 1, m, Nn)
+        torch.cuda.synchronize()
+        hist.append(pss.marg_from_soa(m, Nn, 5))
+    A = orc.ct_ipls(prm, w.model.m0, np.eye(5), w.y, w.M, history=True)
+    # the oracle's own chain restarted from the GPU's first pass (which equals
+    # the oracle's first pass up to round-off): how far the iteration carries
+    # one pass's rounding differences
+    Bp = orc.ct_ipls(prm, w.model.m0, np.eye(5), w.y, w.M - 1, ms_init=hist[0][0],
+                     Ns_init=hist[0][1], history=True)
+    for i in range(w.M):
+        em, eP = par.marg_errs(*hist[i], A["hist_ms"][i], A["hist_Ns"][i])
+        if i == 0:
+            sm = sP = 0.0
+        else:
+            sm, sP = par.marg_errs(Bp["hist_ms"][i - 1], Bp["hist_Ns"][i - 1], A["hist_ms"][i],
+                                   A["hist_Ns"][i])
+        print("chain pass %d: GPU vs oracle (%.3e, %.3e); oracle from the GPU's first pass vs "
+              "oracle (%.3e, %.3e)" % (i + 1, em, eP, sm, sP), flush=True)
+        # within the FP64 bar, or within a small factor of how far the
+        # oracle's own chain carries the first pass's round-off
+        assert em < max(par.TOL["f64"]["m"], 10 * sm), i
+        assert eP < max(par.TOL["f64"]["P"], 10 * sP), i
 
 
 def test_linear_filter_smoother_full_size():
@@ -75,39 +120,55 @@ def test_linear_filter_smoother_full_size():
         assert em < par.TOL["f64"]["m"] and eP < par.TOL["f64"]["P"], what
 
 
-def _per_state_mean_err(m, N, mr, Nr):
+def _per_state(m, N, mr, Nr):
     Pr = par.gram(Nr)
     den = np.maximum(np.linalg.norm(mr, axis=-1),
                      np.sqrt(np.maximum(np.trace(Pr, axis1=-2, axis2=-1), 0.0)))
-    return np.linalg.norm(m - mr, axis=-1) / den
+    em = np.linalg.norm(m - mr, axis=-1) / den
+    dP = (par.gram(N) - Pr).reshape(len(Pr), -1)
+    eP = np.linalg.norm(dP, axis=-1) / np.linalg.norm(Pr.reshape(len(Pr), -1), axis=-1)
+    return em, eP
 
 
-def test_fp32_full_size_per_pass_parity_and_ten_passes(ct_long):
+def test_fp32_full_size_every_pass(ct_long):
     w = ct_long
-    res = {}
-    for passes in (1, 10):
-        out = {}
-        for dt in (torch.float64, torch.float32):
-            b = pss.Batch.ct(w.y_off, w.model, dtype=dt, device=DEV)
-            yd = pss.to_soa(w.y, dt, DEV)
-            m, Nn = pss.ipls_iterate(b, yd, passes)
-            ll, _, _ = pss.loglik_grad(b, m, Nn, yd)
+    prm = orc.ct_params()
+    b = pss.Batch.ct(w.y_off, w.model, dtype=torch.float32, device=DEV)
+    yd = pss.to_soa(w.y, torch.float32, DEV)
+    m, Nn = b.prior_nominal()
+    for i in range(w.M):
+        mp, Np = pss.marg_from_soa(m.double(), Nn.double(), 5)
+        m_in, N_in = m.clone(), Nn.clone()
+        pss.ipls_iterate(b, yd, 1, m, Nn)
+        torch.cuda.synchronize()
+        assert torch.isfinite(m).all() and torch.isfinite(Nn).all()
+        r = orc.ct_ipls(prm, w.model.m0, np.eye(5), w.y, 1, ms_init=mp, Ns_init=Np)
+        em, eP = _per_state(*pss.marg_from_soa(m.double(), Nn.double(), 5), r["ms"], r["Ns"])
+        line = ("full-size FP32 pass %d: mean err max %.3e p99 %.3e, cov err max %.3e p99 "
+                "%.3e, states above 1e-4: %d" % (i + 1, em.max(), np.percentile(em, 99), eP.max(),
+                                                  np.percentile(eP, 99),
+                                                  int((np.maximum(em, eP) > 1e-4).sum())))
+        if i == 2:
+            # the sequential FP32 recursion on the same pass: the FP32 limit
+            ms_, Ns_ = pss.sequential_smoother(b, yd, 1, m_in, N_in)
             torch.cuda.synchronize()
-            out[dt] = (pss.marg_from_soa(m.double(), Nn.double(), 5), float(ll.item()))
-        (m32, N32), ll32 = out[torch.float32]
-        (m64, N64), ll64 = out[torch.float64]
-        assert np.isfinite(m32).all() and np.isfinite(N32).all() and np.isfinite(ll32)
-        e = _per_state_mean_err(m32, N32, m64, N64)
-        res[passes] = (par.marg_errs(m32, N32, m64, N64), np.percentile(e, [50, 99, 100]),
-                       par.ll_err(ll32, ll64))
-        print("full-size FP32 vs FP64, %d passes: (mean, cov) %s, mean-err percentiles "
-              "50/99/100 %s, loglik %.3e" % (passes, res[passes][0], res[passes][1],
-                                           res[passes][2]))
-    # one pass (the same linearisation point for both): within the FP32 bar
-    # at every one of the 10^6 states
-    (em, eP), _, _ = res[1]
-    assert em < par.TOL["f32"]["m"] and eP < par.TOL["f32"]["P"]
-    # ten passes: the fixed-count iteration amplifies FP32 differences in the
-    # ill-conditioned stretches of the trajectory; the bulk stays close
-    (_, pct, el) = res[10]
-    assert pct[0] < 1e-3 and el < 0.1
+            sm, sP = _per_state(*pss.marg_from_soa(ms_.double(), Ns_.double(), 5), r["ms"],
+                                r["Ns"])
+            line += "; sequential FP32: mean max %.3e, cov max %.3e" % (sm.max(), sP.max())
+            assert em.max() < 10 * sm.max() and eP.max() < 10 * max(sP.max(), 1e-4)
+        print(line, flush=True)
+        # the measured FP32 limit of the parallel scan on this sequence: the
+        # bar holds on the first passes; from the third pass on the errors
+        # grow to ~6e-4 (p99) -- see the module docstring
+        if i < 2:
+            assert em.max() < par.TOL["f32"]["m"] and eP.max() < par.TOL["f32"]["P"]
+        assert np.percentile(em, 99) < 2e-3 and np.percentile(eP, 99) < 2e-3
+        assert em.max() < 3e-3 and eP.max() < 3e-3
+    ll, grad, _ = pss.loglik_grad(b, m, Nn, yd)
+    torch.cuda.synchronize()
+    ll_ref, g_ref = orc.ct_score(prm, w.model.m0, np.eye(5), w.y,
+                                 *pss.marg_from_soa(m.double(), Nn.double(), 5))
+    el = par.ll_err(float(ll.item()), ll_ref)
+    eg = par.grad_err(grad[:, 0].cpu().numpy(), g_ref)
+    print("full-size FP32 loglik err %.3e, adjoint gradient err %.3e" % (el, eg))
+    assert el < par.TOL["f32"]["ll"] and eg < par.TOL["f32"]["g"]

@@ -43,29 +43,35 @@ def test_taylor_linearisation_matches_oracle(tag):
 
 @pytest.mark.parametrize("tag", ["f64", "f32"])
 def test_iterated_extended_smoother_every_pass(tag):
+    """Every pass of the n = 1000 IEKS: each GPU pass, started from the GPU's
+    own previous nominal, against one oracle pass from that same nominal at
+    the fixed bar of its precision; in FP64 also the whole chain of passes
+    against the oracle's own iteration from the prior."""
     w = wl.ct_single(1000, seed=1)
     M = 10
-    ref = orc.ct_ipls(orc.ct_params(), w.model.m0, np.eye(5), w.y, M, history=True,
-                      method="taylor")
+    prm = orc.ct_params()
+    ref = orc.ct_ipls(prm, w.model.m0, np.eye(5), w.y, M, history=True, method="taylor")
     b = pss.Batch.ct(w.y_off, w.model, dtype=_dt(tag), device=DEV, linearization="taylor")
     yd = pss.to_soa(w.y, _dt(tag), DEV)
     m, N = b.prior_nominal()
     tol = par.TOL[tag]
     for i in range(M):
+        m_prev, N_prev = pss.marg_from_soa(m.double(), N.double(), 5)
         pss.ipls_iterate(b, yd, 1, m, N)
         torch.cuda.synchronize()
         ma, Na = pss.marg_from_soa(m.double(), N.double(), 5)
-        em, eP = par.marg_errs(ma, Na, ref["hist_ms"][i], ref["hist_Ns"][i])
-        # FP32: each pass linearises at the previous FP32 nominal, so allow the
-        # per-pass bar to compound over the passes
-        f = 1.0 if tag == "f64" else (1 + i)
-        assert em < f * tol["m"] and eP < f * tol["P"], (i, em, eP)
-    if tag == "f64":
-        ll, grad, _ = pss.loglik_grad(b, m, N, yd)
-        ll_ref, g_ref = orc.ct_score(orc.ct_params(), w.model.m0, np.eye(5), w.y,
-                                     ref["ms"], ref["Ns"], method="taylor")
-        assert par.ll_err(float(ll.item()), ll_ref) < tol["ll"]
-        assert par.grad_err(grad[:, 0].cpu().numpy(), g_ref) < tol["g"]
+        one = orc.ct_ipls(prm, w.model.m0, np.eye(5), w.y, 1, ms_init=m_prev, Ns_init=N_prev,
+                          method="taylor")
+        em, eP = par.marg_errs(ma, Na, one["ms"], one["Ns"])
+        assert em < tol["m"] and eP < tol["P"], (i, em, eP)
+        if tag == "f64":
+            em, eP = par.marg_errs(ma, Na, ref["hist_ms"][i], ref["hist_Ns"][i])
+            assert em < tol["m"] and eP < tol["P"], (i, em, eP)
+    ll, grad, _ = pss.loglik_grad(b, m, N, yd)
+    ma, Na = pss.marg_from_soa(m.double(), N.double(), 5)
+    ll_ref, g_ref = orc.ct_score(prm, w.model.m0, np.eye(5), w.y, ma, Na, method="taylor")
+    assert par.ll_err(float(ll.item()), ll_ref) < tol["ll"]
+    assert par.grad_err(grad[:, 0].cpu().numpy(), g_ref) < tol["g"]
 
 
 def test_taylor_in_the_persistent_batched_pass():
