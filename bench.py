@@ -72,7 +72,7 @@ from paper_2207_00426_amd import workloads as wl  # noqa: E402
 # T_k; adjoint_cotangents: the Gram cotangents and the theta contraction.
 FLOPS = dict(filter_combine=3371, filter_combine_leaf=2516, filter_apply=1912,
              filter_apply_leaf=1396, smoother_combine=732, smoother_apply=503,
-             filter_element=1248, smoother_element=1510, slr_transition=942, slr_bearings=437,
+             filter_element=1248, smoother_element=1510, slr_transition=1971, slr_bearings=437,
              adjoint_element=1469, adjoint_combine=740, adjoint_apply=515,
              adjoint_cotangents=966)
 PEAK = {"f64": 78.6, "f32": 78.6}  # TFLOP/s vector ALU (FP32 without packed instructions)

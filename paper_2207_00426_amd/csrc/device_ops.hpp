@@ -1064,40 +1064,141 @@ PSS_INL void sigma_offset(const Marg<T, NX> &mg, int i, T (&dlt)[NX])
 // linear in the map and exact for the identity, so F = I + G_phi,
 // c = off_phi and the residual is phi's alone; phi only sees the velocity
 // and turn-rate coordinates of the sigma points.
+//
+// The images go to the SLR as phi(m) plus deviations formed directly, never
+// as two absolute images subtracted: once the nominal is tight, a sigma
+// point's image differs from phi(m) by a small fraction of |v| dt, and the
+// subtraction lost that many digits (FP32 relative errors of F up to 1e-4).
+
+// sinc(x + d) - sinc(x) without cancellation.  sinc is even, so the
+// difference is taken between X = |x| and X1 = |x + d| with step
+// D = X1 - X (a step across zero becomes a small one).  While both are
+// below 1/2 the power series is differenced term by term, each term
+// carrying the exact factor X1^2 - X^2 = D (X1 + X) (FP32 keeps 4 terms,
+// FP64 7: the rest is below a quarter ulp of the leading term); otherwise a
+// step below X/2 uses the identity
+//   X sin(X + D) - (X + D) sin X
+//     = -2 X sin X sin^2(D/2) + X cos X (sin D - D) + D (X cos X - sin X)
+// over X (X + D), which leaves only products of small factors (sin D - D
+// from its own series), and a larger step differences directly.
 template <typename T>
-PSS_INL void ct_phi(const CTParams<T> &P, T vx, T vy, T w, T (&o)[5])
+struct SincTerms {
+    static constexpr int n = Eps<T>::v > 1e-10 ? 4 : 7;
+};
+// (-1)^k / (2k + 1)!, k = 1, 2, ...
+__host__ __device__ constexpr double sinc_coef(int k)
 {
-    const T a = w * P.dt;
-    const T h = T(0.5) * a;
-    const T sh = sinc_(h);
-    const T s1 = P.dt * sinc_(a);
-    const T s2 = P.dt * h * sh * sh;
-    o[0] = s1 * vx - s2 * vy;
-    o[1] = s2 * vx + s1 * vy;
-    o[2] = -w * o[1];
-    o[3] = w * o[0];
-    o[4] = T(0);
+    constexpr double c[8] = {-1.66666666666666657e-01, 8.33333333333333322e-03,
+                             -1.98412698412698413e-04, 2.75573192239858925e-06,
+                             -2.50521083854417202e-08, 1.60590438368216133e-10,
+                             -7.64716373181981641e-13, 2.81145725434552060e-15};
+    return c[k - 1];
+}
+
+template <typename T>
+PSS_INL T sin_minus_id(T d)
+{ // sin d - d
+    if (fabs(d) < T(0.5)) {
+        const T d2 = d * d;
+        T t = d * d2, s = T(0);
+#pragma unroll
+        for (int k = 1; k <= SincTerms<T>::n; ++k) {
+            s = s + T(sinc_coef(k)) * t;
+            t = t * d2;
+        }
+        return s;
+    }
+    return psin(d) - d;
+}
+
+template <typename T>
+PSS_INL T dsinc(T x, T d)
+{
+    const T x1 = x + d;
+    const T X = fabs(x), X1 = fabs(x1);
+    const bool same = (x < T(0)) == (x1 < T(0));
+    const T D = same ? (x < T(0) ? -d : d) : X1 - X;
+    if (X < T(0.5) && X1 < T(0.5)) {
+        const T u = X * X, u1 = X1 * X1, q = D * (X1 + X);
+        T h = T(1), uk = u, s = T(0);
+#pragma unroll
+        for (int k = 1; k <= SincTerms<T>::n; ++k) {
+            s = s + T(sinc_coef(k)) * h; // h = sum of u1^i u^(k-1-i)
+            h = u1 * h + uk;
+            uk = uk * u;
+        }
+        return q * s;
+    }
+    if (fabs(D) < T(0.5) * X) {
+        const T sx = psin(X), cx = pcos(X), sh = psin(T(0.5) * D);
+        const T num = T(-2) * X * sx * sh * sh + X * cx * sin_minus_id(D) + D * (X * cx - sx);
+        return num / (X * X1);
+    }
+    return sinc_(X1) - sinc_(X);
+}
+
+// phi at the nominal mean, with the parts its deviations reuse
+template <typename T>
+struct CTPhiMean {
+    T vx, vy, w, a, s1, s2, S, phi[5];
+};
+
+template <typename T>
+PSS_INL void ct_phi_mean(const CTParams<T> &P, const Marg<T, 5> &mg, CTPhiMean<T> &b)
+{
+    b.vx = mg.m[2];
+    b.vy = mg.m[3];
+    b.w = mg.m[4];
+    b.a = b.w * P.dt;
+    b.S = sinc_(T(0.5) * b.a);
+    b.s1 = P.dt * sinc_(b.a);
+    b.s2 = P.dt * (T(0.5) * b.a) * b.S * b.S;
+    b.phi[0] = b.s1 * b.vx - b.s2 * b.vy;
+    b.phi[1] = b.s2 * b.vx + b.s1 * b.vy;
+    b.phi[2] = -b.w * b.phi[1];
+    b.phi[3] = b.w * b.phi[0];
+    b.phi[4] = T(0);
+}
+
+// phi(v + dv, w + dw) - phi(v, w): with a = w dt, s1 = dt sinc(a) and
+// s2 = dt (a/2) sinc(a/2)^2, the differences of s1 and s2 come from dsinc
+// and the rest is products of the offsets.
+template <typename T>
+PSS_INL void ct_phi_dev(const CTParams<T> &P, const CTPhiMean<T> &b, T dvx, T dvy, T dw,
+                        T (&e)[5])
+{
+    const T da = dw * P.dt;
+    const T ds1 = P.dt * dsinc(b.a, da);
+    const T dS = dsinc(T(0.5) * b.a, T(0.5) * da), S1 = b.S + dS;
+    const T ds2 = P.dt * (T(0.5) * da * S1 * S1 + T(0.5) * b.a * dS * (S1 + b.S));
+    const T s1 = b.s1 + ds1, s2 = b.s2 + ds2;
+    e[0] = s1 * dvx - s2 * dvy + ds1 * b.vx - ds2 * b.vy;
+    e[1] = s2 * dvx + s1 * dvy + ds2 * b.vx + ds1 * b.vy;
+    e[2] = -(dw * (b.phi[1] + e[1]) + b.w * e[1]);
+    e[3] = dw * (b.phi[0] + e[0]) + b.w * e[0];
+    e[4] = T(0);
 }
 
 template <typename T>
 PSS_INL void ct_slr_transition(const CTParams<T> &P, const Marg<T, 5> &mg, T (&F)[5][5],
                                T (&c)[5], T (&S)[5][5])
 {
+    CTPhiMean<T> b;
+    ct_phi_mean(P, mg, b);
     T ep[5][5], em[5][5];
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
         T dlt[5], zp[5], zm[5];
         sigma_offset(mg, i, dlt);
-        ct_phi(P, mg.m[2] + dlt[2], mg.m[3] + dlt[3], mg.m[4] + dlt[4], zp);
-        ct_phi(P, mg.m[2] - dlt[2], mg.m[3] - dlt[3], mg.m[4] - dlt[4], zm);
+        ct_phi_dev(P, b, dlt[2], dlt[3], dlt[4], zp);
+        ct_phi_dev(P, b, -dlt[2], -dlt[3], -dlt[4], zm);
 #pragma unroll
         for (int a = 0; a < 5; ++a) {
             ep[a][i] = zp[a];
             em[a][i] = zm[a];
         }
     }
-    const T r0[5] = {T(0), T(0), T(0), T(0), T(0)};
-    cubature_from_dev(mg, P.LQ, ep, em, r0, F, c, S);
+    cubature_from_dev(mg, P.LQ, ep, em, b.phi, F, c, S);
 #pragma unroll
     for (int i = 0; i < 5; ++i)
         F[i][i] += T(1);

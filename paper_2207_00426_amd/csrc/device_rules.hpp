@@ -200,11 +200,12 @@ template <typename T>
 PSS_INL void ct_rule_transition(const RuleSpec<T> &R, const CTParams<T> &P, const Marg<T, 5> &mg,
                                 T (&F)[5][5], T (&c)[5], T (&S)[5][5])
 {
-    const T r0[5] = {T(0), T(0), T(0), T(0), T(0)};
+    CTPhiMean<T> b;
+    ct_phi_mean(P, mg, b);
     rule_slr<T, 5, 5, false>(
-        R, mg, r0, P.LQ,
+        R, mg, b.phi, P.LQ,
         [&](const T (&dl)[5], T (&e)[5], T &v) {
-            ct_phi(P, mg.m[2] + dl[2], mg.m[3] + dl[3], mg.m[4] + dl[4], e);
+            ct_phi_dev(P, b, dl[2], dl[3], dl[4], e);
             v = T(0);
         },
         F, c, S);

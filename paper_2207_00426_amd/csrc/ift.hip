@@ -268,10 +268,16 @@ static int launch_slr(const Ctx &c, const IftBufs<S> &w)
     const dim3 grid((unsigned)((c.T_x + tb - 1) / tb));
     const int lin = c.p->linearization;
     KTime kt(c.s, "ift_slr", "", 0);
-    if (lin == PSS_LIN_CUBATURE || lin == PSS_LIN_TAYLOR) {
-        hipLaunchKernelGGL((k_slr_ct<D>), grid, dim3(tb), 0, c.s, c.p->y_off, c.B, c.T_x, c.T_y,
-                           P, C::marg_ref2(w.nm, w.nP, c.T_x), w.yd, C::gamma_ref(&w.gam, c.T_y),
-                           lin == PSS_LIN_TAYLOR ? 1 : 0, 1);
+    // Cubature goes through the general rule kernel too (the same rule, 2 nx
+    // points of weight 1/(2 nx)): it accumulates the sigma-point moments
+    // point by point, while the dedicated kernel holds every image at once.
+    // In Dual<float, 3> that kernel reached the 512-register ceiling and its
+    // results disagreed with the same steps run on the host; the rule kernel
+    // stays well inside the limit.
+    if (lin == PSS_LIN_TAYLOR) {
+        hipLaunchKernelGGL((k_slr_ct<D, true>), grid, dim3(tb), 0, c.s, c.p->y_off, c.B, c.T_x,
+                           c.T_y, P, C::marg_ref2(w.nm, w.nP, c.T_x), w.yd,
+                           C::gamma_ref(&w.gam, c.T_y), 1, 1);
     } else {
         RuleSpec<double> Rd;
         if (!rule_spec(c.p, 5, Rd))

@@ -1331,7 +1331,9 @@ __global__ __launch_bounds__(64) void k_sequential_cov(const int64_t *y_off, int
 // ---------------------------------------------------------------------------
 // one thread per state: transition SLR from state k (slot k, k < n) and
 // measurement SLR from state k (slot k-1, k >= 1)
-template <typename T>
+// (TAYLOR_ONLY: an instance that holds the Taylor linearisation alone; the
+// runtime flag then has to be set)
+template <typename T, bool TAYLOR_ONLY = false>
 __global__ __launch_bounds__(128) void k_slr_ct(const int64_t *y_off, int B, int64_t T_x,
                                                 int64_t T_y, CTParams<T> P, MargRef<T, 5> nom,
                                                 const T *y, GammaRef<T, 5, 2> out, int taylor,
@@ -1357,7 +1359,9 @@ __global__ __launch_bounds__(128) void k_slr_ct(const int64_t *y_off, int B, int
     }
     if (k < n) {
         T G[5][5], off[5], S[5][5];
-        if (taylor)
+        if constexpr (TAYLOR_ONLY)
+            ct_taylor_transition(P, mg, G, off, S);
+        else if (taylor)
             ct_taylor_transition(P, mg, G, off, S);
         else
             ct_slr_transition(P, mg, G, off, S);
@@ -1367,7 +1371,9 @@ __global__ __launch_bounds__(128) void k_slr_ct(const int64_t *y_off, int B, int
         const int64_t t = y_off[b] + k - 1;
         T yy[2] = {y[t], y[T_y + t]};
         T G[2][5], off[2], S[2][2];
-        if (taylor)
+        if constexpr (TAYLOR_ONLY)
+            ct_taylor_bearings(P, mg, yy, G, off, S);
+        else if (taylor)
             ct_taylor_bearings(P, mg, yy, G, off, S);
         else
             ct_slr_bearings(P, mg, yy, G, off, S);

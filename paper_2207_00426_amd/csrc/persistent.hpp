@@ -284,11 +284,12 @@ struct FusedSmoothSrc {
     }
 };
 
-// A tile first builds all its elements (each thread its own chunk, written to
-// the tile-interleaved stash), then folds them back lazily: the model
-// linearisation and element construction never share registers with the
-// fold's operator, so the kernel's register peak is the larger of the two
-// phases rather than their sum.
+// A tile first builds all its elements into the tile-interleaved stash, lane
+// q on elements q, q + Tb, ... (consecutive lanes read consecutive steps of
+// the nominal, y and the stashed linearisation, whole lines per load), then
+// folds them back lazily: the model linearisation and element construction
+// never share registers with the fold's operator, so the kernel's register
+// peak is the larger of the two phases rather than their sum.
 template <class Src>
 struct Stashed {
     static constexpr bool lazy_up = true, lazy_down = true;
@@ -298,20 +299,16 @@ struct Stashed {
     PSS_INL auto dview(const TileInfo &ti, int64_t p) const { return src.dview(ti, p); }
 };
 
+// the block calls this uniformly; the barrier publishes the stash to the
+// lanes whose fold reads it
 template <class Op, class Src>
-PSS_INL void build_phase(const LevelGeom &g, const TileInfo &ti, const Src &src)
+PSS_INL void build_phase(const TileInfo &ti, const Src &src)
 {
-    const int tid = threadIdx.x;
-    if (tid < ti.nvalid) {
-        const int64_t p0 = ti.start + (int64_t)tid * g.E;
-        int64_t pe = p0 + g.E;
-        if (pe > ti.start + ti.tcnt)
-            pe = ti.start + ti.tcnt;
-        for (int64_t p = p0; p < pe; ++p) {
-            typename Op::Elem e;
-            src.up(ti, p, e); // builds and stashes
-        }
+    for (int q = threadIdx.x; q < ti.tcnt; q += blockDim.x) {
+        typename Op::Elem e;
+        src.up(ti, ti.start + q, e); // builds and stashes
     }
+    __syncthreads();
 }
 
 // ---- one tile of a phase ----------------------------------------------------// ---- one tile of a phase ----------------------------------------------------
@@ -341,7 +338,7 @@ PSS_INL void filter_tile(const PArgs<T> &a, const PGroup<T> &G, int64_t gt, T *l
     ti.E = g.E;
     const int Tb = blockDim.x;
     FusedFiltSrc<T, NX, NY, CT> build{&G, G.y_off[b] + b};
-    build_phase<Op>(g, ti, build);
+    build_phase<Op>(ti, build);
     Stashed<FusedFiltSrc<T, NX, NY, CT>> src{build};
     fold_phase<Op>(g, ti, src, lds, Tb);
     tree_up<Op>(lds, Tb, ti.nvalid);
@@ -410,7 +407,7 @@ PSS_INL void smoother_tile(const PArgs<T> &a, const PGroup<T> &G, int64_t gu, T 
     __syncthreads();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     FusedSmoothSrc<T, NX, NY, CT> build{&G, G.y_off[b]};
-    build_phase<Op>(g, ti, build);
+    build_phase<Op>(ti, build);
     Stashed<FusedSmoothSrc<T, NX, NY, CT>> src{build};
     fold_phase<Op>(g, ti, src, lds, Tb);
     tree_up<Op>(lds, Tb, ti.nvalid);

@@ -17,6 +17,19 @@ TOL = {
 }
 
 
+def kernel_input(x, dtype):
+    """x as the kernel reads it: rounded to the kernel's precision (an FP32
+    kernel receives FP32 measurements), returned in FP64 for the oracle, so
+    that both sides solve the same problem.  This matters where the inputs
+    decide an integer: a bearing whose sigma-point images straddle the
+    wrap-around cut takes its branch from y, and the FP32 rounding of y can
+    move an image across the cut."""
+    import torch
+    if dtype in ("f32", torch.float32, np.float32):
+        return np.asarray(x, dtype=np.float32).astype(np.float64)
+    return np.asarray(x, dtype=np.float64)
+
+
 def gram(N):
     return N @ np.swapaxes(N, -1, -2)
 

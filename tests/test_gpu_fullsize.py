@@ -135,6 +135,7 @@ def test_fp32_full_size_every_pass(ct_long):
     prm = orc.ct_params()
     b = pss.Batch.ct(w.y_off, w.model, dtype=torch.float32, device=DEV)
     yd = pss.to_soa(w.y, torch.float32, DEV)
+    y_in = par.kernel_input(w.y, torch.float32)
     m, Nn = b.prior_nominal()
     for i in range(w.M):
         mp, Np = pss.marg_from_soa(m.double(), Nn.double(), 5)
@@ -142,7 +143,7 @@ def test_fp32_full_size_every_pass(ct_long):
         pss.ipls_iterate(b, yd, 1, m, Nn)
         torch.cuda.synchronize()
         assert torch.isfinite(m).all() and torch.isfinite(Nn).all()
-        r = orc.ct_ipls(prm, w.model.m0, np.eye(5), w.y, 1, ms_init=mp, Ns_init=Np)
+        r = orc.ct_ipls(prm, w.model.m0, np.eye(5), y_in, 1, ms_init=mp, Ns_init=Np)
         em, eP = _per_state(*pss.marg_from_soa(m.double(), Nn.double(), 5), r["ms"], r["Ns"])
         line = ("full-size FP32 pass %d: mean err max %.3e p99 %.3e, cov err max %.3e p99 "
                 "%.3e, states above 1e-4: %d" % (i + 1, em.max(), np.percentile(em, 99), eP.max(),
@@ -166,7 +167,7 @@ def test_fp32_full_size_every_pass(ct_long):
         assert em.max() < 3e-3 and eP.max() < 3e-3
     ll, grad, _ = pss.loglik_grad(b, m, Nn, yd)
     torch.cuda.synchronize()
-    ll_ref, g_ref = orc.ct_score(prm, w.model.m0, np.eye(5), w.y,
+    ll_ref, g_ref = orc.ct_score(prm, w.model.m0, np.eye(5), y_in,
                                  *pss.marg_from_soa(m.double(), Nn.double(), 5))
     el = par.ll_err(float(ll.item()), ll_ref)
     eg = par.grad_err(grad[:, 0].cpu().numpy(), g_ref)

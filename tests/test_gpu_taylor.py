@@ -60,8 +60,8 @@ def test_iterated_extended_smoother_every_pass(tag):
         pss.ipls_iterate(b, yd, 1, m, N)
         torch.cuda.synchronize()
         ma, Na = pss.marg_from_soa(m.double(), N.double(), 5)
-        one = orc.ct_ipls(prm, w.model.m0, np.eye(5), w.y, 1, ms_init=m_prev, Ns_init=N_prev,
-                          method="taylor")
+        one = orc.ct_ipls(prm, w.model.m0, np.eye(5), par.kernel_input(w.y, tag), 1,
+                          ms_init=m_prev, Ns_init=N_prev, method="taylor")
         em, eP = par.marg_errs(ma, Na, one["ms"], one["Ns"])
         assert em < tol["m"] and eP < tol["P"], (i, em, eP)
         if tag == "f64":
