@@ -14,9 +14,10 @@ Also in the line (same run):
   fp32            the same step in FP32
   ieks_taylor     the same step with the first-order Taylor linearisation
                   (the iterated extended smoother) instead of cubature SLR
-  sequential      time per IPLS pass of the parallel scans vs the sequential
-                  square-root kernel (one thread walks the sequence) at
-                  n = 10^4 and 10^5 (prefixes of the same sequence)
+  sequential      time per IPLS pass of the parallel scans (with their
+                  algorithmic GB/s) vs the sequential square-root kernel (one
+                  thread walks the sequence) at n = 10^4 and 10^5 (prefixes of
+                  the same sequence, both precisions) and n = 10^6 (FP64)
   loglik_grad_ms  one loglik + gradient evaluation (the reverse-mode
                   adjoint) on 64 CT sequences of 10^4 steps (the parameter-
                   estimation configuration), with the checkpointed split
@@ -240,6 +241,23 @@ def counter_traffic(kernel, level, dtype, n):
     if kv is None or kv.get("src") != kernel_source_hash():
         return None
     return int(float(kv["bytes"]))
+
+
+def pass_alg_bytes(n, dtype, T_req=0, E_req=0):
+    """Algorithmic HBM bytes of one IPLS pass of one sequence of n steps
+    (the kernels of the multi-launch pass: linearisation, filter elements,
+    every filter and smoother scan kernel)."""
+    esz = 8 if dtype == "f64" else 4
+    by = scan_kernel_bytes("filter", [n], *shapes(dtype, T_req, E_req), esz)
+    by.update(scan_kernel_bytes("smoother", [n + 1], *shapes(dtype, T_req, E_req, True), esz))
+    gam = NUM["gam_trans"] + NUM["gam_obs"]
+    tot = sum(by.values())
+    if dtype == "f32":  # linearisation fused with the elements
+        tot += ((n + 1) * NUM["marg"] + n * (NUM["y"] + NUM["gam_trans"] + NUM["felem"])) * esz
+    else:
+        tot += ((n + 1) * NUM["marg"] + n * (NUM["y"] + gam)) * esz
+        tot += n * (gam + NUM["y"] + NUM["felem"]) * esz
+    return tot
 
 
 def copy_probe(stream, dev, reps=5):
@@ -779,11 +797,38 @@ def main():
                                                    pss.sequential_smoother(bb, yy, 1, mm, NN,
                                                                            ws=wsq)),
                                   1 if nn >= 10 ** 5 else 3)
+                    ab = pass_alg_bytes(nn, dt)
                     seq["n%d_%s" % (nn, dt)] = {"parallel_ms_per_pass": round(t_par, 4),
                                                 "sequential_ms_per_pass": round(t_seq, 4),
-                                                "speedup": round(t_seq / t_par, 2)}
-                    log("n=%d %s: parallel %.3f ms/pass, sequential %.3f ms/pass" % (nn, dt, t_par,
-                                                                                   t_seq))
+                                                "speedup": round(t_seq / t_par, 2),
+                                                "parallel_alg_GBps": round(ab / (t_par * 1e-3) / 1e9,
+                                                                           1)}
+                    log("n=%d %s: parallel %.3f ms/pass (%.0f GB/s algorithmic), sequential "
+                        "%.3f ms/pass" % (nn, dt, t_par, ab / (t_par * 1e-3) / 1e9, t_seq))
+            # the long sequence itself: one sequential FP64 pass (about 10 s),
+            # against the parallel pass measured in the main line
+            if n >= 10 ** 6:
+                bb = pss.Batch.ct(full.y_off, full.model, dtype=torch.float64, device=dev)
+                yy = pss.to_soa(full.y, torch.float64, dev)
+                mm, NN = bb.prior_nominal()
+                wsq, _ = bb.workspace("sequential")
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                pss.sequential_smoother(bb, yy, 1, mm, NN, ws=wsq)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                t_seq = e0.elapsed_time(e1)
+                t_par = pass_info["ms"]
+                seq["n%d_f64" % n] = {"parallel_ms_per_pass": round(t_par, 4),
+                                      "sequential_ms_per_pass": round(t_seq, 4),
+                                      "speedup": round(t_seq / t_par, 2),
+                                      "parallel_alg_GBps": round(pass_info["alg_bytes"] /
+                                                                 (t_par * 1e-3) / 1e9, 1)}
+                log("n=%d f64: parallel %.3f ms/pass (the main line's kernels), sequential "
+                    "%.3f ms/pass" % (n, t_par, t_seq))
+                del bb, yy, mm, NN, wsq
+                torch.cuda.empty_cache()
             extras["sequential"] = seq
             # parameter-estimation configuration: loglik + gradient, 64 x 10^4
             log("simulating CT 64 x 10^4")
