@@ -94,6 +94,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="main line only (profiling)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="the ragged 512-sequence batch alone (profiling its persistent pass)")
     return ap.parse_args()
 
 
@@ -223,12 +225,13 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def counter_traffic(kernel, level, dtype, n):
+def counter_traffic(kernel, level, dtype, n, summary=None):
     """HBM bytes per launch of (kernel, level) from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary of this workload, each scaled by what the
     same counter reads for a copy of known size; None when there is no
     summary for the kernels built here."""
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_ct_n%d_%s.md" % (n, dtype))
+    name = summary or "hbm_traffic_ct_n%d_%s.md" % (n, dtype)
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     rec = {}
@@ -353,7 +356,7 @@ def timed(stream, fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
-def bench_batched(stream, dev, M, B=512, seed=3):
+def bench_batched(stream, dev, M, B=512, seed=3, graph=True):
     """Ragged batch: B sequences, lengths uniform in [100, 20000], half linear
     constant-velocity, half coordinated-turn, FP32; each IPLS pass is one
     persistent launch over both groups (autotuned shape, graph-captured)."""
@@ -389,15 +392,32 @@ def bench_batched(stream, dev, M, B=512, seed=3):
 
     step()
     torch.cuda.synchronize()
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph, stream=stream):
-        step()
-    graph.replay()
-    torch.cuda.synchronize()
-    t_batched = timed(stream, graph.replay, 3)
+    if graph:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            step()
+        g.replay()
+        torch.cuda.synchronize()
+        t_batched = timed(stream, g.replay, 3)
+    else:  # eager launches (counter collection)
+        t_batched = timed(stream, step, 3)
     ok = int(status.item()) == 0
     nan = int(torch.isnan(m_ct).any().item() or torch.isnan(m_cv).any().item())
     log("batched: %.3f ms for %d step-passes (status %s)" % (t_batched, steps * M, ok))
+    # HBM: the fused minimum of a pass (every nominal and measurement read
+    # once, every nominal written once) and, from the committed rocprofv3
+    # summary of this batch, the persistent kernel's counter bytes per launch
+    esz = 4
+    n_ct, n_cv = len(wct.y), len(wcv.y)
+    nseq_ct, nseq_cv = len(wct.y_off) - 1, len(wcv.y_off) - 1
+    min_bytes = esz * (2 * NUM["marg"] * (n_ct + nseq_ct) + NUM["y"] * n_ct +
+                       2 * 14 * (n_cv + nseq_cv) + NUM["y"] * n_cv)
+    min_gbps = min_bytes * M / (t_batched * 1e-3) / 1e9
+    ctr = counter_traffic("ipls_persistent", 0, "f32", B,
+                          summary="hbm_traffic_batched_ragged512_f32.md")
+    ctr_gbps = None if ctr is None else ctr * M / (t_batched * 1e-3) / 1e9
+    log("batched: fused-minimum bytes per pass %.3g (%.0f GB/s), counter bytes per pass %s" %
+        (min_bytes, min_gbps, ctr))
     # comparators: the multi-launch path per group, and one call per sequence
     wsi_cv, _ = b_cv.workspace("ipls")
     wsi_ct, _ = b_ct.workspace("ipls")
@@ -433,6 +453,11 @@ def bench_batched(stream, dev, M, B=512, seed=3):
             "autotuned_shape": {"threads": best[0], "filter_elems": best[1],
                                 "smoother_elems": best[2]},
             "persistent_graph_ms": round(t_batched, 4),
+            "fused_min_bytes_per_pass": int(min_bytes),
+            "fused_min_GBps": round(min_gbps, 1),
+            "counter_bytes_per_pass": ctr,
+            "counter_GBps": None if ctr_gbps is None else round(ctr_gbps, 1),
+            "counter_hbm_frac": None if ctr_gbps is None else round(ctr_gbps / HBM_GBPS, 4),
             "value": round(steps * M / (t_batched * 1e-3), 1),
             "unit": "smoothed time steps/s",
             "multi_launch_ms": round(t_multi, 4),
@@ -628,6 +653,11 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
     n, M = args.n, args.passes
+    if args.batched_only:
+        with torch.cuda.stream(stream):
+            log("copy probe: %.1f GB/s" % copy_probe(stream, dev))
+            print(json.dumps(bench_batched(stream, dev, M, graph=not args.no_graph)), flush=True)
+        return
     log("simulating CT n=%d" % n)
     full = wl.ct_long(n, 2, M=M)
     extras = {}
