@@ -184,7 +184,11 @@ template <typename T, int NX, int NY, bool CT>
 struct FusedFiltSrc {
     const PGroup<T> *G;
     int64_t x0; // first state slot of the sequence
-    PSS_INL void up(const TileInfo &ti, int64_t p, FElem<T, NX> &e) const
+    PSS_INL void store(const TileInfo &ti, int64_t p, FElem<T, NX> &e) const
+    {
+        felem_ref_dev<T, NX>(G->fstash, G->T_y).store(ilv_slot(ti, p), e);
+    }
+    PSS_INL void build(const TileInfo &ti, int64_t p, FElem<T, NX> &e) const
     {
         const int64_t s = ti.off + p;
         T F[NX][NX], c[NX], SL[NX][NX], H[NY][NX], d[NY], SO[NY][NY], yy[NY];
@@ -233,7 +237,6 @@ struct FusedFiltSrc {
         } else {
             filter_element(F, c, SL, H, d, SO, yy, e);
         }
-        felem_ref_dev<T, NX>(G->fstash, G->T_y).store(ilv_slot(ti, p), e);
     }
     static constexpr bool lazy_up = false, lazy_down = true;
     static constexpr int leaf_nz = NY < NX ? NY : NX; // Z = Tria([Z_k, 0])
@@ -249,7 +252,11 @@ template <typename T, int NX, int NY, bool CT>
 struct FusedSmoothSrc {
     const PGroup<T> *G;
     int64_t ybase; // y_off[b]
-    PSS_INL void up(const TileInfo &ti, int64_t p, SElem<T, NX> &e) const
+    PSS_INL void store(const TileInfo &ti, int64_t p, SElem<T, NX> &e) const
+    {
+        selem_ref_dev<T, NX>(G->sstash, G->T_x).store(ilv_slot(ti, p), e);
+    }
+    PSS_INL void build(const TileInfo &ti, int64_t p, SElem<T, NX> &e) const
     {
         const int64_t n = ti.cnt - 1, k = n - p;
         Marg<T, NX> f;
@@ -274,7 +281,6 @@ struct FusedSmoothSrc {
             }
             smoother_element(F, c, SL, f, e);
         }
-        selem_ref_dev<T, NX>(G->sstash, G->T_x).store(ilv_slot(ti, p), e);
     }
     static constexpr bool lazy_up = false, lazy_down = true;
     static constexpr int leaf_nz = 0;
@@ -299,14 +305,33 @@ struct Stashed {
     PSS_INL auto dview(const TileInfo &ti, int64_t p) const { return src.dview(ti, p); }
 };
 
-// the block calls this uniformly; the barrier publishes the stash to the
-// lanes whose fold reads it
+// The block calls this uniformly.  Round r builds elements r Tb .. r Tb +
+// Tb - 1, lane q on element r Tb + q (consecutive lanes read consecutive
+// steps), into LDS; the lanes then take the round's elements grouped by
+// interleaved position -- element t E + j of the round goes to lane
+// j (Tb / E) + (t - t0) -- so each store writes runs of Tb / E consecutive
+// words of the stash rather than E runs of Tb / E / E (the direct order is
+// kept when E does not divide Tb).  The last barrier publishes the stash to
+// the lanes whose fold reads it and frees the LDS for the tree.
 template <class Op, class Src>
-PSS_INL void build_phase(const TileInfo &ti, const Src &src)
+PSS_INL void build_phase(const TileInfo &ti, const Src &src, typename Op::T *lds)
 {
-    for (int q = threadIdx.x; q < ti.tcnt; q += blockDim.x) {
+    const int Tb = blockDim.x, tid = threadIdx.x, E = ti.E;
+    const bool grouped = Tb % E == 0;
+    const int m = Tb / E;
+    for (int r0 = 0; r0 < ti.tcnt; r0 += Tb) {
+        __syncthreads(); // the previous round's readers are done with the LDS
         typename Op::Elem e;
-        src.up(ti, ti.start + q, e); // builds and stashes
+        if (r0 + tid < ti.tcnt) {
+            src.build(ti, ti.start + r0 + tid, e);
+            lds_put(e, lds, Tb, tid);
+        }
+        __syncthreads();
+        const int qi = grouped ? (tid % m) * E + tid / m : tid; // element of the round
+        if (r0 + qi < ti.tcnt) {
+            lds_get(e, lds, Tb, qi);
+            src.store(ti, ti.start + r0 + qi, e);
+        }
     }
     __syncthreads();
 }
@@ -338,7 +363,7 @@ PSS_INL void filter_tile(const PArgs<T> &a, const PGroup<T> &G, int64_t gt, T *l
     ti.E = g.E;
     const int Tb = blockDim.x;
     FusedFiltSrc<T, NX, NY, CT> build{&G, G.y_off[b] + b};
-    build_phase<Op>(ti, build);
+    build_phase<Op>(ti, build, lds);
     Stashed<FusedFiltSrc<T, NX, NY, CT>> src{build};
     fold_phase<Op>(g, ti, src, lds, Tb);
     tree_up<Op>(lds, Tb, ti.nvalid);
@@ -407,7 +432,7 @@ PSS_INL void smoother_tile(const PArgs<T> &a, const PGroup<T> &G, int64_t gu, T 
     __syncthreads();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     FusedSmoothSrc<T, NX, NY, CT> build{&G, G.y_off[b]};
-    build_phase<Op>(ti, build);
+    build_phase<Op>(ti, build, lds);
     Stashed<FusedSmoothSrc<T, NX, NY, CT>> src{build};
     fold_phase<Op>(g, ti, src, lds, Tb);
     tree_up<Op>(lds, Tb, ti.nvalid);
