@@ -64,6 +64,12 @@ struct Ctx {
     int B;
     int64_t T_y, T_x;
     hipStream_t s;
+    // inside the FP32 IPLS loop of the CT model: the filter and smoother run
+    // in deviation coordinates relative to the nominal means dev_m ([NX][T_x]):
+    // x~_k = x_k - r_k, so the transition offset of step k is
+    // F r_k + c - r_{k+1}, the measurement offset d + H r_{k+1}, the prior
+    // mean m0 - r_0, and the smoother adds r_k back to its output
+    const void *dev_m = nullptr;
 };
 
 // shape of one scan (filter: n_b elements per sequence, smoother: n_b + 1).

@@ -277,7 +277,7 @@ static int launch_slr(const Ctx &c, const IftBufs<S> &w)
     if (lin == PSS_LIN_TAYLOR) {
         hipLaunchKernelGGL((k_slr_ct<D, true>), grid, dim3(tb), 0, c.s, c.p->y_off, c.B, c.T_x,
                            c.T_y, P, C::marg_ref2(w.nm, w.nP, c.T_x), w.yd,
-                           C::gamma_ref(&w.gam, c.T_y), 1, 1);
+                           C::gamma_ref(&w.gam, c.T_y), 1, 1, 0);
     } else {
         RuleSpec<double> Rd;
         if (!rule_spec(c.p, 5, Rd))
@@ -296,7 +296,7 @@ static int launch_slr(const Ctx &c, const IftBufs<S> &w)
         }
         hipLaunchKernelGGL((k_slr_ct_rule<D>), grid, dim3(tb), 0, c.s, c.p->y_off, c.B, c.T_x,
                            c.T_y, P, C::marg_ref2(w.nm, w.nP, c.T_x), w.yd,
-                           C::gamma_ref(&w.gam, c.T_y), R, 1);
+                           C::gamma_ref(&w.gam, c.T_y), R, 1, 0);
     }
     return hip_check(hipGetLastError(), "ift slr launch");
 }
@@ -311,7 +311,8 @@ static int launch_felem(const Ctx &c, const IftBufs<S> &w)
     KTime kt(c.s, "ift_filter_elements", "", 0);
     hipLaunchKernelGGL((k_filter_elements<D, 5, 2, true>), dim3((unsigned)((c.T_y + tb - 1) / tb)),
                        dim3(tb), 0, c.s, c.p->y_off, c.B, c.T_y, C::gamma_ref(&w.gam, c.T_y), w.yd,
-                       w.m0d, w.N0d, w.fel, sh.T[0], sh.E[0]);
+                       w.m0d, w.N0d, w.fel, sh.T[0], sh.E[0], static_cast<const D *>(nullptr),
+                       c.T_x);
     return hip_check(hipGetLastError(), "ift filter elements launch");
 }
 

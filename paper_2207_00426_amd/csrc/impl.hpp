@@ -395,6 +395,7 @@ struct Core {
         er.Z = mptr<T>(el->Z);
         er.ld = c.T_y;
         FiltDst<T, NX> dst{marg_ref2(mf, Nf, c.T_x), c.p->y_off};
+        dst.dev_m = cptr<T>(c.dev_m);
         StartPre<T, NX> st{cptr<T>(c.p->m0), cptr<T>(c.p->N0)};
         // finest-level elements: Z = Tria([Z_k, 0]) with Z_k of ny columns
         constexpr int LZ = NY < NX ? NY : NX;
@@ -426,6 +427,7 @@ struct Core {
         auto w = carve_scan<SS>(cv, c, sh);
         T *stash = cv.template take<T>((size_t)Sizes<NX>::selem * c.T_x);
         SmoothDst<T, NX> dst{marg_ref2(ms, Ns, c.T_x)};
+        dst.dev_m = cptr<T>(c.dev_m);
         StartPre<T, NX> st{nullptr, nullptr};
         if (cov) {
             using SSC = SmootherScanCov<T, NX>;
@@ -481,11 +483,13 @@ struct Core {
         if (cov)
             hipLaunchKernelGGL((k_filter_elements<T, NX, NY, true>), grid, dim3(tb), 0, c.s,
                                c.p->y_off, c.B, c.T_y, gamma_ref(g, c.T_y), cptr<T>(y),
-                               cptr<T>(c.p->m0), cptr<T>(c.p->N0), er, ilv_T, ilv_E);
+                               cptr<T>(c.p->m0), cptr<T>(c.p->N0), er, ilv_T, ilv_E,
+                               cptr<T>(c.dev_m), c.T_x);
         else
             hipLaunchKernelGGL((k_filter_elements<T, NX, NY>), grid, dim3(tb), 0, c.s,
                                c.p->y_off, c.B, c.T_y, gamma_ref(g, c.T_y), cptr<T>(y),
-                               cptr<T>(c.p->m0), cptr<T>(c.p->N0), er, ilv_T, ilv_E);
+                               cptr<T>(c.p->m0), cptr<T>(c.p->N0), er, ilv_T, ilv_E,
+                               cptr<T>(c.dev_m), c.T_x);
         return hip_check(hipGetLastError(), "filter elements launch");
     }
 
@@ -611,6 +615,15 @@ struct Core {
         T *mfb = cv.template take<T>((size_t)Sizes<NX>::marg * c.T_x);
         void *scan_ws = cv.base + cv.used;
         const pss_gamma *g = nonlinear(c) ? &gw : gin;
+        // FP32: the CT model's passes run in deviation coordinates relative
+        // to the nominal means (see Ctx), unless the caller takes the
+        // filtering marginals (those are absolute).  On the 10^6-step track
+        // this cut the late passes' mean error about 5x; FP64 loses nothing
+        // measurable in absolute coordinates and keeps them (the offsets and
+        // the smoother's read of the nominal cost 0.04 ms per pass there).
+        Ctx cs = c;
+        if (sizeof(T) == 4 && c.p->model == PSS_MODEL_CT_BEARINGS && !mf_out)
+            cs.dev_m = m_nom;
         FElemRef<T, NX> fr = felem_ref(fel, c.T_y);
         pss_felem el{fr.A, fr.b, fr.U, fr.eta, fr.Z};
         void *mf = mf_out ? mf_out : (void *)mfb;
@@ -618,20 +631,21 @@ struct Core {
         int rc = PSS_OK;
         const bool cov = c.p->form == PSS_FORM_COV;
         for (int it = 0; it < n_iter && rc == PSS_OK; ++it) {
-            const int fused = nonlinear(c) ? slr_felem(c, m_nom, N_nom, y, &gw, &el, cov, false) : 1;
+            const int fused =
+                nonlinear(c) ? slr_felem(cs, m_nom, N_nom, y, &gw, &el, cov, false) : 1;
             if (fused < 0) {
                 rc = fused;
                 break;
             }
             if (fused) {
-                if (nonlinear(c) && (rc = slr(c, m_nom, N_nom, y, &gw)))
+                if (nonlinear(c) && (rc = slr(cs, m_nom, N_nom, y, &gw)))
                     break;
-                if ((rc = felem(c, g, y, &el, true, cov)))
+                if ((rc = felem(cs, g, y, &el, true, cov)))
                     break;
             }
-            if ((rc = fscan(c, &el, mf, Nf, scan_ws, true, cov)))
+            if ((rc = fscan(cs, &el, mf, Nf, scan_ws, true, cov)))
                 break;
-            rc = sscan(c, g, mf, Nf, m_nom, N_nom, scan_ws, cov);
+            rc = sscan(cs, g, mf, Nf, m_nom, N_nom, scan_ws, cov);
         }
         return rc;
     }
@@ -968,12 +982,14 @@ int Core<T, NX, NY>::slr_felem(const Ctx &c, const void *m, const void *N, const
                 hipLaunchKernelGGL((k_slr_felem_ct<T, true>), grid, dim3(tb), 0, c.s, c.p->y_off,
                                    c.B, c.T_y, P, marg_ref2(m, N, c.T_x), cptr<T>(y),
                                    cptr<T>(c.p->m0), cptr<T>(c.p->N0), gamma_ref(g, c.T_y),
-                                   store_obs ? 1 : 0, er, sh.T[0], sh.E[0], taylor, 1);
+                                   store_obs ? 1 : 0, er, sh.T[0], sh.E[0], taylor, 1,
+                                   c.dev_m ? 1 : 0);
             else
                 hipLaunchKernelGGL((k_slr_felem_ct<T, false>), grid, dim3(tb), 0, c.s,
                                    c.p->y_off, c.B, c.T_y, P, marg_ref2(m, N, c.T_x), cptr<T>(y),
                                    cptr<T>(c.p->m0), cptr<T>(c.p->N0), gamma_ref(g, c.T_y),
-                                   store_obs ? 1 : 0, er, sh.T[0], sh.E[0], taylor, 0);
+                                   store_obs ? 1 : 0, er, sh.T[0], sh.E[0], taylor, 0,
+                                   c.dev_m ? 1 : 0);
             return hip_check(hipGetLastError(), "slr + filter elements launch");
         }
     }
@@ -995,7 +1011,8 @@ int Core<T, NX, NY>::slr(const Ctx &c, const void *m, const void *N, const void 
                 KTime kt(c.s, "slr", "", 0);
                 hipLaunchKernelGGL((k_slr_ct<T>), grid, dim3(tb), 0, c.s, c.p->y_off, c.B, c.T_x,
                                    c.T_y, P, marg_ref2(m, N, c.T_x), cptr<T>(y),
-                                   gamma_ref(out, c.T_y), lin == PSS_LIN_TAYLOR ? 1 : 0, cov);
+                                   gamma_ref(out, c.T_y), lin == PSS_LIN_TAYLOR ? 1 : 0, cov,
+                                   c.dev_m ? 1 : 0);
             } else {
                 RuleSpec<T> R;
                 if (!rule_spec(c.p, NX, R))
@@ -1003,7 +1020,7 @@ int Core<T, NX, NY>::slr(const Ctx &c, const void *m, const void *N, const void 
                 KTime kt(c.s, "slr", "", 0);
                 hipLaunchKernelGGL((k_slr_ct_rule<T>), grid, dim3(tb), 0, c.s, c.p->y_off, c.B,
                                    c.T_x, c.T_y, P, marg_ref2(m, N, c.T_x), cptr<T>(y),
-                                   gamma_ref(out, c.T_y), R, cov);
+                                   gamma_ref(out, c.T_y), R, cov, c.dev_m ? 1 : 0);
             }
             return hip_check(hipGetLastError(), "slr launch");
         }

