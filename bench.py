@@ -16,7 +16,8 @@ Also in the line (same run):
                   (the iterated extended smoother) instead of cubature SLR
   sequential      time per IPLS pass of the parallel scans (with their
                   algorithmic GB/s) vs the sequential square-root kernel (one
-                  thread walks the sequence) at n = 10^4 and 10^5 (prefixes of
+                  wavefront walks the sequence, each step's Tria rows on its
+                  lanes) at n = 10^4 and 10^5 (prefixes of
                   the same sequence, both precisions) and n = 10^6 (FP64)
   loglik_grad_ms  one loglik + gradient evaluation (the reverse-mode
                   adjoint) on 64 CT sequences of 10^4 steps (the parameter-

@@ -378,10 +378,12 @@ int pss_loglik_grad_ift(const pss_problem *p, const void *m_nom, const void *N_n
                         void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* Sequential comparator: the same n_iter passes as pss_ipls_iterate, but
-   the filter and smoother run as the sequential recursions (one thread per
-   sequence walks k = 1..n then n-1..0); only the SLR is parallel.  The
-   square-root recursions, or with PSS_FORM_COV the standard Kalman filter
-   and RTS smoother (marginals then hold P, as in pss_ipls_iterate).  Same
+   the filter and smoother run as the sequential recursions, walking
+   k = 1..n then n-1..0; only the SLR is parallel.  The square-root
+   recursions (one wavefront per sequence, each step's Tria rows spread over
+   its lanes), or with PSS_FORM_COV the standard Kalman filter and RTS
+   smoother (one thread per sequence; marginals then hold P, as in
+   pss_ipls_iterate).  Same
    arguments and outputs as pss_ipls_iterate.
    ws: pss_workspace_size(PSS_OP_SEQUENTIAL). */
 int pss_sequential_smoother(const pss_problem *p, const pss_gamma *g, const void *y,

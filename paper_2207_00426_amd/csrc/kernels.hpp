@@ -25,6 +25,7 @@
 #include "device_cov.hpp"
 #include "device_ops.hpp"
 #include "device_rules.hpp"
+#include "device_wave.hpp"
 
 namespace pss {
 
@@ -1164,64 +1165,197 @@ __global__ __launch_bounds__(64) void k_seq_total(const int64_t *chunk_off, cons
 __global__ __launch_bounds__(256) void k_weighted_grad(const double *grad, const double *w, int B,
                                                        double *theta_bar);
 
-// sequential square-root comparator: one thread per sequence runs the
-// filter recursion forward (m^f, N^f stored) and the RTS recursion back.
+// Sequential square-root comparator, one wavefront per sequence: the filter
+// recursion forward (eqs. sqrt-filter-step1/2: predict with
+// Tria([F N, S_Lambda]), update with Psi = Tria([[H N^-, S_Omega], [N^-, 0]]);
+// m^f, N^f stored) and the RTS recursion back through the Table 4 element
+// (Phi = Tria([[F N^f, S_Lambda], [N^f, 0]]), E = Phi21 Phi11^{-1}, then
+// N^s = Tria([E N^s_{k+1}, D])).  Every Tria runs over the wave with its rows
+// on lanes (pss::wave): lane NX + r holds row r of the state (m[r] and row r
+// of N), lanes 0..NX-1 the upper rows of Phi, lanes 2NX.. the measurement
+// rows of Psi.  The steps are serial; the wave spreads each step's rows.
 template <typename T, int NX, int NY>
 __global__ __launch_bounds__(64) void k_sequential(const int64_t *y_off, int B, int64_t T_y,
                                                    GammaRef<T, NX, NY> gam, const T *y,
                                                    const T *m0, const T *N0,
                                                    MargRef<T, NX> filt, MargRef<T, NX> smooth)
 {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    static_assert(2 * NX + NY <= 64, "k_sequential: 2 nx + ny rows must fit one wave");
+    using St = wave::Contig<NX>;                 // state rows
+    using Ps = wave::Split<NY, 2 * NX, NX>;      // Psi: measurement rows, then state rows
+    using Ph = wave::Contig<0>;                  // Phi: upper rows on 0..NX-1, lower on the state lanes
+    const int b = blockIdx.x;
     if (b >= B)
         return;
+    const int lane = threadIdx.x;
+    const int r = lane - NX, oa = lane - 2 * NX;
+    const bool st = r >= 0 && r < NX, ob = oa >= 0 && oa < NY, up = lane < NX;
+    const int rs = st ? r : 0, os = ob ? oa : 0, us = up ? lane : 0; // clamped rows for loads
     const int64_t a = y_off[b], n = y_off[b + 1] - a, x0 = a + b;
-    Marg<T, NX> f;
+    const int64_t ld = gam.ld, gs = gam.stride;
+    // this lane's state row: m[r], N[r][0..r] (zeros right of the diagonal)
+    T m_r, Nr[NX];
+    auto tri = [](int i, int j) { return i * (i + 1) / 2 + (j < i ? j : i); };
+    auto store_state = [&](const MargRef<T, NX> &M, int64_t t) {
+        if (st) {
+            M.m[r * M.ld + t] = m_r;
 #pragma unroll
-    for (int i = 0; i < NX; ++i) {
-        f.m[i] = m0[i];
+            for (int j = 0; j < NX; ++j)
+                if (j <= r)
+                    M.N[tri(r, j) * M.ld + t] = Nr[j];
+        }
+    };
+    m_r = m0[rs];
 #pragma unroll
-        for (int j = 0; j <= i; ++j)
-            f.N[i][j] = N0[tri_idx(i, j)];
-    }
-    filt.store(x0, f);
+    for (int j = 0; j < NX; ++j)
+        Nr[j] = (j <= rs) ? N0[tri(rs, j)] : T(0);
+    store_state(filt, x0);
     for (int64_t k = 0; k < n; ++k) {
-        T F[NX][NX], c[NX], SL[NX][NX], H[NY][NX], d[NY], SO[NY][NY];
-        gam.load_trans(a + k, F, c, SL);
-        gam.load_obs(a + k, H, d, SO);
-        T mp[NX], FN[NX][NX], Np[NX][NX];
-        mv(F, f.m, mp);
+        const int64_t u = (a + k) * gs;
+        T mb[NX], Nb[NX][NX];
+        wave::bcast_vec<St>(m_r, mb);
+        wave::bcast_lower<St, NX>(Nr, Nb);
+        // predict on the state lanes: mp[r] = F[r] m + c[r]; row r of [F N, S_Lambda]
+        T Fr[NX], row[2 * NX];
 #pragma unroll
-        for (int i = 0; i < NX; ++i)
-            mp[i] += c[i];
-        mm_lower(F, f.N, FN);
-        tria_dense_lower(FN, SL, Np);
-        T P11[NY][NY], P21[NX][NY];
-        psi_blocks(H, Np, SO, P11, P21, f.N);
-        T Hm[NY], v[NY], u[NY], Ku[NX];
-        mv(H, mp, Hm);
+        for (int j = 0; j < NX; ++j)
+            Fr[j] = gam.F[(rs * NX + j) * ld + u];
+        T mp_r = Fr[0] * mb[0];
 #pragma unroll
-        for (int q = 0; q < NY; ++q)
-            v[q] = y[q * T_y + a + k] - Hm[q] - d[q];
-        lsolve_lower(P11, v, u);
-        mv(P21, u, Ku);
+        for (int j = 1; j < NX; ++j)
+            mp_r = pfma(Fr[j], mb[j], mp_r);
+        mp_r += gam.c[rs * ld + u];
 #pragma unroll
-        for (int i = 0; i < NX; ++i)
-            f.m[i] = mp[i] + Ku[i];
-        filt.store(x0 + k + 1, f);
+        for (int j = 0; j < NX; ++j) {
+            T s = Fr[j] * Nb[j][j];
+#pragma unroll
+            for (int t = j + 1; t < NX; ++t)
+                s = pfma(Fr[t], Nb[t][j], s);
+            row[j] = s;
+            row[NX + j] = (j <= rs) ? gam.SL[tri(rs, j) * ld + u] : T(0);
+        }
+        wave::lq_rows<NX, NX, St>(row, st ? r : -1);
+        // Psi: measurement rows [H N^-, S_Omega] on lanes 2NX.., state rows [N^-, 0]
+        T Pb[NX][NX], mpb[NX];
+        wave::bcast_lower<St, NX>(row, Pb);
+        wave::bcast_vec<St>(mp_r, mpb);
+        T Ho[NX];
+#pragma unroll
+        for (int j = 0; j < NX; ++j)
+            Ho[j] = gam.H[(os * NX + j) * ld + u];
+        T psi[NX + NY];
+#pragma unroll
+        for (int j = 0; j < NX; ++j) {
+            T s = Ho[j] * Pb[j][j];
+#pragma unroll
+            for (int t = j + 1; t < NX; ++t)
+                s = pfma(Ho[t], Pb[t][j], s);
+            psi[j] = ob ? s : ((st && j <= r) ? row[j] : T(0));
+        }
+#pragma unroll
+        for (int j = 0; j < NY; ++j)
+            psi[NX + j] = (ob && j <= oa) ? gam.SO[tri(os, j) * ld + u] : T(0);
+        wave::lq_rows<NY + NX, NX, Ps>(psi, ob ? oa : (st ? NY + r : -1));
+        // innovation v = y - H mp - d on the measurement lanes; u = Psi11^{-1} v
+        T Hm = Ho[0] * mpb[0];
+#pragma unroll
+        for (int j = 1; j < NX; ++j)
+            Hm = pfma(Ho[j], mpb[j], Hm);
+        const T v_o = y[os * T_y + a + k] - Hm - gam.d[os * ld + u];
+        T vb[NY], P11[NY][NY], ub[NY];
+        wave::bcast_vec<wave::Contig<2 * NX>>(v_o, vb);
+        wave::bcast_lower<wave::Contig<2 * NX>, NY>(psi, P11);
+        lsolve_lower(P11, vb, ub);
+        // update on the state lanes: m = mp + Psi21 u, N = Psi22
+        T Ku = psi[0] * ub[0];
+#pragma unroll
+        for (int q = 1; q < NY; ++q)
+            Ku = pfma(psi[q], ub[q], Ku);
+        m_r = mp_r + Ku;
+#pragma unroll
+        for (int j = 0; j < NX; ++j)
+            Nr[j] = (j <= rs) ? psi[NY + j] : T(0);
+        store_state(filt, x0 + k + 1);
     }
-    Marg<T, NX> s = f;
-    smooth.store(x0 + n, s);
+    store_state(smooth, x0 + n);
+    // the filtered marginals are read back by other lanes of this wave
+    __threadfence_block();
     for (int64_t k = n - 1; k >= 0; --k) {
-        T F[NX][NX], c[NX], SL[NX][NX];
-        gam.load_trans(a + k, F, c, SL);
-        Marg<T, NX> fk, o;
-        filt.load(x0 + k, fk);
-        SElem<T, NX> e;
-        smoother_element(F, c, SL, fk, e);
-        smoother_apply(e, s, o);
-        s = o;
-        smooth.store(x0 + k, s);
+        const int64_t u = (a + k) * gs, xk = x0 + k;
+        // Phi rows: upper (lanes 0..NX-1) [F N^f, S_Lambda], lower (state lanes) [N^f, 0]
+        T fm[NX], fN[NX][NX];
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+            fm[i] = filt.m[i * filt.ld + xk];
+#pragma unroll
+            for (int j = 0; j <= i; ++j)
+                fN[i][j] = filt.N[tri_idx(i, j) * filt.ld + xk];
+        }
+        T Fu[NX], ph[2 * NX];
+#pragma unroll
+        for (int j = 0; j < NX; ++j)
+            Fu[j] = gam.F[(us * NX + j) * ld + u];
+#pragma unroll
+        for (int j = 0; j < NX; ++j) {
+            T s = Fu[j] * fN[j][j];
+#pragma unroll
+            for (int t = j + 1; t < NX; ++t)
+                s = pfma(Fu[t], fN[t][j], s);
+            ph[j] = up ? s : ((st && j <= r) ? filt.N[tri(rs, j) * filt.ld + xk] : T(0));
+            ph[NX + j] = (up && j <= lane) ? gam.SL[tri(us, j) * ld + u] : T(0);
+        }
+        wave::lq_rows<2 * NX, NX, Ph>(ph, (up || st) ? lane : -1);
+        // E row r = Phi21[r] Phi11^{-1} on the state lanes
+        T P11[NX][NX], inv[NX], E[NX];
+        wave::bcast_lower<Ph, NX>(ph, P11);
+#pragma unroll
+        for (int j = 0; j < NX; ++j)
+            inv[j] = prcp(P11[j][j]);
+#pragma unroll
+        for (int j = NX - 1; j >= 0; --j) {
+            T s = ph[j];
+#pragma unroll
+            for (int t = j + 1; t < NX; ++t)
+                s = pfma(-E[t], P11[t][j], s);
+            E[j] = s * inv[j];
+        }
+        // g = m^f - E (F m^f + c): F m^f + c on the upper lanes
+        T Fm_u = Fu[0] * fm[0];
+#pragma unroll
+        for (int j = 1; j < NX; ++j)
+            Fm_u = pfma(Fu[j], fm[j], Fm_u);
+        Fm_u += gam.c[us * ld + u];
+        T Fmb[NX];
+        wave::bcast_vec<Ph>(Fm_u, Fmb);
+        T Eg = E[0] * Fmb[0];
+#pragma unroll
+        for (int j = 1; j < NX; ++j)
+            Eg = pfma(E[j], Fmb[j], Eg);
+        const T g_r = filt.m[rs * filt.ld + xk] - Eg;
+        // apply to the smoothed marginal of step k+1: m = E m^s + g,
+        // N = Tria([E N^s, D]) with D = Phi22
+        T sb[NX], sN[NX][NX], ap[2 * NX];
+        wave::bcast_vec<St>(m_r, sb);
+        wave::bcast_lower<St, NX>(Nr, sN);
+#pragma unroll
+        for (int j = 0; j < NX; ++j) {
+            T s = E[j] * sN[j][j];
+#pragma unroll
+            for (int t = j + 1; t < NX; ++t)
+                s = pfma(E[t], sN[t][j], s);
+            ap[j] = s;
+            ap[NX + j] = (j <= rs) ? ph[NX + j] : T(0);
+        }
+        wave::lq_rows<NX, NX, St>(ap, st ? r : -1);
+        T Es = E[0] * sb[0];
+#pragma unroll
+        for (int j = 1; j < NX; ++j)
+            Es = pfma(E[j], sb[j], Es);
+        m_r = Es + g_r;
+#pragma unroll
+        for (int j = 0; j < NX; ++j)
+            Nr[j] = (j <= rs) ? ap[j] : T(0);
+        store_state(smooth, xk);
     }
 }
 
