@@ -909,6 +909,11 @@ struct Core {
                                    c.p->y_off, c.B, c.T_y, gamma_ref(g, c.T_y), cptr<T>(y),
                                    cptr<T>(c.p->m0), cptr<T>(c.p->N0), marg_ref2(mf, Nf, c.T_x),
                                    marg_ref2(m_nom, N_nom, c.T_x));
+            else if constexpr (NX == 1) // scalar state: one thread per sequence
+                hipLaunchKernelGGL((k_sequential_1t<T, NX, NY>), grid, dim3(tb), 0, c.s,
+                                   c.p->y_off, c.B, c.T_y, gamma_ref(g, c.T_y), cptr<T>(y),
+                                   cptr<T>(c.p->m0), cptr<T>(c.p->N0), marg_ref2(mf, Nf, c.T_x),
+                                   marg_ref2(m_nom, N_nom, c.T_x));
             else // one wavefront per sequence
                 hipLaunchKernelGGL((k_sequential<T, NX, NY>), dim3((unsigned)c.B), dim3(64), 0, c.s,
                                    c.p->y_off, c.B, c.T_y, gamma_ref(g, c.T_y), cptr<T>(y),

@@ -1174,6 +1174,7 @@ __global__ __launch_bounds__(256) void k_weighted_grad(const double *grad, const
 // on lanes (pss::wave): lane NX + r holds row r of the state (m[r] and row r
 // of N), lanes 0..NX-1 the upper rows of Phi, lanes 2NX.. the measurement
 // rows of Psi.  The steps are serial; the wave spreads each step's rows.
+// Used for nx >= 2 (a scalar state runs k_sequential_1t below).
 template <typename T, int NX, int NY>
 __global__ __launch_bounds__(64) void k_sequential(const int64_t *y_off, int B, int64_t T_y,
                                                    GammaRef<T, NX, NY> gam, const T *y,
@@ -1356,6 +1357,68 @@ __global__ __launch_bounds__(64) void k_sequential(const int64_t *y_off, int B, 
         for (int j = 0; j < NX; ++j)
             Nr[j] = (j <= rs) ? ap[j] : T(0);
         store_state(smooth, xk);
+    }
+}
+
+// The same comparator with one thread per sequence, for a scalar state
+// (nx = 1): its Trias have one row, nothing to spread over lanes, and the
+// wave form's broadcasts only add latency there.
+template <typename T, int NX, int NY>
+__global__ __launch_bounds__(64) void k_sequential_1t(const int64_t *y_off, int B, int64_t T_y,
+                                                   GammaRef<T, NX, NY> gam, const T *y,
+                                                   const T *m0, const T *N0,
+                                                   MargRef<T, NX> filt, MargRef<T, NX> smooth)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B)
+        return;
+    const int64_t a = y_off[b], n = y_off[b + 1] - a, x0 = a + b;
+    Marg<T, NX> f;
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+        f.m[i] = m0[i];
+#pragma unroll
+        for (int j = 0; j <= i; ++j)
+            f.N[i][j] = N0[tri_idx(i, j)];
+    }
+    filt.store(x0, f);
+    for (int64_t k = 0; k < n; ++k) {
+        T F[NX][NX], c[NX], SL[NX][NX], H[NY][NX], d[NY], SO[NY][NY];
+        gam.load_trans(a + k, F, c, SL);
+        gam.load_obs(a + k, H, d, SO);
+        T mp[NX], FN[NX][NX], Np[NX][NX];
+        mv(F, f.m, mp);
+#pragma unroll
+        for (int i = 0; i < NX; ++i)
+            mp[i] += c[i];
+        mm_lower(F, f.N, FN);
+        tria_dense_lower(FN, SL, Np);
+        T P11[NY][NY], P21[NX][NY];
+        psi_blocks(H, Np, SO, P11, P21, f.N);
+        T Hm[NY], v[NY], u[NY], Ku[NX];
+        mv(H, mp, Hm);
+#pragma unroll
+        for (int q = 0; q < NY; ++q)
+            v[q] = y[q * T_y + a + k] - Hm[q] - d[q];
+        lsolve_lower(P11, v, u);
+        mv(P21, u, Ku);
+#pragma unroll
+        for (int i = 0; i < NX; ++i)
+            f.m[i] = mp[i] + Ku[i];
+        filt.store(x0 + k + 1, f);
+    }
+    Marg<T, NX> s = f;
+    smooth.store(x0 + n, s);
+    for (int64_t k = n - 1; k >= 0; --k) {
+        T F[NX][NX], c[NX], SL[NX][NX];
+        gam.load_trans(a + k, F, c, SL);
+        Marg<T, NX> fk, o;
+        filt.load(x0 + k, fk);
+        SElem<T, NX> e;
+        smoother_element(F, c, SL, fk, e);
+        smoother_apply(e, s, o);
+        s = o;
+        smooth.store(x0 + k, s);
     }
 }
 
