@@ -313,6 +313,34 @@ def test_sequential_comparator_matches_oracle(tag):
     assert em < tol["m"] and eP < tol["P"]
 
 
+@pytest.mark.parametrize("tag", ["f64", "f32"])
+@pytest.mark.parametrize("nx,ny", DIMS)
+def test_sequential_comparator_linear_every_dim(nx, ny, tag):
+    """The comparator (one wave per sequence from nx = 2, one thread for
+    nx = 1) on a ragged batch with n = 1 and n = 2 sequences, per-step Gamma:
+    filtering and smoothing marginals at every state against the oracle's
+    sequential square-root recursions."""
+    lengths = np.array([1, 2, 300, 129, 64])
+    G, m0, N0, y, y_off = _linear_case(nx, ny, lengths, 7 * nx + ny)
+    ref = _oracle_linear(G, m0, N0, y, y_off)
+    dt = _tdtype(tag)
+    b = pss.Batch(pss.MODEL_LINEAR, dt, nx, ny, y_off, m0, N0, device=DEV)
+    ms, Ns, mf, Nf = pss.sequential_smoother(b, pss.to_soa(y, dt, DEV), 1,
+                                             gamma=b.gamma_from_numpy(G), want_filter=True)
+    torch.cuda.synchronize()
+    tol = par.TOL[tag]
+    mfa, Nfa = pss.marg_from_soa(mf, Nf, nx)
+    msa, Nsa = pss.marg_from_soa(ms, Ns, nx)
+    for bi, (r, a1, a2, a3, a4) in enumerate(zip(ref, _split_states(mfa, y_off),
+                                                 _split_states(Nfa, y_off),
+                                                 _split_states(msa, y_off),
+                                                 _split_states(Nsa, y_off))):
+        em, eP = par.marg_errs(a1, a2, r["mf"], r["Nf"])
+        assert em < tol["m"] and eP < tol["P"], ("filter", bi, em, eP)
+        em, eP = par.marg_errs(a3, a4, r["ms"], r["Ns"])
+        assert em < tol["m"] and eP < tol["P"], ("smoother", bi, em, eP)
+
+
 def test_batch_equals_single_and_is_deterministic():
     """A ragged CT batch gives, per sequence, bitwise the single-sequence
     result (tiles never cross sequences); two runs are bitwise equal."""
