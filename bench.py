@@ -25,7 +25,9 @@ Also in the line (same run):
                   (forward with a checkpoint of each level, backward from it,
                   bytes kept) and the Fisher-identity route beside it, and 50
                   L-BFGS steps on theta from theta* + 0.5 on that batch (IPLS
-                  re-run at every evaluation)
+                  re-run at every evaluation); ipls_next_pass_change: how far
+                  the nominal still moves in one more pass after those
+                  passes, per sequence (whether IPLS reached a fixed point)
   kernels         every scan kernel of one filter and one smoother scan,
                   timed per launch with HIP events on its stream, with the
                   counted flops it executes
@@ -891,10 +893,26 @@ def main():
                 m0, N0 = bb.prior_nominal()
                 t_i = timed(stream, lambda: (mm.copy_(m0), NN.copy_(N0),
                                              pss.ipls_iterate(bb, yy, M, mm, NN, ws=wi)), 3)
+                # how far IPLS is from a fixed point after the M passes every
+                # objective evaluation runs: the change one more pass makes,
+                # per sequence (max over its states and components)
+                m_prev = mm.clone()
+                pss.ipls_iterate(bb, yy, 1, mm, NN, ws=wi)
+                dmax = (mm - m_prev).abs().amax(dim=0).double().cpu().numpy()
+                off = np.asarray(wb.y_off)
+                dseq = np.array([dmax[off[i] + i:off[i + 1] + i + 1].max()
+                                 for i in range(len(off) - 1)])
                 lg[dt] = {"loglik_plus_grad_ms": round(t_g, 4), "loglik_ms": round(t_l, 4),
                           "fisher_route_ms": round(t_f, 4), "ipls_ms": round(t_i, 4),
                           "checkpoints": ck, "workspace_bytes_grad": pss.workspace_size(
-                              bb, "loglik_grad")}
+                              bb, "loglik_grad"),
+                          "ipls_next_pass_change": {
+                              "max": float(dseq.max()),
+                              "sequences_above_1e-6": int((dseq > 1e-6).sum()),
+                              "sequences": int(len(dseq))}}
+                log("64x1e4 %s: one more IPLS pass after %d moves the means by up to %.3g; "
+                    "%d of %d sequences by more than 1e-6" % (dt, M, dseq.max(),
+                                                             int((dseq > 1e-6).sum()), len(dseq)))
                 log("64x1e4 %s: loglik+grad %.3f ms (loglik %.3f, Fisher route %.3f), IPLS %.3f "
                     "ms, checkpoints %s" % (dt, t_g, t_l, t_f, t_i, ck))
                 # 50 L-BFGS steps from theta* + 0.5 (IPLS re-run at every
