@@ -12,6 +12,8 @@ launch configuration bench.py times (the library's default shapes).
   round-off where bearings-only triangulation is ill-conditioned);
 * linear constant-velocity model: filter and smoother at every state
   against the oracle's sequential square-root recursions;
+* the sequential comparator (FP64) over the whole track: one pass against
+  the oracle's at every state;
 * FP32 at full size: every pass from the GPU's own FP32 nominal against one
   oracle pass from it.  Measured limit, not the FP32 bar: passes 1 and 2
   meet 1e-4 at every state; from pass 3 on (a nominal concentrated on the
@@ -181,3 +183,19 @@ def test_fp32_full_size_every_pass(ct_long):
     eg = par.grad_err(grad[:, 0].cpu().numpy(), g_ref)
     print("full-size FP32 loglik err %.3e, adjoint gradient err %.3e" % (el, eg))
     assert el < par.TOL["f32"]["ll"] and eg < par.TOL["f32"]["g"]
+
+
+def test_sequential_comparator_full_size_fp64(ct_long):
+    """The sequential comparator (one wave per sequence) over the whole
+    10^6-step track: one pass from the prior nominal against the oracle's
+    pass, every state, FP64 bar."""
+    w = ct_long
+    prm = orc.ct_params()
+    b = pss.Batch.ct(w.y_off, w.model, dtype=torch.float64, device=DEV)
+    yd = pss.to_soa(w.y, torch.float64, DEV)
+    m, Nn = pss.sequential_smoother(b, yd, 1)
+    torch.cuda.synchronize()
+    r = orc.ct_ipls(prm, w.model.m0, np.eye(5), w.y, 1)
+    em, eP = par.marg_errs(*pss.marg_from_soa(m, Nn, 5), r["ms"], r["Ns"])
+    print("full-size sequential FP64: mean err %.3e, cov err %.3e" % (em, eP))
+    assert em < par.TOL["f64"]["m"] and eP < par.TOL["f64"]["P"]
